@@ -1,0 +1,193 @@
+/*
+ * fluidsim — MI355X (gfx950) library for the differentiable MAC-grid liquid
+ * step of arXiv 2503.00868: semi-Lagrangian advection, viscosity and
+ * pressure projection by preconditioned conjugate gradients, with the exact
+ * discrete adjoint and a learned U-Net preconditioner inside flexible CG.
+ *
+ * Paper passages the operations follow (section numbers of the paper):
+ *   - momentum equation with pressure, viscosity and gravity: Section 3.2.2,
+ *     Eq. (v); operator splitting after Chorin: Section 3.2.2;
+ *   - semi-Lagrangian back-tracing of the convection term: Section 3.4.1;
+ *   - a learned convolutional solver for the pressure Poisson equation,
+ *     fitted on pressure pairs taken before and after an implicit solve:
+ *     Section 3.4.1 (PeRCNN, Fig. "percnn_str_fit");
+ *   - differentiability with respect to the simulation parameters and the
+ *     masked L2 velocity loss: Section 3.4.2, Eq. (optLoss); parameter
+ *     normalisation by an exponential activation: Section 3.4.2.
+ *
+ * GRID.  Unit box, n cells per axis, h = 1/n.  All arrays are flat, x fastest:
+ *   cell (i,j,k)            -> i + n*(j + n*k)                 n^3 entries
+ *   u face (i,j,k), i <= n  -> i + (n+1)*(j + n*k)            (n+1)n^2 entries
+ *   v face (i,j,k), j <= n  -> i + n*(j + (n+1)*k)            (n+1)n^2 entries
+ *   w face (i,j,k), k <= n  -> i + n*(j + n*k)                (n+1)n^2 entries
+ * Cell types (uint8): 0 air, 1 liquid, 2 solid; outside the box is solid.
+ * A face is a WALL if a solid cell touches it, ACTIVE if otherwise a liquid
+ * cell touches it, INACTIVE otherwise.  Every operation leaves zero on every
+ * non-active face.  Velocities are float32 in m/s (box side 1 m).
+ *
+ * MEMORY.  Pointers named d_* are DEVICE pointers owned by the caller and
+ * must stay valid for the duration of the call (and, for the workspace, for
+ * the life of the context).  Pointers named h_* are host pointers.  The
+ * library allocates no device memory: every buffer it needs lives in the
+ * caller's workspace (size from sim_workspace_size).  The sim_ctx object is
+ * host memory owned by the library and freed by sim_destroy.
+ *
+ * STREAMS.  All device work is enqueued on the stream given to sim_create.
+ * Calls return after their work is complete on that stream (they read back
+ * convergence scalars), except sim_init_state and sim_op_* which only enqueue.
+ *
+ * ERRORS.  Every entry point returns one of the SIM_* codes below and never
+ * throws.  Arguments are validated on the host before any device work, so
+ * an invalid call leaves device memory untouched.  sim_last_error returns a
+ * message for the last failure on a context.
+ */
+#ifndef FLUIDSIM_H
+#define FLUIDSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_ctx sim_ctx; /* opaque, host memory owned by the library */
+
+enum {
+    SIM_OK = 0,
+    SIM_OK_FALLBACK = 1,           /* converged, but the learned solve fell back to MIC(0) */
+    SIM_ERR_INVALID_ARG = -1,
+    SIM_ERR_WORKSPACE_TOO_SMALL = -2,
+    SIM_ERR_HIP = -3,
+    SIM_ERR_NOT_CONVERGED = -4,    /* fields hold the last iterate; stats are filled */
+    SIM_ERR_SINGULAR_MASK = -5,    /* a liquid region touches no air: pure-Neumann system */
+    SIM_ERR_STATE = -6             /* e.g. backward without a recorded rollout */
+};
+
+enum { SIM_PRECOND_JACOBI = 0, SIM_PRECOND_MIC0 = 1, SIM_PRECOND_LEARNED = 2 };
+enum { SIM_DIFFUSION_AUTO = 0, SIM_DIFFUSION_EXPLICIT = 1, SIM_DIFFUSION_IMPLICIT = 2 };
+
+/* Static configuration, fixed for the life of a context. */
+typedef struct {
+    int32_t n;                 /* cells per axis, 4 <= n <= 1024; n % 4 == 0 for LEARNED */
+    int32_t precond;           /* SIM_PRECOND_* for the pressure solve */
+    int32_t diffusion;         /* SIM_DIFFUSION_*; AUTO = explicit iff nu*dt*n^2 <= 1/12 */
+    int32_t max_iter;          /* per solve, >= 1 */
+    int32_t check_every;       /* FP64 true-residual check period m, 1..1024 */
+    int32_t checkpoint_every;  /* K: rollout checkpoint spacing for sim_backward, >= 1 */
+    int32_t max_steps;         /* longest recordable rollout (0 = no recording) */
+    int32_t learned_max_iter;  /* flexible-CG iterations before the MIC(0) restart */
+    double tol;                /* relative L2 true residual of the pressure solve, (0, 1) */
+    double diff_tol;           /* same for the implicit viscosity solve, (0, 1) */
+} sim_desc;
+
+/* Dynamic parameters (sim_set_params).  Density is 1: the solver works with
+ * the scaled pressure p*dt/rho, which does not depend on rho. */
+typedef struct {
+    double nu;                 /* kinematic viscosity, > 0 */
+    double s;                  /* initial-velocity scale used by sim_init_state, > 0 */
+    double dt;                 /* time step, > 0 */
+    double gravity[3];         /* body acceleration, m/s^2, e.g. {0, -9.8, 0} */
+} sim_params;
+
+/* Per-solve statistics (host struct filled by the library). */
+typedef struct {
+    int32_t status;            /* SIM_* code of this step or solve */
+    int32_t iters;             /* pressure (F)CG iterations, including any fallback */
+    int32_t diff_iters;        /* implicit viscosity CG iterations (0 if explicit) */
+    int32_t fallback_used;     /* 1 if the learned solve restarted with MIC(0) */
+    double rel_residual;       /* final FP64 true relative residual of the pressure */
+    double diff_rel_residual;  /* same for the viscosity solve */
+} sim_stats;
+
+/* Bytes of device workspace a context with this description needs.
+ * Host only.  Returns SIM_ERR_INVALID_ARG on a bad description. */
+int sim_workspace_size(const sim_desc* desc, size_t* bytes);
+
+/* Validate desc and the cell types (host copy h_cell_type, n^3 bytes, values
+ * 0/1/2; every connected liquid region must share a face with an air cell,
+ * else SIM_ERR_SINGULAR_MASK), carve the workspace (d_workspace, >= the
+ * size above, 256-byte aligned), upload the mask and build the per-mask
+ * tables (face codes, Poisson diagonal, MIC(0) factor).  hip_stream is a
+ * hipStream_t (NULL = default stream). */
+int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspace,
+               size_t workspace_bytes, void* hip_stream, sim_ctx** out);
+
+/* Set nu, s, dt and gravity; host only, checks ranges.  Required before
+ * sim_step / sim_init_state / sim_backward. */
+int sim_set_params(sim_ctx* ctx, const sim_params* params);
+
+/* u0 = s * ugen on active faces, 0 elsewhere (the fitted initial velocity
+ * scale of the rollout).  Enqueue only. */
+int sim_init_state(sim_ctx* ctx, const float* d_ugen_u, const float* d_ugen_v,
+                   const float* d_ugen_w, float* d_u, float* d_v, float* d_w);
+
+/* Advance (d_u, d_v, d_w) in place by nsteps steps, each: advection (+ gravity),
+ * viscosity (explicit or implicit), pressure projection.  With record != 0
+ * the entry state is recorded as the start of a rollout (checkpoints every
+ * checkpoint_every steps) so sim_backward can differentiate it; nsteps must
+ * then be <= max_steps.  h_stats (nullable) receives nsteps entries. */
+int sim_step(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, int32_t nsteps, int32_t record,
+             sim_stats* h_stats);
+
+/* Pressure projection alone, in place.  d_p_out (nullable) receives the
+ * scaled pressure p*dt/rho per cell as float64 (zero off liquid). */
+int sim_project(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, double* d_p_out,
+                sim_stats* h_stats);
+
+/* Reverse-mode gradient of the last recorded rollout.  In: dJ/du_T
+ * (d_gu, d_gv, d_gw).  Out: (d_gu0, d_gv0, d_gw0) = dJ/du0 on active faces, or
+ * dJ/dugen = s * dJ/du0 when d_ugen_* are given (the same ugen that
+ * sim_init_state used).  h_grad[0] = dJ/dnu; h_grad[1] = dJ/ds (0 when ugen
+ * is NULL).  h_stats (nullable) receives one entry with the summed iterations. */
+int sim_backward(sim_ctx* ctx, const float* d_gu, const float* d_gv, const float* d_gw,
+                 const float* d_ugen_u, const float* d_ugen_v, const float* d_ugen_w,
+                 float* d_gu0, float* d_gv0, float* d_gw0, double* h_grad, sim_stats* h_stats);
+
+/* MSE over active faces between (u,v,w) and a target (the L2 term of
+ * Eq. (optLoss)): h_loss receives J; (d_gu, d_gv, d_gw) (nullable) receive
+ * dJ/du. */
+int sim_loss_mse(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                 const float* d_tu, const float* d_tv, const float* d_tw, double* h_loss,
+                 float* d_gu, float* d_gv, float* d_gw);
+
+/* ---- learned preconditioner (Section 3.4.1 analogue) ---------------------
+ * A 3-level 3-D U-Net (16/32/64 channels, 3x3x3 bias-free convolutions,
+ * ReLU, 2x average pooling, nearest upsampling with skip concatenation, one
+ * 16->1 output convolution) maps (r / rms(r), liquid mask) to a correction;
+ * z = mask * rms(r) * out.  Weights are one float32 blob in the order and
+ * shapes sim_net_param_count documents; the library keeps bf16 copies. */
+int sim_net_param_count(int64_t* count);
+int sim_net_set_weights(sim_ctx* ctx, const float* d_weights, int64_t count);
+int sim_net_forward(sim_ctx* ctx, const float* d_r, float* d_z);
+
+/* One Adam step of the U-Net on a batch of (r, e) pairs, e = A^-1 r (cell
+ * arrays, batch-major): loss 1 - (r.z)^2 / ((r.e)(z.Az)) averaged over the
+ * batch (A-norm angle between the correction z = net(r) and the true error).
+ * d_master: float32 weights (updated), d_adam: 2*count float32 moments,
+ * step: 1-based Adam step.  h_loss receives the batch loss before the update. */
+int sim_net_train_step(sim_ctx* ctx, const float* d_r, const float* d_e, int32_t batch,
+                       float* d_master, float* d_adam, int32_t step, float lr, double* h_loss);
+
+/* ---- single operators, for parity tests and custom drivers (enqueue only) --
+ * Each acts on the context's mask; outputs get zero on non-active faces /
+ * non-liquid cells.  b is the Poisson right-hand side -h * (net outflow). */
+int sim_op_advect(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                  float* d_au, float* d_av, float* d_aw);
+int sim_op_diffuse(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                   float* d_ou, float* d_ov, float* d_ow, sim_stats* h_stats);
+int sim_op_divergence(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                      float* d_b);
+int sim_op_poisson_apply(sim_ctx* ctx, const float* d_x, float* d_y);
+int sim_op_precond_apply(sim_ctx* ctx, int32_t precond, const float* d_r, float* d_z);
+int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                          const float* d_lu, const float* d_lv, const float* d_lw, float* d_gu,
+                          float* d_gv, float* d_gw);
+
+int sim_destroy(sim_ctx* ctx);
+const char* sim_last_error(const sim_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,62 @@
+"""torch.autograd.Function over a recorded rollout of the HIP step.
+
+Forward: u0 = s * mask(ugen), then `steps` steps recorded by the library.
+Backward: the library's checkpointed exact discrete adjoint.  The fitted
+parameters enter through the exponential normalisation of Section 3.4.2:
+nu = exp(theta_nu), s = exp(theta_s), so dJ/dtheta = param * dJ/dparam.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+
+class FluidRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta_nu, theta_s, ugen_u, ugen_v, ugen_w, sim, steps, dt, gravity):
+        nu = math.exp(float(theta_nu))
+        s = math.exp(float(theta_s))
+        sim.set_params(nu=nu, dt=dt, s=s, gravity=gravity)
+        ugen = tuple(t.contiguous() for t in (ugen_u, ugen_v, ugen_w))
+        u = sim.faces()
+        sim.init_state(ugen, u)
+        ctx.stats = sim.step(u, steps, record=True)
+        ctx.sim, ctx.nu, ctx.s = sim, nu, s
+        ctx.save_for_backward(theta_nu, theta_s, *ugen)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu, gv, gw):
+        theta_nu, theta_s, ug_u, ug_v, ug_w = ctx.saved_tensors
+        sim = ctx.sim
+        g = tuple(torch.zeros_like(ref) if t is None else t.contiguous()
+                  for t, ref in zip((gu, gv, gw), (ug_u, ug_v, ug_w)))
+        out, dnu, ds, _ = sim.backward(g, ugen=(ug_u, ug_v, ug_w))
+        return (theta_nu.new_tensor(ctx.nu * dnu), theta_s.new_tensor(ctx.s * ds), out[0], out[1],
+                out[2], None, None, None, None)
+
+
+def rollout(theta_nu, theta_s, ugen, sim, steps, dt, gravity=(0.0, -9.8, 0.0)):
+    """u_T of a recorded rollout; differentiable in theta_nu, theta_s, ugen."""
+    return FluidRollout.apply(theta_nu, theta_s, ugen[0], ugen[1], ugen[2], sim, steps, dt,
+                              tuple(gravity))
+
+
+def mse_loss(sim, u, target):
+    """Mean squared error over active faces (L2 term of Eq. (optLoss)),
+    computed by the library; differentiable in u."""
+    return _MSE.apply(sim, u[0], u[1], u[2], target[0], target[1], target[2])
+
+
+class _MSE(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim, u0, u1, u2, t0, t1, t2):
+        J, g = sim.loss_mse((u0, u1, u2), (t0, t1, t2), want_grad=True)
+        ctx.g = g
+        return u0.new_tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        s = gJ.to(torch.float32)
+        return (None, ctx.g[0] * s, ctx.g[1] * s, ctx.g[2] * s, None, None, None)

@@ -1,0 +1,137 @@
+// Device-side helpers shared by the fluidsim kernels: grid layout, the
+// XCD-aware block order, wave64/LDS reductions in FP64 and the last-block
+// finish that keeps CG scalars on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs {
+
+constexpr int kBlock = 256;  // threads per block for streaming/stencil kernels
+constexpr int kWave = 64;
+
+enum : uint8_t { AIR = 0, LIQUID = 1, SOLID = 2 };
+
+// Face code bits (one byte per face, built once per mask):
+//   bit a (0..5) -> the neighbour along -x,+x,-y,+y,-z,+z enters the viscous
+//                   Laplacian (an active face, or a wall along the face's own
+//                   axis, whose stored value is always zero);
+//   bit 6        -> the face itself is active.
+enum : uint8_t { FC_ACTIVE = 1u << 6 };
+
+struct Dims {
+  int nx, ny, nz;
+};
+
+__host__ __device__ inline Dims face_dims(int n, int comp) {
+  return Dims{n + (comp == 0), n + (comp == 1), n + (comp == 2)};
+}
+
+__host__ __device__ inline int64_t face_count(int n) { return (int64_t)(n + 1) * n * n; }
+
+__host__ __device__ inline int64_t cells(int n) { return (int64_t)n * n * n; }
+
+// Walks a flat index of a 3-D array (x fastest) in fixed strides without a
+// division per step.
+struct Walker {
+  int i, j, k;
+  int ai, aj, ak;  // the stride decomposed along x, y, z
+  Dims d;
+  __device__ inline void init(Dims dd, int64_t start, int64_t stride) {
+    d = dd;
+    int64_t row = start / d.nx;
+    i = (int)(start - row * d.nx);
+    j = (int)(row % d.ny);
+    k = (int)(row / d.ny);
+    int64_t srow = stride / d.nx;
+    ai = (int)(stride - srow * d.nx);
+    aj = (int)(srow % d.ny);
+    ak = (int)(srow / d.ny);
+  }
+  __device__ inline void next() {
+    i += ai;
+    int c = i >= d.nx;
+    i -= c ? d.nx : 0;
+    j += aj + c;
+    c = j >= d.ny;
+    j -= c ? d.ny : 0;
+    k += ak + c;
+  }
+};
+
+// Blocks are dispatched to the 8 XCDs round-robin by block id, and each XCD
+// has its own L2.  Renumber so every XCD gets one contiguous run of logical
+// blocks: stencil neighbours (the next row, the next plane) then sit in the
+// same L2 as the block that needs them.
+__device__ inline int xcd_logical_block(int b, int nblocks) {
+  const int nx = 8;
+  int q = nblocks / nx, r = nblocks % nx;
+  int x = b % nx;
+  int prefix = x * q + (x < r ? x : r);
+  return prefix + b / nx;
+}
+
+// Sum over a block of kBlock threads; result valid in thread 0.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV]) {
+  __shared__ double lds[NV][kBlock / kWave];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int off = kWave / 2; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, kWave);
+  int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[q][wid] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kBlock / kWave; ++w) s += lds[q][w];
+      v[q] = s;
+    }
+  }
+}
+
+// Each block stores its NV partial sums; the last block to finish adds all
+// partials in block order (deterministic for a given grid) and returns true
+// with the totals in `tot` (valid in every thread of that block).  The
+// counter is reset for the next launch.
+template <int NV>
+__device__ inline bool finish_sums(double (&v)[NV], double* partials, unsigned* counter,
+                                   int nblocks, int block_id, double (&tot)[NV]) {
+  __shared__ bool is_last;
+  __shared__ double res[NV];
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) partials[(int64_t)block_id * NV + q] = v[q];
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    is_last = (prev == (unsigned)nblocks - 1u);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] += __builtin_nontemporal_load(&partials[(int64_t)b * NV + q]);
+  }
+  block_sum<NV>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) res[q] = acc[q];
+    *counter = 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) tot[q] = res[q];
+  return true;
+}
+
+}  // namespace fs

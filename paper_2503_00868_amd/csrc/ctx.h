@@ -1,0 +1,159 @@
+// Host-side context of the fluidsim library and the launchers the runtime
+// calls.  Every launcher only enqueues work on ctx->stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fluidsim.h"
+
+namespace fs {
+
+// Device scalar slots (double) and flag slots (int) used by the solvers.
+enum ScalarSlot {
+  S_BB = 0,    // |b|^2
+  S_RZ,        // r.z of the current iterate
+  S_RZ_PREV,   // r.z of the previous iterate
+  S_DQ,        // d.Ad
+  S_BETA,      // direction update coefficient
+  S_RR,        // true residual |b - Ax|^2 at the last check
+  S_ZQ,        // z.q (flexible CG)
+  S_DR,        // d.r (flexible CG)
+  S_DOT0,      // general-purpose reduction results
+  S_DOT1,
+  S_DOT2,
+  S_COUNT = 32
+};
+enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };
+
+struct F3 {
+  float* c[3];
+};
+struct CF3 {
+  const float* c[3];
+};
+
+// Kinds of preconditioner application inside the Poisson CG.
+enum PrecKind { PK_JACOBI = 0, PK_ZARRAY = 1 };
+
+}  // namespace fs
+
+struct UNetState;
+
+struct sim_ctx {
+  sim_desc desc;
+  sim_params params;
+  int params_set = 0;
+  int n = 0;
+  hipStream_t stream = nullptr;
+  int64_t C = 0;  // cells
+  int64_t F = 0;  // faces per component
+  int64_t n_active = 0;
+  int64_t n_liquid = 0;
+
+  // per-mask tables
+  uint8_t* cell = nullptr;   // C
+  uint8_t* cdiag = nullptr;  // C: Poisson diagonal (0 off liquid)
+  uint8_t* fcode = nullptr;  // 3F: face codes, stacked u|v|w
+
+  // Poisson solver vectors (cells)
+  double* x = nullptr;
+  float* r = nullptr;
+  float* z = nullptr;
+  float* dA = nullptr;
+  float* dB = nullptr;
+  float* q = nullptr;
+  float* b = nullptr;
+  float* rprev = nullptr;   // flexible CG
+  float* precon = nullptr;  // MIC(0) factor
+  float* mq = nullptr;      // MIC(0) forward-sweep result
+
+  // face-domain buffers, each 3F stacked
+  float* tmp = nullptr;  // advection output / diffusion right-hand side
+  double* fx = nullptr;  // FP64 iterate of the viscosity solve
+  float* fr = nullptr;
+  float* fdA = nullptr;
+  float* fdB = nullptr;
+  float* fq = nullptr;
+  float* lam = nullptr;   // adjoint state
+  float* lam2 = nullptr;  // adjoint scratch
+
+  // reductions
+  double* partials = nullptr;
+  double* scal = nullptr;
+  unsigned* counter = nullptr;
+  int* flags = nullptr;
+
+  // rollout recording
+  float* ckpt = nullptr;  // (ckpt_slots) x 3F
+  int ckpt_slots = 0;
+  float* seg = nullptr;  // (2 * checkpoint_every) x 3F: state and diffusion operand per step
+  int rec_steps = 0;
+  int recorded = 0;
+
+  // learned preconditioner
+  UNetState* net = nullptr;
+  void* net_ws = nullptr;
+  size_t net_ws_bytes = 0;
+
+  // launch shapes
+  int grid_cells = 0;  // blocks for cell-domain kernels
+  int grid_faces = 0;  // blocks per component for face-domain kernels
+
+  // host readback
+  double* h_scal = nullptr;  // pinned: S_COUNT doubles + F_COUNT ints
+  std::string err;
+};
+
+namespace fs {
+
+// ---- launchers (k_*.hip) ----
+void launch_setup_tables(sim_ctx* c);
+void launch_mic0_setup(sim_ctx* c);
+void launch_mic0_apply(sim_ctx* c, const float* r, float* z, const int* flags);
+
+void launch_advect(sim_ctx* c, CF3 in, F3 out, float dth, const float force[3]);
+void launch_diffuse_explicit(sim_ctx* c, CF3 in, F3 out, float alpha);
+void launch_divergence(sim_ctx* c, CF3 in, float* b);
+void launch_pressure_update(sim_ctx* c, const double* x, F3 u);
+void launch_mask_scale(sim_ctx* c, CF3 in, F3 out, float s);
+void launch_copy_faces(sim_ctx* c, CF3 in, F3 out);
+
+// Poisson CG pieces
+void launch_pcg_init(sim_ctx* c, int prec);
+void launch_pcg_dir_spmv(sim_ctx* c, int prec, const float* d_in, float* d_out);
+void launch_pcg_update(sim_ctx* c, int prec, const float* d);
+void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
+void launch_pcg_rz_first(sim_ctx* c, int first);
+void launch_pcg_check(sim_ctx* c, int prec, double tol);
+void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
+void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
+void launch_x_to_double(sim_ctx* c, const double* x, double* out);
+
+// flexible CG pieces (learned preconditioner)
+void launch_fcg_init(sim_ctx* c);
+void launch_fcg_dir_spmv(sim_ctx* c, const float* d_in, float* d_out);
+void launch_fcg_update(sim_ctx* c, const float* d);
+void launch_fcg_beta(sim_ctx* c);
+void launch_fcg_beta_first(sim_ctx* c, int first);
+void launch_fcg_check(sim_ctx* c, double tol);
+
+// implicit viscosity CG pieces (face domain, FP64 iterate ctx->fx, rhs ctx->tmp)
+void launch_dcg_init(sim_ctx* c, float alpha);
+void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_out);
+void launch_dcg_update(sim_ctx* c, float alpha, const float* d);
+void launch_dcg_check(sim_ctx* c, float alpha, double tol);
+void launch_dcg_finish(sim_ctx* c, F3 out);
+
+// adjoint and loss
+void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth);
+void launch_zero_faces(sim_ctx* c, F3 out);
+// scal[slot] = (accumulate ? scal[slot] : 0) + scale * <a, L y>
+void launch_dot_lap(sim_ctx* c, CF3 a, CF3 y, int slot, double scale, int accumulate);
+void launch_dot_faces(sim_ctx* c, CF3 a, CF3 b, int slot, int masked);
+void launch_loss_mse(sim_ctx* c, CF3 u, CF3 t, F3 g, int slot);
+void launch_axpy_faces(sim_ctx* c, CF3 a, F3 y, float alpha);
+
+}  // namespace fs

@@ -1,0 +1,303 @@
+"""ctypes binding of ``libfluidsim.so`` (the C ABI in ``include/fluidsim.h``).
+
+Argument marshalling only: every operation runs in the library's HIP
+kernels.  PyTorch provides device memory (the caller-owned workspace and
+fields) and the stream.  If the library is missing this module raises; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfluidsim.so")
+
+SIM_OK = 0
+SIM_OK_FALLBACK = 1
+SIM_ERR_INVALID_ARG = -1
+SIM_ERR_WORKSPACE_TOO_SMALL = -2
+SIM_ERR_HIP = -3
+SIM_ERR_NOT_CONVERGED = -4
+SIM_ERR_SINGULAR_MASK = -5
+SIM_ERR_STATE = -6
+
+SIM_PRECOND_JACOBI, SIM_PRECOND_MIC0, SIM_PRECOND_LEARNED = 0, 1, 2
+SIM_DIFFUSION_AUTO, SIM_DIFFUSION_EXPLICIT, SIM_DIFFUSION_IMPLICIT = 0, 1, 2
+
+PRECONDS = {"jacobi": SIM_PRECOND_JACOBI, "mic0": SIM_PRECOND_MIC0, "learned": SIM_PRECOND_LEARNED}
+DIFFUSIONS = {"auto": SIM_DIFFUSION_AUTO, "explicit": SIM_DIFFUSION_EXPLICIT,
+              "implicit": SIM_DIFFUSION_IMPLICIT}
+
+
+class sim_desc(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("precond", c_int32), ("diffusion", c_int32),
+                ("max_iter", c_int32), ("check_every", c_int32), ("checkpoint_every", c_int32),
+                ("max_steps", c_int32), ("learned_max_iter", c_int32), ("tol", c_double),
+                ("diff_tol", c_double)]
+
+
+class sim_params(ctypes.Structure):
+    _fields_ = [("nu", c_double), ("s", c_double), ("dt", c_double), ("gravity", c_double * 3)]
+
+
+class sim_stats(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("iters", c_int32), ("diff_iters", c_int32),
+                ("fallback_used", c_int32), ("rel_residual", c_double),
+                ("diff_rel_residual", c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FluidSimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fluidsim error {code}: {msg}")
+        self.code = code
+
+
+# every entry point declared in include/fluidsim.h: name -> (restype, argtypes)
+_P = c_void_p
+SIGNATURES = {
+    "sim_workspace_size": (c_int32, [POINTER(sim_desc), POINTER(c_size_t)]),
+    "sim_create": (c_int32, [POINTER(sim_desc), _P, _P, c_size_t, _P, POINTER(_P)]),
+    "sim_set_params": (c_int32, [_P, POINTER(sim_params)]),
+    "sim_init_state": (c_int32, [_P, _P, _P, _P, _P, _P, _P]),
+    "sim_step": (c_int32, [_P, _P, _P, _P, c_int32, c_int32, POINTER(sim_stats)]),
+    "sim_project": (c_int32, [_P, _P, _P, _P, _P, POINTER(sim_stats)]),
+    "sim_backward": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, POINTER(c_double),
+                               POINTER(sim_stats)]),
+    "sim_loss_mse": (c_int32, [_P, _P, _P, _P, _P, _P, _P, POINTER(c_double), _P, _P, _P]),
+    "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
+    "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
+    "sim_net_forward": (c_int32, [_P, _P, _P]),
+    "sim_net_train_step": (c_int32, [_P, _P, _P, c_int32, _P, _P, c_int32, c_float,
+                                     POINTER(c_double)]),
+    "sim_op_advect": (c_int32, [_P, _P, _P, _P, _P, _P, _P]),
+    "sim_op_diffuse": (c_int32, [_P, _P, _P, _P, _P, _P, _P, POINTER(sim_stats)]),
+    "sim_op_divergence": (c_int32, [_P, _P, _P, _P, _P]),
+    "sim_op_poisson_apply": (c_int32, [_P, _P, _P]),
+    "sim_op_precond_apply": (c_int32, [_P, c_int32, _P, _P]),
+    "sim_op_advect_adjoint": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_destroy": (c_int32, [_P]),
+    "sim_last_error": (ctypes.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfluidsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FluidSimError(SIM_ERR_STATE, f"{LIB_PATH} is not built; run "
+                                "`python -m paper_2503_00868_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return c_void_p(t.data_ptr())
+
+
+def last_error(ctx):
+    msg = lib().sim_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def check(rc, ctx=None, allow=(SIM_OK, SIM_OK_FALLBACK)):
+    if rc not in allow:
+        raise FluidSimError(rc, last_error(ctx) if ctx else "")
+    return rc
+
+
+# ------------------------------------------------------------------ raw ABI
+
+def sim_workspace_size(desc: sim_desc) -> int:
+    out = c_size_t(0)
+    check(lib().sim_workspace_size(byref(desc), byref(out)))
+    return out.value
+
+
+def sim_create(desc: sim_desc, cell_host: np.ndarray, workspace, stream_handle: int):
+    cell = np.ascontiguousarray(cell_host, dtype=np.uint8)
+    ctx = c_void_p()
+    rc = lib().sim_create(byref(desc), cell.ctypes.data_as(c_void_p), _ptr(workspace),
+                          workspace.numel() * workspace.element_size(), c_void_p(stream_handle),
+                          byref(ctx))
+    check(rc)
+    return ctx
+
+
+def make_desc(n, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6, max_iter=20000,
+              check_every=8, checkpoint_every=8, max_steps=0, learned_max_iter=200):
+    return sim_desc(n=n, precond=PRECONDS[precond] if isinstance(precond, str) else precond,
+                    diffusion=DIFFUSIONS[diffusion] if isinstance(diffusion, str) else diffusion,
+                    max_iter=max_iter, check_every=check_every, checkpoint_every=checkpoint_every,
+                    max_steps=max_steps, learned_max_iter=learned_max_iter, tol=tol,
+                    diff_tol=diff_tol)
+
+
+def face_shapes(n):
+    return [(n, n, n + 1), (n, n + 1, n), (n + 1, n, n)]
+
+
+class Sim:
+    """One context: owns the device workspace (a torch uint8 tensor) and
+    forwards every call to the C ABI on torch's current stream."""
+
+    def __init__(self, cell, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6,
+                 max_iter=20000, check_every=8, checkpoint_every=8, max_steps=0,
+                 learned_max_iter=200, device="cuda"):
+        import torch
+        self.torch = torch
+        cell = np.ascontiguousarray(cell, dtype=np.uint8)
+        self.n = n = cell.shape[0]
+        self.device = torch.device(device)
+        self.desc = make_desc(n, precond, diffusion, tol, diff_tol, max_iter, check_every,
+                              checkpoint_every, max_steps, learned_max_iter)
+        size = sim_workspace_size(self.desc)
+        self.ws = torch.empty(size, dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = sim_create(self.desc, cell, self.ws, self.stream.cuda_stream)
+        self.cell = cell
+        self.params = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().sim_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def faces(self, fill=0.0):
+        t = self.torch
+        return tuple(t.full(s, fill, dtype=t.float32, device=self.device)
+                     for s in face_shapes(self.n))
+
+    def to_faces(self, arrays):
+        t = self.torch
+        return tuple(t.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+                     for a in arrays)
+
+    def cells_tensor(self, arr=None, dtype=None):
+        t = self.torch
+        dtype = dtype or t.float32
+        if arr is None:
+            return t.zeros((self.n,) * 3, dtype=dtype, device=self.device)
+        return t.as_tensor(np.ascontiguousarray(arr), device=self.device).to(dtype)
+
+    def _chk(self, rc, allow=(SIM_OK, SIM_OK_FALLBACK)):
+        return check(rc, self.ctx, allow)
+
+    # -- ABI
+    def set_params(self, nu, dt, s=1.0, gravity=(0.0, -9.8, 0.0)):
+        p = sim_params(nu=nu, s=s, dt=dt, gravity=(c_double * 3)(*gravity))
+        self._chk(lib().sim_set_params(self.ctx, byref(p)))
+        self.params = dict(nu=nu, dt=dt, s=s, gravity=tuple(gravity))
+
+    def init_state(self, ugen, out):
+        self._chk(lib().sim_init_state(self.ctx, *map(_ptr, ugen), *map(_ptr, out)))
+        return out
+
+    def step(self, u, nsteps=1, record=False, allow=(SIM_OK, SIM_OK_FALLBACK)):
+        st = (sim_stats * max(nsteps, 1))()
+        rc = lib().sim_step(self.ctx, *map(_ptr, u), nsteps, int(record), st)
+        self._chk(rc, allow)
+        return [st[q].as_dict() for q in range(nsteps)]
+
+    def project(self, u, want_p=False, allow=(SIM_OK, SIM_OK_FALLBACK)):
+        t = self.torch
+        p = t.zeros((self.n,) * 3, dtype=t.float64, device=self.device) if want_p else None
+        st = sim_stats()
+        rc = lib().sim_project(self.ctx, *map(_ptr, u), _ptr(p), byref(st))
+        self._chk(rc, allow)
+        return st.as_dict(), p
+
+    def backward(self, g, ugen=None, out=None):
+        out = out if out is not None else self.faces()
+        grad = (c_double * 2)()
+        st = sim_stats()
+        ug = ugen if ugen is not None else (None, None, None)
+        rc = lib().sim_backward(self.ctx, *map(_ptr, g), *map(_ptr, ug), *map(_ptr, out), grad,
+                                byref(st))
+        self._chk(rc)
+        return out, grad[0], grad[1], st.as_dict()
+
+    def loss_mse(self, u, target, want_grad=True):
+        g = self.faces() if want_grad else (None, None, None)
+        J = c_double()
+        self._chk(lib().sim_loss_mse(self.ctx, *map(_ptr, u), *map(_ptr, target), byref(J),
+                                     *map(_ptr, g)))
+        return J.value, (g if want_grad else None)
+
+    def op_advect(self, u, out=None):
+        out = out if out is not None else self.faces()
+        self._chk(lib().sim_op_advect(self.ctx, *map(_ptr, u), *map(_ptr, out)))
+        return out
+
+    def op_diffuse(self, u, out=None):
+        out = out if out is not None else self.faces()
+        st = sim_stats()
+        self._chk(lib().sim_op_diffuse(self.ctx, *map(_ptr, u), *map(_ptr, out), byref(st)))
+        return out, st.as_dict()
+
+    def op_divergence(self, u, b=None):
+        b = b if b is not None else self.cells_tensor()
+        self._chk(lib().sim_op_divergence(self.ctx, *map(_ptr, u), _ptr(b)))
+        return b
+
+    def op_poisson_apply(self, x, y=None):
+        y = y if y is not None else self.cells_tensor()
+        self._chk(lib().sim_op_poisson_apply(self.ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def op_precond_apply(self, precond, r, z=None):
+        z = z if z is not None else self.cells_tensor()
+        pc = PRECONDS[precond] if isinstance(precond, str) else precond
+        self._chk(lib().sim_op_precond_apply(self.ctx, pc, _ptr(r), _ptr(z)))
+        return z
+
+    def op_advect_adjoint(self, u, lam, out=None):
+        out = out if out is not None else self.faces()
+        self._chk(lib().sim_op_advect_adjoint(self.ctx, *map(_ptr, u), *map(_ptr, lam),
+                                              *map(_ptr, out)))
+        return out
+
+    # -- learned preconditioner
+    def net_set_weights(self, w):
+        self._chk(lib().sim_net_set_weights(self.ctx, _ptr(w), w.numel()))
+
+    def net_forward(self, r, z=None):
+        z = z if z is not None else self.cells_tensor()
+        self._chk(lib().sim_net_forward(self.ctx, _ptr(r), _ptr(z)))
+        return z
+
+    def net_train_step(self, r, e, batch, master, adam, step, lr):
+        loss = c_double()
+        self._chk(lib().sim_net_train_step(self.ctx, _ptr(r), _ptr(e), batch, _ptr(master),
+                                           _ptr(adam), step, c_float(lr), byref(loss)))
+        return loss.value
+
+
+def net_param_count():
+    out = c_int64()
+    check(lib().sim_net_param_count(byref(out)))
+    return out.value
