@@ -75,7 +75,9 @@ def test_divergence_and_poisson_apply_parity(torch_gpu, orc, n):
     rng = np.random.default_rng(0)
     x = np.where(cell == 1, rng.standard_normal(cell.shape), 0.0).astype(np.float32)
     y = sim.op_poisson_apply(sim.cells_tensor(x)).cpu().numpy().astype(np.float64)
-    np.testing.assert_allclose(y, orc.poisson_apply(cell, x.astype(np.float64)), rtol=0, atol=3e-6)
+    yref = orc.poisson_apply(cell, x.astype(np.float64))
+    # FP32 sums of up to 7 terms: a few ulp of the largest row value
+    np.testing.assert_allclose(y, yref, rtol=0, atol=1e-6 * np.abs(yref).max())
 
 
 @pytest.mark.parametrize("n", [16, 27])
