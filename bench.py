@@ -1,0 +1,259 @@
+"""Benchmark of the MAC-grid liquid step on one MI355X.
+
+One bench step = one differentiable rollout of the whole hot path on the
+256^3 workload (seeded slab + 3 ellipsoids liquid mask, curl-of-potential
+initial velocity, nu drawn log-uniformly from [1e-4, 1e-1] for seed 4,
+gravity (0,-9.8,0), dt = 1/120): u0 = s * mask(ugen), `--rollout` steps of
+advection + viscosity + pressure projection to a 1e-6 FP64 relative
+residual (recorded, checkpoint every 16 steps), the MSE loss against a
+target rollout, and the full checkpointed reverse pass (adjoint projection
+solves included).  Inputs are resident in HBM before timing starts.
+
+value = cell-steps/s = n^3 * rollout / (seconds per bench step).
+
+Also reported: ms per projection and iterations for each preconditioner on
+the same state (learned-FCG vs plain PCG), the roofline of the dominant
+kernel from HIP-event timing inside the timed region, and the FP64 CPU
+oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+# Algorithmic bytes per unit (cell, or face for the viscosity CG) of each
+# timed kernel kind: every array the operation must read or write once.
+BYTES_PER_UNIT = {
+    "pcg_dir_spmv": 17.0,   # r 4 + diag 1 + d 4 in; d 4 + q 4 out
+    # Jacobi PCG updates the FP64 iterate every second iteration: odd
+    # iterations move r 4+4, q 4, diag 1 (13 B), even ones also x 8+8 and two
+    # directions 4+4 (37 B); the average is 25 B.  (33 B for MIC(0)/learned.)
+    "pcg_update": 25.0,
+    "pcg_check": 17.0,      # x 8, b 4, diag 1 in; r 4 out
+    "advect": 9.0,          # own component 4 + face code 1 in; 4 out (per face)
+    "diffuse_explicit": 9.0,
+    "dcg_dir_spmv": 17.0,   # per face, as pcg_dir_spmv
+    "dcg_update": 33.0,
+    "advect_adjoint": 21.0,  # state 4 + lambda 4 + code 1 in; 3 x 4 scattered gradient
+}
+FACE_KINDS = {"advect", "diffuse_explicit", "dcg_dir_spmv", "dcg_update", "advect_adjoint"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=256)
+    p.add_argument("--rollout", type=int, default=64)
+    p.add_argument("--checkpoint", type=int, default=16)
+    p.add_argument("--warmup-rollout", type=int, default=2,
+                   help="rollout length of the untimed warmup steps")
+    p.add_argument("--precond", default="auto", choices=["auto", "jacobi", "mic0", "learned"])
+    p.add_argument("--weights", default=os.path.join(ROOT, "paper_2503_00868_amd", "weights",
+                                                     "unet.safetensors"))
+    p.add_argument("--seed", type=int, default=4)
+    p.add_argument("--no-compare", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-n", type=int, default=128)
+    return p.parse_args()
+
+
+def cpu_baseline(n, seed):
+    """The FP64 oracle's step (advect, force, viscosity, projection to a
+    1e-6 relative residual) on one seed at n^3, timed on the host."""
+    import numpy as np
+    from oracle import fluid as orc
+    from paper_2503_00868_amd import inputs
+    cell, ug = inputs.gen_case(n, seed)
+    nu = inputs.gen_nu(seed)
+    u0 = orc.mask_faces(cell, ug)
+    orc.lib()
+    t0 = time.perf_counter()
+    _, info = orc.step(cell, u0, nu, 1.0 / 120, tol=1e-6, diff_tol=1e-6)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 / dt, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step of the FP64 oracle at {n}^3, seed {seed} (plain CG to 1e-6, "
+                      f"{info.proj_iters} iterations, {'explicit' if info.explicit else 'implicit'}"
+                      f" viscosity), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2503_00868_amd import inputs
+    from paper_2503_00868_amd.fluidsim import Sim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, T, K = args.n, args.rollout, args.checkpoint
+    dt = 1.0 / 120
+    g = (0.0, -9.8, 0.0)
+
+    precond = args.precond
+    weights = None
+    if precond in ("auto", "learned"):
+        if os.path.exists(args.weights):
+            from paper_2503_00868_amd import unet
+            weights = unet.load_weights(args.weights, dev)
+            precond = "learned"
+        elif precond == "learned":
+            raise SystemExit(f"no trained weights at {args.weights}")
+        else:
+            precond = "jacobi"
+    log(f"n={n} rollout={T} checkpoint={K} precond={precond}")
+
+    cell, ug = inputs.gen_case(n, args.seed)
+    nu_t, s_t = inputs.gen_nu(100), inputs.gen_scale(100)
+    nu_e, s_e = inputs.gen_nu(101), inputs.gen_scale(101)
+    log(f"liquid fraction {inputs.liquid_fraction(cell):.3f}; nu*={nu_t:.3e} s*={s_t:.3f}; "
+        f"eval nu={nu_e:.3e} s={s_e:.3f}")
+
+    sim = Sim(cell, precond=precond, tol=1e-6, diff_tol=1e-6, max_iter=20000, check_every=8,
+              checkpoint_every=K, max_steps=T, device=dev)
+    if weights is not None:
+        sim.net_set_weights(weights)
+    ugen = sim.to_faces(ug)
+    u = sim.faces()
+
+    # target rollout (untimed setup)
+    sim.set_params(nu=nu_t, dt=dt, s=s_t, gravity=g)
+    target = sim.faces()
+    sim.init_state(ugen, target)
+    sim.step(target, T)
+    torch.cuda.synchronize()
+
+    def bench_step(rollout):
+        sim.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
+        sim.init_state(ugen, u)
+        st = sim.step(u, rollout, record=True)
+        J, gT = sim.loss_mse(u, target)
+        _, dnu, ds, bst = sim.backward(gT, ugen=ugen)
+        return st, bst, J, dnu, ds
+
+    for _ in range(args.warmup):
+        bench_step(args.warmup_rollout)
+    torch.cuda.synchronize()
+
+    sim.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd_stats, bwd_stats = [], []
+    for _ in range(args.steps):
+        st, bst, J, dnu, ds = bench_step(T)
+        fwd_stats += st
+        bwd_stats.append(bst)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile_enable(False)
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n ** 3 * T / (elapsed / args.steps)
+    fwd_iters = [s["iters"] for s in fwd_stats]
+    log(f"{ms_per_step:.1f} ms per bench step; {value:.3e} cell-steps/s; pressure iters "
+        f"fwd mean {np.mean(fwd_iters):.1f}; adjoint iters {bwd_stats[-1]['iters']}; J={J:.4e} "
+        f"dJ/dnu={dnu:.4e} dJ/ds={ds:.4e}")
+
+    # roofline of the dominant bandwidth kernel
+    C, F3 = n ** 3, 3 * (n + 1) * n * n
+    kinds = {k: v for k, v in prof.items() if k in BYTES_PER_UNIT and v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms_tot, launches = kinds[dom]
+    units = F3 if dom in FACE_KINDS else C
+    per_unit = BYTES_PER_UNIT[dom]
+    if dom == "pcg_update" and precond != "jacobi":
+        per_unit = 33.0
+    per_launch = per_unit * units
+    avg_s = ms_tot / launches / 1e3
+    achieved = per_launch / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_us": round(avg_s * 1e6, 2), "launches": launches,
+                "bytes_per_launch": per_launch}
+    log("kernel time in the timed region (ms, launches): " +
+        ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items() if v[1]))
+
+    compare = None
+    if not args.no_compare:
+        compare = {}
+        for pc in ("jacobi", "mic0", "learned"):
+            if pc == "learned" and weights is None:
+                continue
+            if pc == "mic0" and n > 128:
+                # hyperplane MIC(0) sweeps: 2 x (3n - 2) dependent launches per apply
+                pass
+            s2 = Sim(cell, precond=pc, tol=1e-6, check_every=8, device=dev)
+            if pc == "learned":
+                s2.net_set_weights(weights)
+            s2.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
+            uu = sim.faces()
+            s2.init_state(ugen, uu)
+            s2.step(uu, 1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st2, _ = s2.project(uu)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3
+            compare[pc] = {"ms_per_projection": round(ms, 2), "iters": st2["iters"],
+                           "rel_residual": st2["rel_residual"]}
+            log(f"projection with {pc}: {ms:.1f} ms, {st2['iters']} iterations")
+            s2.close()
+            del s2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle sample at {args.cpu_n}^3 ...")
+        cpu = cpu_baseline(args.cpu_n, args.seed)
+        log(f"CPU oracle: {cpu['value']:.3e} cell-steps/s ({cpu['sample']})")
+
+    out = {
+        "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 iterate, dots and residual)",
+        "data": "synthetic (seeded slab + ellipsoids mask, curl-of-potential velocity)",
+        "config": {"workload": f"differentiable rollout {n}^3 x {T} steps, forward + "
+                               f"checkpointed adjoint (K={K}), {precond} pressure "
+                               f"preconditioner, tol 1e-6",
+                   "n": n, "rollout": T, "checkpoint_every": K, "precond": precond,
+                   "seed": args.seed, "nu": nu_e, "s": s_e},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "compare": compare,
+        "pressure_iters_mean": float(np.mean(fwd_iters)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

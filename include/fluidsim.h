@@ -72,8 +72,9 @@ typedef struct {
     int32_t n;                 /* cells per axis, 4 <= n <= 1024; n % 4 == 0 for LEARNED */
     int32_t precond;           /* SIM_PRECOND_* for the pressure solve */
     int32_t diffusion;         /* SIM_DIFFUSION_*; AUTO = explicit iff nu*dt*n^2 <= 1/12 */
-    int32_t max_iter;          /* per solve, >= 1 */
-    int32_t check_every;       /* FP64 true-residual check period m, 1..1024 */
+    int32_t max_iter;          /* per solve, >= 1 (Jacobi: rounded up to even) */
+    int32_t check_every;       /* FP64 true-residual check period m, 1..1024 (Jacobi: rounded
+                                  up to even; it updates the FP64 iterate every 2 iterations) */
     int32_t checkpoint_every;  /* K: rollout checkpoint spacing for sim_backward, >= 1 */
     int32_t max_steps;         /* longest recordable rollout (0 = no recording) */
     int32_t learned_max_iter;  /* flexible-CG iterations before the MIC(0) restart */
@@ -183,6 +184,28 @@ int sim_op_precond_apply(sim_ctx* ctx, int32_t precond, const float* d_r, float*
 int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
                           const float* d_lu, const float* d_lv, const float* d_lw, float* d_gu,
                           float* d_gv, float* d_gw);
+
+/* ---- kernel timing for benchmarks -------------------------------------
+ * When enabled, HIP events on the context's stream bracket every launch of
+ * the kernels below (the finalize reductions are not included); durations
+ * accumulate per kind until read.  sim_profile_read synchronises the
+ * stream, writes SIM_KERN_COUNT totals in milliseconds and launch counts,
+ * and resets them.  At most 1<<15 launches are timed between reads. */
+enum {
+    SIM_KERN_PCG_DIR_SPMV = 0,  /* d = M^-1 r + beta d ; q = A d ; d.q            */
+    SIM_KERN_PCG_UPDATE,        /* x += alpha d ; r -= alpha q ; r.M^-1 r          */
+    SIM_KERN_PCG_CHECK,         /* FP64 true residual and residual replacement     */
+    SIM_KERN_ADVECT,            /* semi-Lagrangian advection + body force          */
+    SIM_KERN_DIFFUSE_EXPLICIT,  /* explicit viscosity step                          */
+    SIM_KERN_DCG_DIR_SPMV,      /* implicit viscosity CG: direction + SpMV          */
+    SIM_KERN_DCG_UPDATE,        /* implicit viscosity CG: update                    */
+    SIM_KERN_MIC0,              /* one MIC(0) apply (all hyperplane launches)        */
+    SIM_KERN_NET,               /* one U-Net preconditioner apply                   */
+    SIM_KERN_ADVECT_ADJOINT,    /* advection adjoint scatter                        */
+    SIM_KERN_COUNT
+};
+int sim_profile_enable(sim_ctx* ctx, int32_t on);
+int sim_profile_read(sim_ctx* ctx, double* h_ms, int64_t* h_launches);
 
 int sim_destroy(sim_ctx* ctx);
 const char* sim_last_error(const sim_ctx* ctx);

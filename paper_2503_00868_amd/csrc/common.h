@@ -1,6 +1,5 @@
 // Device-side helpers shared by the fluidsim kernels: grid layout, the
-// XCD-aware block order, wave64/LDS reductions in FP64 and the last-block
-// finish that keeps CG scalars on the device.
+// XCD-aware block order and wave64/LDS reductions in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -95,43 +94,18 @@ __device__ inline void block_sum(double (&v)[NV]) {
   }
 }
 
-// Each block stores its NV partial sums; the last block to finish adds all
-// partials in block order (deterministic for a given grid) and returns true
-// with the totals in `tot` (valid in every thread of that block).  The
-// counter is reset for the next launch.
+// Block-level partial sums are stored per block; a one-block finalize
+// kernel (k_finalize) adds them in block order (deterministic for a given
+// grid) and turns them into solver scalars.  A kernel boundary, not a
+// device-scope fence per block, makes the partials visible: on this chip a
+// release fence per block costs ~20 ns each, serialised.
 template <int NV>
-__device__ inline bool finish_sums(double (&v)[NV], double* partials, unsigned* counter,
-                                   int nblocks, int block_id, double (&tot)[NV]) {
-  __shared__ bool is_last;
-  __shared__ double res[NV];
+__device__ inline void store_partials(double (&v)[NV], double* partials, int block_id) {
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) partials[(int64_t)block_id * NV + q] = v[q];
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == (unsigned)nblocks - 1u);
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] += __builtin_nontemporal_load(&partials[(int64_t)b * NV + q]);
-  }
-  block_sum<NV>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) res[q] = acc[q];
-    *counter = 0u;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NV; ++q) tot[q] = res[q];
-  return true;
 }
 
 }  // namespace fs

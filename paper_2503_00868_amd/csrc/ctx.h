@@ -24,6 +24,7 @@ enum ScalarSlot {
   S_DOT0,      // general-purpose reduction results
   S_DOT1,
   S_DOT2,
+  S_ALPHA_PREV,  // alpha of the previous iteration (two-step iterate update)
   S_COUNT = 32
 };
 enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };
@@ -38,9 +39,24 @@ struct CF3 {
 // Kinds of preconditioner application inside the Poisson CG.
 enum PrecKind { PK_JACOBI = 0, PK_ZARRAY = 1 };
 
+// What the one-block finalize kernel does with the summed partials
+// ([...] lists the partial sums per block it expects).
+enum FinMode : int {
+  FIN_PCG_INIT = 0,  // [bb, rz]      -> BB, RR, RZ, RZ_PREV, BETA = 0; flags reset
+  FIN_DQ,            // [dq]          -> DQ; iteration counted; breakdown if dq <= 0
+  FIN_RZ_UPD,        // [rz]          -> RZ_PREV = RZ, RZ, BETA = rz / RZ_PREV
+  FIN_RZ_FIRST,      // [rz]          -> RZ, RZ_PREV, BETA = 0
+  FIN_CHECK,         // [rr, rz]      -> RR; (jacobi) RZ, BETA; done at tol
+  FIN_FCG_DQDR,      // [dq, dr]      -> DQ, DR; iteration counted; breakdown
+  FIN_FCG_BETA,      // [zq]          -> BETA = -zq / DQ
+  FIN_DCG_INIT,      // [bb, rz, rr]  -> BB, RZ, RZ_PREV, RR, BETA = 0; done at tol
+  FIN_SLOT,          // [v]           -> scal[slot] = (acc ? scal[slot] : 0) + scale * v
+};
+
 }  // namespace fs
 
 struct UNetState;
+struct Profiler;
 
 struct sim_ctx {
   sim_desc desc;
@@ -83,7 +99,6 @@ struct sim_ctx {
   // reductions
   double* partials = nullptr;
   double* scal = nullptr;
-  unsigned* counter = nullptr;
   int* flags = nullptr;
 
   // rollout recording
@@ -104,12 +119,19 @@ struct sim_ctx {
 
   // host readback
   double* h_scal = nullptr;  // pinned: S_COUNT doubles + F_COUNT ints
+  Profiler* prof = nullptr;  // kernel timing (sim_profile_*), off by default
   std::string err;
 };
 
 namespace fs {
 
+// Kernel timing: HIP events around the main kernel of each kind, recorded
+// on ctx->stream when profiling is enabled (no-op otherwise).
+void prof_mark(sim_ctx* c, int kind, bool begin);
+
 // ---- launchers (k_*.hip) ----
+void launch_finalize(sim_ctx* c, int nblocks, int nv, int mode, double tol2, int jacobi, int slot,
+                     double scale, int acc);
 void launch_setup_tables(sim_ctx* c);
 void launch_mic0_setup(sim_ctx* c);
 void launch_mic0_apply(sim_ctx* c, const float* r, float* z, const int* flags);
@@ -125,6 +147,8 @@ void launch_copy_faces(sim_ctx* c, CF3 in, F3 out);
 void launch_pcg_init(sim_ctx* c, int prec);
 void launch_pcg_dir_spmv(sim_ctx* c, int prec, const float* d_in, float* d_out);
 void launch_pcg_update(sim_ctx* c, int prec, const float* d);
+// Jacobi only: odd iterations update r; even ones also x += a_prev d_prev + a d
+void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool with_x);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);

@@ -124,6 +124,7 @@ void launch_mic0_setup(sim_ctx* c) {
 
 void launch_mic0_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
   const int n = c->n;
+  prof_mark(c, SIM_KERN_MIC0, true);
   for (int s = 0; s <= 3 * (n - 1); ++s) {
     PlaneRange pr = plane_range(n, s);
     int threads = n * pr.k_count;
@@ -136,6 +137,7 @@ void launch_mic0_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
     hipLaunchKernelGGL(k_mic0_bwd_plane, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        c->stream, n, s, pr.k_lo, pr.k_count, c->cdiag, c->precon, c->mq, z, flags);
   }
+  prof_mark(c, SIM_KERN_MIC0, false);
 }
 
 }  // namespace fs

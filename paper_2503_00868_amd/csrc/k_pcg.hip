@@ -5,238 +5,806 @@
 // off liquid); off-diagonals are -1 between liquid neighbours.  Every vector
 // is zero off liquid, so a neighbour read needs no mask.  The iterate x is
 // FP64; r, z, d, q are FP32; every dot product is accumulated in FP64.
-// The scalars alpha and beta never leave the device: the last block of each
-// reduction computes them (deterministic order) for the next kernel.
 //
-// One iteration of Jacobi PCG is two kernels:
-//   dir_spmv : d' = M^-1 r + beta d ; q = A d' ; partial d'.q
-//   update   : alpha = rz / dq ; x += alpha d' ; r -= alpha q ; partial r.M^-1 r
+// One iteration of Jacobi PCG is two streaming kernels, each followed by a
+// one-block finalize kernel that reduces the per-block partials and computes
+// the CG scalar on the device:
+//   dir_spmv : d' = M^-1 r + beta d ; q = A d' ; partial d'.q  -> alpha
+//   update   : x += alpha d' ; r -= alpha q ; partial r.M^-1 r -> beta
 // With an explicit preconditioner (MIC(0), learned) z is an array computed
 // between update and the next dir_spmv, and a separate kernel reduces r.z.
 // Every m iterations `check` recomputes r = b - A x from the FP64 x (FP64
 // residual replacement), reduces |r|^2 and raises the done flag at tol.
 // Every kernel returns at once when the done flag is set, so the host can
 // enqueue the next block of iterations before it has read the flag.
+//
+// Cell-domain kernels take V = 4 consecutive x-cells per thread (float4,
+// double2 and 32-bit mask loads) when n % 4 == 0, else V = 1.  The x
+// neighbours of a thread's cells come from the adjacent lanes by wave
+// shuffle; y and z neighbours are vector loads served mostly by L2.
 #include "common.h"
 #include "ctx.h"
 
 namespace fs {
 
-struct Chunk2 {
-  int64_t begin, end;
-};
-
-__device__ inline Chunk2 chunk_of(int64_t total, int nblocks, int lb) {
-  int64_t per = (total + nblocks - 1) / nblocks;
-  per = (per + kBlock - 1) / kBlock * kBlock;
-  int64_t b = per * lb;
-  int64_t e = b + per < total ? b + per : total;
-  return Chunk2{b, e};
-}
-
 __constant__ float c_inv_count[8] = {0.f, 1.f, 0.5f, 1.f / 3.f, 0.25f, 0.2f, 1.f / 6.f, 0.f};
 
-// (A v)_c for liquid c, in the precision of T.
-template <typename T, typename V>
-__device__ inline T poisson_row(const V* __restrict__ v, int64_t idx, uint8_t dg, const Walker& w,
-                                int n) {
-  const int64_t sy = n, sz = (int64_t)n * n;
-  T s = (T)dg * (T)v[idx];
-  if (w.i > 0) s -= (T)v[idx - 1];
-  if (w.i < n - 1) s -= (T)v[idx + 1];
-  if (w.j > 0) s -= (T)v[idx - sy];
-  if (w.j < n - 1) s -= (T)v[idx + sy];
-  if (w.k > 0) s -= (T)v[idx - sz];
-  if (w.k < n - 1) s -= (T)v[idx + sz];
-  return s;
+// ------------------------------------------------------------ vector I/O
+
+template <int V>
+__device__ inline void ldf(const float* __restrict__ p, float (&o)[V]) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x, o[1] = t.y, o[2] = t.z, o[3] = t.w;
+  } else {
+    o[0] = *p;
+  }
+}
+
+template <int V>
+__device__ inline void stf(float* __restrict__ p, const float (&o)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else {
+    *p = o[0];
+  }
+}
+
+template <int V>
+__device__ inline void ldd(const double* __restrict__ p, double (&o)[V]) {
+  if constexpr (V == 4) {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+  } else {
+    o[0] = *p;
+  }
+}
+
+template <int V>
+__device__ inline void std_(double* __restrict__ p, const double (&o)[V]) {
+  if constexpr (V == 4) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+  } else {
+    *p = o[0];
+  }
+}
+
+template <int V>
+__device__ inline void ldg(const uint8_t* __restrict__ p, uint8_t (&o)[V]) {
+  if constexpr (V == 4) {
+    const uint32_t t = *reinterpret_cast<const uint32_t*>(p);
+    o[0] = t & 255u, o[1] = (t >> 8) & 255u, o[2] = (t >> 16) & 255u, o[3] = t >> 24;
+  } else {
+    o[0] = *p;
+  }
+}
+
+// Block-contiguous run of V-cell groups with a uniform trip count, so every
+// lane takes part in every shuffle.
+struct Run {
+  int64_t begin, end;  // in groups
+  int trips;
+};
+
+__device__ inline Run group_run(int64_t groups, int nblocks, int lb) {
+  int64_t per = (groups + nblocks - 1) / nblocks;
+  per = (per + kBlock - 1) / kBlock * kBlock;
+  Run r;
+  r.begin = per * lb;
+  r.end = r.begin + per < groups ? r.begin + per : groups;
+  r.trips = (int)(per / kBlock);
+  return r;
+}
+
+// ------------------------------------------------------------ finalize
+
+__global__ void __launch_bounds__(kBlock)
+    k_finalize(const double* __restrict__ partials, int nblocks, int nv, int mode, double* scal,
+               int* flags, double tol2, int jacobi, int slot, double scale, int acc) {
+  const bool in_loop = mode == FIN_DQ || mode == FIN_RZ_UPD || mode == FIN_RZ_FIRST ||
+                       mode == FIN_CHECK || mode == FIN_FCG_DQDR || mode == FIN_FCG_BETA;
+  if (in_loop && flags[F_DONE]) return;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    for (int q = 0; q < nv; ++q) v[q] += partials[(int64_t)b * nv + q];
+  block_sum<3>(v);
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case FIN_PCG_INIT:
+      scal[S_BB] = v[0];
+      scal[S_RR] = v[0];
+      scal[S_RZ] = v[1];
+      scal[S_RZ_PREV] = v[1];
+      scal[S_BETA] = 0.0;
+      flags[F_DONE] = v[0] == 0.0 ? 1 : 0;
+      flags[F_ITERS] = 0;
+      flags[F_ITERS_AT_DONE] = 0;
+      break;
+    case FIN_DQ:
+      scal[S_DQ] = v[0];
+      flags[F_ITERS] += 1;
+      if (!(v[0] > 0.0)) flags[F_DONE] = 2;  // breakdown: NaN or non-positive curvature
+      break;
+    case FIN_RZ_UPD: {
+      const double rz_old = scal[S_RZ];
+      scal[S_RZ_PREV] = rz_old;
+      scal[S_RZ] = v[0];
+      scal[S_BETA] = v[0] / rz_old;
+      if (!(v[0] >= 0.0)) flags[F_DONE] = 2;
+      break;
+    }
+    case FIN_RZ_FIRST:
+      scal[S_RZ] = v[0];
+      scal[S_RZ_PREV] = v[0];
+      scal[S_BETA] = 0.0;
+      if (!(v[0] > 0.0)) flags[F_DONE] = 2;
+      break;
+    case FIN_CHECK:
+      scal[S_RR] = v[0];
+      if (jacobi) {
+        scal[S_RZ] = v[1];
+        scal[S_BETA] = scal[S_RZ_PREV] > 0.0 ? v[1] / scal[S_RZ_PREV] : 0.0;
+      }
+      if (v[0] <= tol2 * scal[S_BB]) {
+        flags[F_DONE] = 1;
+        flags[F_ITERS_AT_DONE] = flags[F_ITERS];
+      } else if (!(v[0] == v[0])) {
+        flags[F_DONE] = 2;
+      }
+      break;
+    case FIN_FCG_DQDR:
+      scal[S_DQ] = v[0];
+      scal[S_DR] = v[1];
+      flags[F_ITERS] += 1;
+      if (!(v[0] > 0.0) || !(v[1] > 0.0)) flags[F_DONE] = 2;  // not a descent direction
+      break;
+    case FIN_FCG_BETA:
+      scal[S_BETA] = -v[0] / scal[S_DQ];
+      if (!(scal[S_BETA] == scal[S_BETA])) flags[F_DONE] = 2;
+      break;
+    case FIN_DCG_INIT:
+      scal[S_BB] = v[0];
+      scal[S_RZ] = v[1];
+      scal[S_RZ_PREV] = v[1];
+      scal[S_RR] = v[2];
+      scal[S_BETA] = 0.0;
+      flags[F_DONE] = v[2] <= tol2 * v[0] ? 1 : 0;
+      flags[F_ITERS] = 0;
+      flags[F_ITERS_AT_DONE] = 0;
+      break;
+    case FIN_SLOT:
+      scal[slot] = (acc ? scal[slot] : 0.0) + scale * v[0];
+      break;
+  }
+}
+
+void launch_finalize(sim_ctx* c, int nblocks, int nv, int mode, double tol2, int jacobi, int slot,
+                     double scale, int acc) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, c->partials, nblocks, nv,
+                     mode, c->scal, c->flags, tol2, jacobi, slot, scale, acc);
 }
 
 // ---------------------------------------------------------------- Poisson
 
-template <int PREC>
+template <int V>
+__device__ inline void walk_init(Walker& w, int n, int64_t g0) {
+  w.init(Dims{n / V, n, n}, g0, kBlock);
+}
+
+template <int V, int PREC>
 __global__ void __launch_bounds__(kBlock)
     k_pcg_init(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
                double* __restrict__ x, float* __restrict__ r, float* __restrict__ d0,
-               double* partials, unsigned* counter, double* scal, int* flags) {
-  const int64_t C = cells(n);
+               double* partials) {
+  const int64_t G = cells(n) / V;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
+  const Run run = group_run(G, gridDim.x, lb);
   double v[2] = {0.0, 0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock) {
-    const float bv = b[idx];
-    x[idx] = 0.0;
-    r[idx] = bv;
-    d0[idx] = 0.f;
-    v[0] += (double)bv * bv;
-    if (PREC == PK_JACOBI) v[1] += (double)bv * bv * c_inv_count[cdiag[idx]];
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
+    const int64_t idx = g * V;
+    float bv[V], z[V];
+    uint8_t dg[V];
+    double xz[V];
+    ldf<V>(b + idx, bv);
+    ldg<V>(cdiag + idx, dg);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      z[e] = 0.f;
+      xz[e] = 0.0;
+      v[0] += (double)bv[e] * bv[e];
+      if (PREC == PK_JACOBI) v[1] += (double)bv[e] * bv[e] * c_inv_count[dg[e]];
+    }
+    std_<V>(x + idx, xz);
+    stf<V>(r + idx, bv);
+    stf<V>(d0 + idx, z);
   }
-  double tot[2];
-  if (finish_sums<2>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    scal[S_BB] = tot[0];
-    scal[S_RR] = tot[0];
-    scal[S_RZ] = tot[1];
-    scal[S_RZ_PREV] = tot[1];
-    scal[S_BETA] = 0.0;
-    flags[F_DONE] = tot[0] == 0.0 ? 1 : 0;
-    flags[F_ITERS] = 0;
-    flags[F_ITERS_AT_DONE] = 0;
-  }
+  store_partials<2>(v, partials, lb);
 }
 
-template <int PREC>
+// Direction at V cells: z + beta * d_in with z = r / diag (Jacobi) or z.
+template <int V, int PREC>
+__device__ inline void dir_at(const float* __restrict__ r, const float* __restrict__ z,
+                              const uint8_t* __restrict__ cdiag, const float* __restrict__ d_in,
+                              int64_t idx, float beta, float (&o)[V]) {
+  float dv[V], zv[V];
+  ldf<V>(d_in + idx, dv);
+  if (PREC == PK_JACOBI) {
+    float rv[V];
+    uint8_t gv[V];
+    ldf<V>(r + idx, rv);
+    ldg<V>(cdiag + idx, gv);
+#pragma unroll
+    for (int e = 0; e < V; ++e) zv[e] = rv[e] * c_inv_count[gv[e]];
+  } else {
+    ldf<V>(z + idx, zv);
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e) o[e] = zv[e] + beta * dv[e];
+}
+
+// d' = z + beta d_in ; q = A d' ; partials d'.q (and d'.r for flexible CG).
+template <int V, int PREC, bool FLEX>
 __global__ void __launch_bounds__(kBlock)
-    k_pcg_dir_spmv(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
-                   const float* __restrict__ z, const float* __restrict__ d_in,
-                   float* __restrict__ d_out, float* __restrict__ q, double* partials,
-                   unsigned* counter, double* scal, int* flags) {
+    k_dir_spmv(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
+               const float* __restrict__ z, const float* __restrict__ d_in,
+               float* __restrict__ d_out, float* __restrict__ q, const double* __restrict__ scal,
+               const int* __restrict__ flags, double* partials) {
   if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
+  const int64_t G = cells(n) / V;
   const float beta = (float)scal[S_BETA];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
+  const Run run = group_run(G, gridDim.x, lb);
   const int64_t sy = n, sz = (int64_t)n * n;
-  auto dir = [&](int64_t m) -> float {
-    const float zm = PREC == PK_JACOBI ? r[m] * c_inv_count[cdiag[m]] : z[m];
-    return zm + beta * d_in[m];
-  };
+  const int lane = threadIdx.x & (kWave - 1);
   Walker w;
-  w.init(Dims{n, n, n}, ch.begin + threadIdx.x, kBlock);
-  double v[1] = {0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
-    const uint8_t dg = cdiag[idx];
-    if (!dg) {
-      d_out[idx] = 0.f;
-      q[idx] = 0.f;
-      continue;
+  walk_init<V>(w, n, run.begin + threadIdx.x);
+  double v[2] = {0.0, 0.0};
+  for (int t = 0; t < run.trips; ++t, w.next()) {
+    const int64_t g = run.begin + threadIdx.x + (int64_t)t * kBlock;
+    const bool act = g < run.end;
+    const int64_t idx = g * V;
+    const int i = w.i * V;
+    float dc[V];
+    uint8_t dg[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) dc[e] = 0.f, dg[e] = 0;
+    if (act) {
+      dir_at<V, PREC>(r, z, cdiag, d_in, idx, beta, dc);
+      ldg<V>(cdiag + idx, dg);
     }
-    const float dc = dir(idx);
-    float s = 0.f;
-    if (w.i > 0) s += dir(idx - 1);
-    if (w.i < n - 1) s += dir(idx + 1);
-    if (w.j > 0) s += dir(idx - sy);
-    if (w.j < n - 1) s += dir(idx + sy);
-    if (w.k > 0) s += dir(idx - sz);
-    if (w.k < n - 1) s += dir(idx + sz);
-    const float qc = (float)dg * dc - s;
-    d_out[idx] = dc;
-    q[idx] = qc;
-    v[0] += (double)dc * (double)qc;
+    // x neighbours from the adjacent lanes (the previous/next group of the same row)
+    float left = __shfl_up(dc[V - 1], 1, kWave);
+    float right = __shfl_down(dc[0], 1, kWave);
+    if (!act) continue;
+    if (i > 0 && lane == 0) {
+      float t1[1];
+      dir_at<1, PREC>(r, z, cdiag, d_in, idx - 1, beta, t1);
+      left = t1[0];
+    }
+    if (i + V < n && lane == kWave - 1) {
+      float t1[1];
+      dir_at<1, PREC>(r, z, cdiag, d_in, idx + V, beta, t1);
+      right = t1[0];
+    }
+    float s[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) s[e] = 0.f;
+    if (w.j > 0) {
+      float t4[V];
+      dir_at<V, PREC>(r, z, cdiag, d_in, idx - sy, beta, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    }
+    if (w.j < n - 1) {
+      float t4[V];
+      dir_at<V, PREC>(r, z, cdiag, d_in, idx + sy, beta, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    }
+    if (w.k > 0) {
+      float t4[V];
+      dir_at<V, PREC>(r, z, cdiag, d_in, idx - sz, beta, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    }
+    if (w.k < n - 1) {
+      float t4[V];
+      dir_at<V, PREC>(r, z, cdiag, d_in, idx + sz, beta, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    }
+    if (i > 0) s[0] += left;
+    if (i + V < n) s[V - 1] += right;
+#pragma unroll
+    for (int e = 1; e < V; ++e) s[e] += dc[e - 1];
+#pragma unroll
+    for (int e = 0; e + 1 < V; ++e) s[e] += dc[e + 1];
+    float qv[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      qv[e] = dg[e] ? (float)dg[e] * dc[e] - s[e] : 0.f;
+      v[0] += (double)dc[e] * (double)qv[e];
+    }
+    if (FLEX) {
+      float rv[V];
+      ldf<V>(r + idx, rv);
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[1] += (double)dc[e] * (double)rv[e];
+    }
+    stf<V>(d_out + idx, dc);
+    stf<V>(q + idx, qv);
   }
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    scal[S_DQ] = tot[0];
-    if (!(tot[0] > 0.0)) flags[F_DONE] = 2;  // breakdown (NaN or non-positive curvature)
+  store_partials<2>(v, partials, lb);
+}
+
+// ------------------------------------------------- z-marching stencils
+// The same d' = z + beta d ; q = A d' (and the FP64 check) organised so
+// every cell's direction is formed exactly once: a block owns a tile of
+// 64 (x) x 16 (y) cells and marches up a chunk of z planes.  Each thread
+// holds one 4-cell group; the direction of planes z-1, z, z+1 stays in
+// registers, the current plane (plus a one-cell halo) goes through LDS for
+// the x and y neighbours.  Halo cells outside the box are written as zero,
+// which is also their contribution (every vector is zero off liquid).
+constexpr int ZM_GX = 16;  // 4-cell groups per tile along x (64 cells)
+constexpr int ZM_TY = 16;  // rows per tile
+constexpr int ZM_W = 4 * ZM_GX + 2;
+
+struct ZTile {
+  int x0, y0, z0, z1, x, y, gx, ty;
+  bool in_xy;
+};
+
+__device__ inline ZTile ztile(int n, int zc) {
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tiles_x = (n + 4 * ZM_GX - 1) / (4 * ZM_GX);
+  const int tiles_y = (n + ZM_TY - 1) / ZM_TY;
+  ZTile t;
+  const int txi = lb % tiles_x;
+  const int rest = lb / tiles_x;
+  t.x0 = txi * 4 * ZM_GX;
+  t.y0 = (rest % tiles_y) * ZM_TY;
+  t.z0 = (rest / tiles_y) * zc;
+  t.z1 = t.z0 + zc < n ? t.z0 + zc : n;
+  t.gx = threadIdx.x % ZM_GX;
+  t.ty = threadIdx.x / ZM_GX;
+  t.x = t.x0 + 4 * t.gx;
+  t.y = t.y0 + t.ty;
+  t.in_xy = t.x < n && t.y < n;
+  return t;
+}
+
+// Raw inputs of the direction at one 4-cell group (z = r/diag for Jacobi,
+// else the explicit z array).
+template <int PREC>
+struct DirRaw {
+  float a[4];  // r (Jacobi) or z
+  float d[4];
+  uint32_t g;
+};
+
+template <int PREC>
+__device__ inline void dir_raw_load(const float* __restrict__ r, const float* __restrict__ z,
+                                    const uint8_t* __restrict__ cdiag,
+                                    const float* __restrict__ d_in, int64_t idx, bool ok,
+                                    DirRaw<PREC>& o) {
+  if (ok) {
+    ldf<4>((PREC == PK_JACOBI ? r : z) + idx, o.a);
+    ldf<4>(d_in + idx, o.d);
+    o.g = PREC == PK_JACOBI ? *reinterpret_cast<const uint32_t*>(cdiag + idx) : 0u;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o.a[e] = 0.f, o.d[e] = 0.f;
+    o.g = 0u;
   }
 }
 
 template <int PREC>
+__device__ inline void dir_raw_eval(const DirRaw<PREC>& w, float beta, float (&o)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float zv =
+        PREC == PK_JACOBI ? w.a[e] * c_inv_count[(w.g >> (8 * e)) & 255u] : w.a[e];
+    o[e] = zv + beta * w.d[e];
+  }
+}
+
+template <int PREC, bool FLEX>
 __global__ void __launch_bounds__(kBlock)
-    k_pcg_update(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
-                 float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
-                 double* partials, unsigned* counter, double* scal, int* flags) {
+    k_dir_spmv_zm(int n, int zc, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
+                  const float* __restrict__ z, const float* __restrict__ d_in,
+                  float* __restrict__ d_out, float* __restrict__ q, const double* __restrict__ scal,
+                  const int* __restrict__ flags, double* partials) {
   if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
+  __shared__ float sd[ZM_TY + 2][ZM_W];
+  const float beta = (float)scal[S_BETA];
+  const ZTile t = ztile(n, zc);
+  const int64_t sz = (int64_t)n * n;
+  auto gidx = [&](int xx, int yy, int zz) -> int64_t { return xx + (int64_t)n * yy + sz * zz; };
+  auto in_box = [&](int xx, int yy, int zz) {
+    return xx >= 0 && xx < n && yy >= 0 && yy < n && zz >= 0 && zz < n;
+  };
+  // halo roles: a y-halo group (top or bottom row of the tile) and an x-halo cell
+  const int hy = t.ty == 0 ? t.y0 - 1 : (t.ty == ZM_TY - 1 ? t.y0 + ZM_TY : -1);
+  const int hrow = t.ty == 0 ? 0 : ZM_TY + 1;
+  const int hx = t.gx == 0 ? t.x0 - 1 : (t.gx == ZM_GX - 1 ? t.x0 + 4 * ZM_GX : -1);
+  const int hcol = t.gx == 0 ? 0 : ZM_W - 1;
+  const bool has_hy = (t.ty == 0 || t.ty == ZM_TY - 1) && t.x < n;
+  const bool has_hx = t.gx == 0 || t.gx == ZM_GX - 1;
+
+  auto load_center = [&](int zz, DirRaw<PREC>& o) {
+    dir_raw_load<PREC>(r, z, cdiag, d_in, gidx(t.x, t.y, zz), t.in_xy && zz >= 0 && zz < n, o);
+  };
+  auto load_hy = [&](int zz, DirRaw<PREC>& o) {
+    dir_raw_load<PREC>(r, z, cdiag, d_in, gidx(t.x, hy, zz), has_hy && in_box(t.x, hy, zz), o);
+  };
+  auto load_hx = [&](int zz, float& a, float& d, uint8_t& g) {
+    if (has_hx && in_box(hx, t.y, zz)) {
+      const int64_t m = gidx(hx, t.y, zz);
+      a = (PREC == PK_JACOBI ? r : z)[m];
+      d = d_in[m];
+      g = PREC == PK_JACOBI ? cdiag[m] : 0;
+    } else {
+      a = 0.f, d = 0.f, g = 0;
+    }
+  };
+
+  // pipeline: centre raw data two planes ahead, halo raw data one plane ahead
+  DirRaw<PREC> c1, c2, h1;
+  float hxa, hxd;
+  uint8_t hxg;
+  float dm[4], dc[4], dp[4];
+  {
+    DirRaw<PREC> c0;
+    load_center(t.z0 - 1, c0);
+    load_center(t.z0, c1);
+    dir_raw_eval<PREC>(c0, beta, dm);
+    dir_raw_eval<PREC>(c1, beta, dc);
+  }
+  load_center(t.z0 + 1, c1);
+  load_hy(t.z0, h1);
+  load_hx(t.z0, hxa, hxd, hxg);
+  double v[2] = {0.0, 0.0};
+  for (int zz = t.z0; zz < t.z1; ++zz) {
+    // halo values of plane zz from the data loaded one iteration ago
+    float hyv[4];
+    dir_raw_eval<PREC>(h1, beta, hyv);
+    const float hxv = (PREC == PK_JACOBI ? hxa * c_inv_count[hxg] : hxa) + beta * hxd;
+    dir_raw_eval<PREC>(c1, beta, dp);
+    // issue the next loads before the barrier
+    load_center(zz + 2, c2);
+    load_hy(zz + 1, h1);
+    load_hx(zz + 1, hxa, hxd, hxg);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sd[t.ty + 1][1 + 4 * t.gx + e] = dc[e];
+    if (has_hx) sd[t.ty + 1][hcol] = hxv;
+    if (t.ty == 0 || t.ty == ZM_TY - 1) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sd[hrow][1 + 4 * t.gx + e] = hyv[e];
+    }
+    __syncthreads();
+    if (t.in_xy) {
+      const int64_t idx = gidx(t.x, t.y, zz);
+      uint8_t dg[4];
+      ldg<4>(cdiag + idx, dg);
+      const int c0 = 1 + 4 * t.gx;
+      float qv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float s = sd[t.ty + 1][c0 + e - 1] + sd[t.ty + 1][c0 + e + 1] + sd[t.ty][c0 + e] +
+                        sd[t.ty + 2][c0 + e] + dm[e] + dp[e];
+        qv[e] = dg[e] ? (float)dg[e] * dc[e] - s : 0.f;
+        v[0] += (double)dc[e] * (double)qv[e];
+      }
+      if (FLEX) {
+        float rv[4];
+        ldf<4>(r + idx, rv);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[1] += (double)dc[e] * (double)rv[e];
+      }
+      stf<4>(d_out + idx, dc);
+      stf<4>(q + idx, qv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dm[e] = dc[e], dc[e] = dp[e];
+    c1 = c2;
+  }
+  store_partials<2>(v, partials, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// FP64 true residual r = b - A x with the same tiling (x in LDS as double).
+template <int PREC>
+__global__ void __launch_bounds__(kBlock)
+    k_check_zm(int n, int zc, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
+               const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
+               double* partials) {
+  if (flags[F_DONE]) return;
+  __shared__ double sx[ZM_TY + 2][ZM_W];
+  const ZTile t = ztile(n, zc);
+  const int64_t sz = (int64_t)n * n;
+  auto gidx = [&](int xx, int yy, int zz) -> int64_t { return xx + (int64_t)n * yy + sz * zz; };
+  auto group_x = [&](int xx, int yy, int zz, double (&o)[4]) {
+    if (xx >= 0 && xx < n && yy >= 0 && yy < n && zz >= 0 && zz < n)
+      ldd<4>(x + gidx(xx, yy, zz), o);
+    else
+      o[0] = o[1] = o[2] = o[3] = 0.0;
+  };
+  auto cell_x = [&](int xx, int yy, int zz) -> double {
+    if (xx < 0 || xx >= n || yy < 0 || yy >= n) return 0.0;
+    return x[gidx(xx, yy, zz)];
+  };
+  double xm[4], xc[4], xp[4];
+  group_x(t.in_xy ? t.x : -1, t.y, t.z0 - 1, xm);
+  group_x(t.in_xy ? t.x : -1, t.y, t.z0, xc);
+  double v[2] = {0.0, 0.0};
+  for (int zz = t.z0; zz < t.z1; ++zz) {
+    group_x(t.in_xy ? t.x : -1, t.y, zz + 1, xp);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sx[t.ty + 1][1 + 4 * t.gx + e] = xc[e];
+    if (t.gx == 0) sx[t.ty + 1][0] = cell_x(t.x0 - 1, t.y, zz);
+    if (t.gx == ZM_GX - 1) sx[t.ty + 1][ZM_W - 1] = cell_x(t.x0 + 4 * ZM_GX, t.y, zz);
+    if (t.ty == 0) {
+      double o[4];
+      group_x(t.x < n ? t.x : -1, t.y0 - 1, zz, o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sx[0][1 + 4 * t.gx + e] = o[e];
+    }
+    if (t.ty == ZM_TY - 1) {
+      double o[4];
+      group_x(t.x < n ? t.x : -1, t.y0 + ZM_TY, zz, o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sx[ZM_TY + 1][1 + 4 * t.gx + e] = o[e];
+    }
+    __syncthreads();
+    if (t.in_xy) {
+      const int64_t idx = gidx(t.x, t.y, zz);
+      uint8_t dg[4];
+      float bv[4], rf[4];
+      ldg<4>(cdiag + idx, dg);
+      ldf<4>(b + idx, bv);
+      const int c0 = 1 + 4 * t.gx;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double s = sx[t.ty + 1][c0 + e - 1] + sx[t.ty + 1][c0 + e + 1] + sx[t.ty][c0 + e] +
+                         sx[t.ty + 2][c0 + e] + xm[e] + xp[e];
+        const double rc = dg[e] ? (double)bv[e] - ((double)dg[e] * xc[e] - s) : 0.0;
+        rf[e] = (float)rc;
+        v[0] += rc * rc;
+        if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg[e]];
+      }
+      stf<4>(r + idx, rf);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xm[e] = xc[e], xc[e] = xp[e];
+  }
+  store_partials<2>(v, partials, xcd_logical_block(blockIdx.x, gridDim.x));
+}
+
+// Launch shape of the z-marching kernels: tiles of 64 x 16 cells and a z
+// chunk sized for about 4 blocks per CU (at most 4096 blocks in total).
+struct ZmShape {
+  int blocks, zc;
+};
+
+static ZmShape zm_shape(int n) {
+  const int tiles = ((n + 4 * ZM_GX - 1) / (4 * ZM_GX)) * ((n + ZM_TY - 1) / ZM_TY);
+  int chunks = 1024 / tiles;
+  if (chunks < 1) chunks = 1;
+  if (chunks > n / 4) chunks = n / 4 > 0 ? n / 4 : 1;
+  int zc = (n + chunks - 1) / chunks;
+  chunks = (n + zc - 1) / zc;
+  return ZmShape{tiles * chunks, zc};
+}
+
+// Jacobi PCG update that touches the FP64 iterate only every second
+// iteration: on odd iterations only r -= alpha q (alpha kept in S_ALPHA_PREV),
+// on even iterations x += alpha_prev d_prev + alpha d, r -= alpha q.  Both
+// directions are still in the ping-pong buffers, so this saves the 16 B/cell
+// read-modify-write of x on half of the iterations.
+template <int V, bool WITH_X>
+__global__ void __launch_bounds__(kBlock)
+    k_update2(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
+              float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ d_prev,
+              const float* __restrict__ q, double* __restrict__ scal,
+              const int* __restrict__ flags, double* partials) {
+  if (flags[F_DONE]) return;
+  const int64_t G = cells(n) / V;
   const double alpha = scal[S_RZ] / scal[S_DQ];
+  const double alpha_prev = scal[S_ALPHA_PREV];
   const float alpha_f = (float)alpha;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
+  const Run run = group_run(G, gridDim.x, lb);
   double v[1] = {0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock) {
-    const uint8_t dg = cdiag[idx];
-    if (!dg) continue;
-    x[idx] += alpha * (double)d[idx];
-    const float rn = r[idx] - alpha_f * q[idx];
-    r[idx] = rn;
-    if (PREC == PK_JACOBI) v[0] += (double)rn * (double)rn * c_inv_count[dg];
-  }
-  if (PREC != PK_JACOBI && blockIdx.x == 0 && threadIdx.x == 0) flags[F_ITERS] += 1;
-  if (PREC == PK_JACOBI) {
-    double tot[1];
-    if (finish_sums<1>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-      const double rz_old = scal[S_RZ];
-      scal[S_RZ_PREV] = rz_old;
-      scal[S_RZ] = tot[0];
-      scal[S_BETA] = tot[0] / rz_old;
-      flags[F_ITERS] += 1;
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
+    const int64_t idx = g * V;
+    float qv[V], rv[V];
+    uint8_t dg[V];
+    ldf<V>(q + idx, qv);
+    ldf<V>(r + idx, rv);
+    ldg<V>(cdiag + idx, dg);
+    if (WITH_X) {
+      double xv[V];
+      float dv[V], pv[V];
+      ldd<V>(x + idx, xv);
+      ldf<V>(d + idx, dv);
+      ldf<V>(d_prev + idx, pv);
+#pragma unroll
+      for (int e = 0; e < V; ++e) xv[e] += alpha_prev * (double)pv[e] + alpha * (double)dv[e];
+      std_<V>(x + idx, xv);
     }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      rv[e] -= alpha_f * qv[e];
+      v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+    }
+    stf<V>(r + idx, rv);
   }
+  store_partials<1>(v, partials, lb);
+  if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_PREV] = alpha;
 }
 
-// r.z for an explicit preconditioner output z; beta = rz_new / rz_old
-// (first = 1: start of a solve, beta = 0 and no iteration counted).
+// x += alpha d ; r -= alpha q ; (Jacobi) partial r.M^-1 r.
+// alpha = RZ / DQ (PCG) or DR / DQ (flexible CG).
+template <int V, int PREC, bool FLEX>
 __global__ void __launch_bounds__(kBlock)
-    k_pcg_rz(int n, const float* __restrict__ r, const float* __restrict__ z, int first,
-             double* partials, unsigned* counter, double* scal, int* flags) {
+    k_update(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
+             float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
+             const double* __restrict__ scal, const int* __restrict__ flags, double* partials) {
   if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
+  const int64_t G = cells(n) / V;
+  const double alpha = (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
+  const float alpha_f = (float)alpha;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
+  const Run run = group_run(G, gridDim.x, lb);
   double v[1] = {0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock)
-    v[0] += (double)r[idx] * (double)z[idx];
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    if (first) {
-      scal[S_RZ] = tot[0];
-      scal[S_RZ_PREV] = tot[0];
-      scal[S_BETA] = 0.0;
-    } else {
-      const double rz_old = scal[S_RZ];
-      scal[S_RZ_PREV] = rz_old;
-      scal[S_RZ] = tot[0];
-      scal[S_BETA] = tot[0] / rz_old;
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
+    const int64_t idx = g * V;
+    double xv[V];
+    float dv[V], qv[V], rv[V];
+    uint8_t dg[V];
+    ldd<V>(x + idx, xv);
+    ldf<V>(d + idx, dv);
+    ldf<V>(q + idx, qv);
+    ldf<V>(r + idx, rv);
+    if (PREC == PK_JACOBI) ldg<V>(cdiag + idx, dg);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      xv[e] += alpha * (double)dv[e];
+      rv[e] -= alpha_f * qv[e];
+      if (PREC == PK_JACOBI) v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
     }
-    if (!(tot[0] > 0.0) && !(tot[0] == 0.0 && scal[S_BB] == 0.0)) flags[F_DONE] = 2;
+    std_<V>(x + idx, xv);
+    stf<V>(r + idx, rv);
   }
+  if (PREC == PK_JACOBI) store_partials<1>(v, partials, lb);
 }
 
-// True residual in FP64 from the FP64 iterate; replaces r.  For Jacobi also
-// recomputes r.M^-1 r and beta from the replaced residual.
-template <int PREC>
+// partial a.b over cells (r.z for an explicit preconditioner, z.q for the
+// flexible-CG beta).
+template <int V>
 __global__ void __launch_bounds__(kBlock)
-    k_pcg_check(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
-                const double* __restrict__ x, float* __restrict__ r, double tol2,
-                double* partials, unsigned* counter, double* scal, int* flags) {
-  if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
+    k_dot_cells(int n, const float* __restrict__ a, const float* __restrict__ b,
+                const int* __restrict__ flags, double* partials) {
+  if (flags && flags[F_DONE]) return;
+  const int64_t G = cells(n) / V;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
+  const Run run = group_run(G, gridDim.x, lb);
+  double v[1] = {0.0};
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
+    float av[V], bv[V];
+    ldf<V>(a + g * V, av);
+    ldf<V>(b + g * V, bv);
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[0] += (double)av[e] * (double)bv[e];
+  }
+  store_partials<1>(v, partials, lb);
+}
+
+// r = b - A x in FP64 from the FP64 iterate (residual replacement);
+// partials |r|^2 and (Jacobi) r.M^-1 r.
+template <int V, int PREC>
+__global__ void __launch_bounds__(kBlock)
+    k_check(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
+            const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
+            double* partials) {
+  if (flags[F_DONE]) return;
+  const int64_t G = cells(n) / V;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const Run run = group_run(G, gridDim.x, lb);
+  const int64_t sy = n, sz = (int64_t)n * n;
+  const int lane = threadIdx.x & (kWave - 1);
   Walker w;
-  w.init(Dims{n, n, n}, ch.begin + threadIdx.x, kBlock);
+  walk_init<V>(w, n, run.begin + threadIdx.x);
   double v[2] = {0.0, 0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
-    const uint8_t dg = cdiag[idx];
-    if (!dg) continue;
-    const double rc = (double)b[idx] - poisson_row<double>(x, idx, dg, w, n);
-    const float rf = (float)rc;
-    r[idx] = rf;
-    v[0] += rc * rc;
-    if (PREC == PK_JACOBI) v[1] += (double)rf * (double)rf * c_inv_count[dg];
-  }
-  double tot[2];
-  if (finish_sums<2>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    scal[S_RR] = tot[0];
-    if (PREC == PK_JACOBI) {
-      scal[S_RZ] = tot[1];
-      scal[S_BETA] = scal[S_RZ_PREV] > 0.0 ? tot[1] / scal[S_RZ_PREV] : 0.0;
+  for (int t = 0; t < run.trips; ++t, w.next()) {
+    const int64_t g = run.begin + threadIdx.x + (int64_t)t * kBlock;
+    const bool act = g < run.end;
+    const int64_t idx = g * V;
+    const int i = w.i * V;
+    double xc[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) xc[e] = 0.0;
+    if (act) ldd<V>(x + idx, xc);
+    double left = __shfl_up(xc[V - 1], 1, kWave);
+    double right = __shfl_down(xc[0], 1, kWave);
+    if (!act) continue;
+    if (i > 0 && lane == 0) left = x[idx - 1];
+    if (i + V < n && lane == kWave - 1) right = x[idx + V];
+    double s[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) s[e] = 0.0;
+    auto add = [&](int64_t m) {
+      double t4[V];
+      ldd<V>(x + m, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    };
+    if (w.j > 0) add(idx - sy);
+    if (w.j < n - 1) add(idx + sy);
+    if (w.k > 0) add(idx - sz);
+    if (w.k < n - 1) add(idx + sz);
+    if (i > 0) s[0] += left;
+    if (i + V < n) s[V - 1] += right;
+#pragma unroll
+    for (int e = 1; e < V; ++e) s[e] += xc[e - 1];
+#pragma unroll
+    for (int e = 0; e + 1 < V; ++e) s[e] += xc[e + 1];
+    float bv[V], rf[V];
+    uint8_t dg[V];
+    ldf<V>(b + idx, bv);
+    ldg<V>(cdiag + idx, dg);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const double rc = dg[e] ? (double)bv[e] - ((double)dg[e] * xc[e] - s[e]) : 0.0;
+      rf[e] = (float)rc;
+      v[0] += rc * rc;
+      if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg[e]];
     }
-    if (tot[0] <= tol2 * scal[S_BB]) {
-      flags[F_DONE] = 1;
-      flags[F_ITERS_AT_DONE] = flags[F_ITERS];
-    }
+    stf<V>(r + idx, rf);
   }
+  store_partials<2>(v, partials, lb);
 }
 
+template <int V>
 __global__ void __launch_bounds__(kBlock)
     k_poisson_apply(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ xin,
                     float* __restrict__ y) {
-  const int64_t C = cells(n);
-  const Chunk2 ch = chunk_of(C, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
+  const int64_t G = cells(n) / V;
+  const Run run = group_run(G, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
+  const int64_t sy = n, sz = (int64_t)n * n;
   Walker w;
-  w.init(Dims{n, n, n}, ch.begin + threadIdx.x, kBlock);
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
-    const uint8_t dg = cdiag[idx];
-    y[idx] = dg ? poisson_row<float>(xin, idx, dg, w, n) : 0.f;
+  walk_init<V>(w, n, run.begin + threadIdx.x);
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock, w.next()) {
+    const int64_t idx = g * V;
+    const int i = w.i * V;
+    float xc[V], s[V], out[V];
+    uint8_t dg[V];
+    ldf<V>(xin + idx, xc);
+    ldg<V>(cdiag + idx, dg);
+#pragma unroll
+    for (int e = 0; e < V; ++e) s[e] = 0.f;
+    auto add = [&](int64_t m) {
+      float t4[V];
+      ldf<V>(xin + m, t4);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s[e] += t4[e];
+    };
+    if (w.j > 0) add(idx - sy);
+    if (w.j < n - 1) add(idx + sy);
+    if (w.k > 0) add(idx - sz);
+    if (w.k < n - 1) add(idx + sz);
+    if (i > 0) s[0] += xin[idx - 1];
+    if (i + V < n) s[V - 1] += xin[idx + V];
+#pragma unroll
+    for (int e = 1; e < V; ++e) s[e] += xc[e - 1];
+#pragma unroll
+    for (int e = 0; e + 1 < V; ++e) s[e] += xc[e + 1];
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[e] = dg[e] ? (float)dg[e] * xc[e] - s[e] : 0.f;
+    stf<V>(y + idx, out);
   }
 }
 
@@ -244,8 +812,8 @@ __global__ void __launch_bounds__(kBlock)
     k_jacobi_apply(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
                    float* __restrict__ z) {
   const int64_t C = cells(n);
-  const Chunk2 ch = chunk_of(C, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock)
+  for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
+       idx += (int64_t)gridDim.x * kBlock)
     z[idx] = r[idx] * c_inv_count[cdiag[idx]];
 }
 
@@ -256,60 +824,129 @@ __global__ void __launch_bounds__(kBlock)
     o[idx] = a[idx];
 }
 
+// ----------------------------------------------------------- launchers
+
+// Launch kern<4, ...> when rows hold whole 4-cell groups, else kern<1, ...>;
+// the kernel arguments come from the ARGS macro defined at the call site.
+#define FS_CELL_LAUNCH(kern, ...)                                                       \
+  do {                                                                                  \
+    if (c->n % 4 == 0)                                                                  \
+      hipLaunchKernelGGL((kern<4, ##__VA_ARGS__>), dim3(c->grid_cells), dim3(kBlock), 0, \
+                         c->stream, ARGS);                                              \
+    else                                                                                \
+      hipLaunchKernelGGL((kern<1, ##__VA_ARGS__>), dim3(c->grid_cells), dim3(kBlock), 0, \
+                         c->stream, ARGS);                                              \
+  } while (0)
+
+static double tol_sq(double t) { return t * t; }
+
 void launch_pcg_init(sim_ctx* c, int prec) {
+#define ARGS c->n, c->cdiag, c->b, c->x, c->r, c->dA, c->partials
   if (prec == PK_JACOBI)
-    hipLaunchKernelGGL(k_pcg_init<PK_JACOBI>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->b, c->x, c->r, c->dA, c->partials, c->counter, c->scal,
-                       c->flags);
+    FS_CELL_LAUNCH(k_pcg_init, PK_JACOBI);
   else
-    hipLaunchKernelGGL(k_pcg_init<PK_ZARRAY>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->b, c->x, c->r, c->dA, c->partials, c->counter, c->scal,
-                       c->flags);
+    FS_CELL_LAUNCH(k_pcg_init, PK_ZARRAY);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 2, FIN_PCG_INIT, 0.0, prec == PK_JACOBI, 0, 0.0, 0);
+}
+
+template <bool FLEX>
+static int dir_spmv_any(sim_ctx* c, int prec, const float* d_in, float* d_out) {
+  if (c->n % 4 == 0) {
+    const ZmShape zs = zm_shape(c->n);
+    if (prec == PK_JACOBI)
+      hipLaunchKernelGGL((k_dir_spmv_zm<PK_JACOBI, FLEX>), dim3(zs.blocks), dim3(kBlock), 0,
+                         c->stream, c->n, zs.zc, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal,
+                         c->flags, c->partials);
+    else
+      hipLaunchKernelGGL((k_dir_spmv_zm<PK_ZARRAY, FLEX>), dim3(zs.blocks), dim3(kBlock), 0,
+                         c->stream, c->n, zs.zc, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal,
+                         c->flags, c->partials);
+    return zs.blocks;
+  }
+#define ARGS c->n, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal, c->flags, c->partials
+  if (prec == PK_JACOBI)
+    hipLaunchKernelGGL((k_dir_spmv<1, PK_JACOBI, FLEX>), dim3(c->grid_cells), dim3(kBlock), 0,
+                       c->stream, ARGS);
+  else
+    hipLaunchKernelGGL((k_dir_spmv<1, PK_ZARRAY, FLEX>), dim3(c->grid_cells), dim3(kBlock), 0,
+                       c->stream, ARGS);
+#undef ARGS
+  return c->grid_cells;
 }
 
 void launch_pcg_dir_spmv(sim_ctx* c, int prec, const float* d_in, float* d_out) {
-  if (prec == PK_JACOBI)
-    hipLaunchKernelGGL(k_pcg_dir_spmv<PK_JACOBI>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->partials, c->counter,
-                       c->scal, c->flags);
-  else
-    hipLaunchKernelGGL(k_pcg_dir_spmv<PK_ZARRAY>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->partials, c->counter,
-                       c->scal, c->flags);
+  prof_mark(c, SIM_KERN_PCG_DIR_SPMV, true);
+  const int nb = dir_spmv_any<false>(c, prec, d_in, d_out);
+  prof_mark(c, SIM_KERN_PCG_DIR_SPMV, false);
+  launch_finalize(c, nb, 2, FIN_DQ, 0.0, 0, 0, 0.0, 0);
 }
 
 void launch_pcg_update(sim_ctx* c, int prec, const float* d) {
-  if (prec == PK_JACOBI)
-    hipLaunchKernelGGL(k_pcg_update<PK_JACOBI>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->x, c->r, d, c->q, c->partials, c->counter, c->scal,
-                       c->flags);
+#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials
+  prof_mark(c, SIM_KERN_PCG_UPDATE, true);
+  if (prec == PK_JACOBI) {
+    FS_CELL_LAUNCH(k_update, PK_JACOBI, false);
+    prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+    launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
+  } else {
+    FS_CELL_LAUNCH(k_update, PK_ZARRAY, false);
+    prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+  }
+#undef ARGS
+}
+
+void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool with_x) {
+#define ARGS c->n, c->cdiag, c->x, c->r, d, d_prev, c->q, c->scal, c->flags, c->partials
+  prof_mark(c, SIM_KERN_PCG_UPDATE, true);
+  if (with_x)
+    FS_CELL_LAUNCH(k_update2, true);
   else
-    hipLaunchKernelGGL(k_pcg_update<PK_ZARRAY>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->x, c->r, d, c->q, c->partials, c->counter, c->scal,
-                       c->flags);
+    FS_CELL_LAUNCH(k_update2, false);
+  prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }
 
 void launch_pcg_rz_first(sim_ctx* c, int first) {
-  hipLaunchKernelGGL(k_pcg_rz, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n, c->r, c->z,
-                     first, c->partials, c->counter, c->scal, c->flags);
+#define ARGS c->n, c->r, c->z, c->flags, c->partials
+  FS_CELL_LAUNCH(k_dot_cells);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 1, first ? FIN_RZ_FIRST : FIN_RZ_UPD, 0.0, 0, 0, 0.0, 0);
 }
 
 void launch_pcg_rz(sim_ctx* c) { launch_pcg_rz_first(c, 0); }
 
 void launch_pcg_check(sim_ctx* c, int prec, double tol) {
-  if (prec == PK_JACOBI)
-    hipLaunchKernelGGL(k_pcg_check<PK_JACOBI>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->b, c->x, c->r, tol * tol, c->partials, c->counter,
-                       c->scal, c->flags);
-  else
-    hipLaunchKernelGGL(k_pcg_check<PK_ZARRAY>, dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
-                       c->n, c->cdiag, c->b, c->x, c->r, tol * tol, c->partials, c->counter,
-                       c->scal, c->flags);
+  prof_mark(c, SIM_KERN_PCG_CHECK, true);
+  int nb = c->grid_cells;
+  if (c->n % 4 == 0) {
+    const ZmShape zs = zm_shape(c->n);
+    nb = zs.blocks;
+    if (prec == PK_JACOBI)
+      hipLaunchKernelGGL((k_check_zm<PK_JACOBI>), dim3(zs.blocks), dim3(kBlock), 0, c->stream,
+                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials);
+    else
+      hipLaunchKernelGGL((k_check_zm<PK_ZARRAY>), dim3(zs.blocks), dim3(kBlock), 0, c->stream,
+                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials);
+  } else {
+#define ARGS c->n, c->cdiag, c->b, c->x, c->r, c->flags, c->partials
+    if (prec == PK_JACOBI)
+      hipLaunchKernelGGL((k_check<1, PK_JACOBI>), dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
+                         ARGS);
+    else
+      hipLaunchKernelGGL((k_check<1, PK_ZARRAY>), dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
+                         ARGS);
+#undef ARGS
+  }
+  prof_mark(c, SIM_KERN_PCG_CHECK, false);
+  launch_finalize(c, nb, 2, FIN_CHECK, tol_sq(tol), prec == PK_JACOBI, 0, 0.0, 0);
 }
 
 void launch_poisson_apply(sim_ctx* c, const float* xin, float* y) {
-  hipLaunchKernelGGL(k_poisson_apply, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n,
-                     c->cdiag, xin, y);
+#define ARGS c->n, c->cdiag, xin, y
+  FS_CELL_LAUNCH(k_poisson_apply);
+#undef ARGS
 }
 
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z) {
@@ -326,106 +963,38 @@ void launch_x_to_double(sim_ctx* c, const double* xin, double* out) {
 //   alpha = d.r / d.q ; x += alpha d ; r -= alpha q ; z = B(r) ;
 //   beta = -(z.q) / (d.q) ; d = z + beta d.
 
-__global__ void __launch_bounds__(kBlock)
-    k_fcg_dir_spmv(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
-                   const float* __restrict__ z, const float* __restrict__ d_in,
-                   float* __restrict__ d_out, float* __restrict__ q, double* partials,
-                   unsigned* counter, double* scal, int* flags) {
-  if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
-  const float beta = (float)scal[S_BETA];
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
-  const int64_t sy = n, sz = (int64_t)n * n;
-  auto dir = [&](int64_t m) -> float { return z[m] + beta * d_in[m]; };
-  Walker w;
-  w.init(Dims{n, n, n}, ch.begin + threadIdx.x, kBlock);
-  double v[2] = {0.0, 0.0};
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
-    const uint8_t dg = cdiag[idx];
-    if (!dg) {
-      d_out[idx] = 0.f;
-      q[idx] = 0.f;
-      continue;
-    }
-    const float dc = dir(idx);
-    float s = 0.f;
-    if (w.i > 0) s += dir(idx - 1);
-    if (w.i < n - 1) s += dir(idx + 1);
-    if (w.j > 0) s += dir(idx - sy);
-    if (w.j < n - 1) s += dir(idx + sy);
-    if (w.k > 0) s += dir(idx - sz);
-    if (w.k < n - 1) s += dir(idx + sz);
-    const float qc = (float)dg * dc - s;
-    d_out[idx] = dc;
-    q[idx] = qc;
-    v[0] += (double)dc * (double)qc;
-    v[1] += (double)dc * (double)r[idx];
-  }
-  double tot[2];
-  if (finish_sums<2>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    scal[S_DQ] = tot[0];
-    scal[S_DR] = tot[1];
-    if (!(tot[0] > 0.0) || !(tot[1] > 0.0)) flags[F_DONE] = 2;  // not a descent direction
-  }
+void launch_fcg_init(sim_ctx* c) {
+#define ARGS c->n, c->cdiag, c->b, c->x, c->r, c->dA, c->partials
+  FS_CELL_LAUNCH(k_pcg_init, PK_ZARRAY);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 2, FIN_PCG_INIT, 0.0, 0, 0, 0.0, 0);
 }
-
-__global__ void __launch_bounds__(kBlock)
-    k_fcg_update(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
-                 float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
-                 double* scal, int* flags) {
-  if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
-  const double alpha = scal[S_DR] / scal[S_DQ];
-  const float alpha_f = (float)alpha;
-  const Chunk2 ch = chunk_of(C, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock) {
-    if (!cdiag[idx]) continue;
-    x[idx] += alpha * (double)d[idx];
-    r[idx] -= alpha_f * q[idx];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) flags[F_ITERS] += 1;
-}
-
-// beta = -(z.q)/(d.q); first = 1 at the start of a solve (beta = 0).
-__global__ void __launch_bounds__(kBlock)
-    k_fcg_beta(int n, const float* __restrict__ z, const float* __restrict__ q, int first,
-               double* partials, unsigned* counter, double* scal, int* flags) {
-  if (flags[F_DONE]) return;
-  const int64_t C = cells(n);
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const Chunk2 ch = chunk_of(C, gridDim.x, lb);
-  double v[1] = {0.0};
-  if (!first)
-    for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock)
-      v[0] += (double)z[idx] * (double)q[idx];
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x, lb, tot) && threadIdx.x == 0) {
-    if (first) {
-      scal[S_BETA] = 0.0;
-    } else {
-      scal[S_BETA] = -tot[0] / scal[S_DQ];
-    }
-    if (!(scal[S_BETA] == scal[S_BETA])) flags[F_DONE] = 2;
-  }
-}
-
-void launch_fcg_init(sim_ctx* c) { launch_pcg_init(c, PK_ZARRAY); }
 
 void launch_fcg_dir_spmv(sim_ctx* c, const float* d_in, float* d_out) {
-  hipLaunchKernelGGL(k_fcg_dir_spmv, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n,
-                     c->cdiag, c->r, c->z, d_in, d_out, c->q, c->partials, c->counter, c->scal,
-                     c->flags);
+  prof_mark(c, SIM_KERN_PCG_DIR_SPMV, true);
+  const int nb = dir_spmv_any<true>(c, PK_ZARRAY, d_in, d_out);
+  prof_mark(c, SIM_KERN_PCG_DIR_SPMV, false);
+  launch_finalize(c, nb, 2, FIN_FCG_DQDR, 0.0, 0, 0, 0.0, 0);
 }
 
 void launch_fcg_update(sim_ctx* c, const float* d) {
-  hipLaunchKernelGGL(k_fcg_update, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n, c->cdiag,
-                     c->x, c->r, d, c->q, c->scal, c->flags);
+#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials
+  prof_mark(c, SIM_KERN_PCG_UPDATE, true);
+  FS_CELL_LAUNCH(k_update, PK_ZARRAY, true);
+  prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+#undef ARGS
 }
 
 void launch_fcg_beta_first(sim_ctx* c, int first) {
-  hipLaunchKernelGGL(k_fcg_beta, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n, c->z, c->q,
-                     first, c->partials, c->counter, c->scal, c->flags);
+  if (first) {
+    // beta = 0 for the first direction
+    launch_finalize(c, 0, 1, FIN_SLOT, 0.0, 0, S_BETA, 0.0, 0);
+    return;
+  }
+#define ARGS c->n, c->z, c->q, c->flags, c->partials
+  FS_CELL_LAUNCH(k_dot_cells);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 1, FIN_FCG_BETA, 0.0, 0, 0, 0.0, 0);
 }
 
 void launch_fcg_beta(sim_ctx* c) { launch_fcg_beta_first(c, 0); }
@@ -441,6 +1010,18 @@ void launch_fcg_check(sim_ctx* c, double tol) { launch_pcg_check(c, PK_ZARRAY, t
 // relative residual of |M| * 2^-24 ~ 4e-5.  r, d, q are FP32, dots FP64.
 // b is ctx->tmp; the FP64 iterate is ctx->fx; the result is rounded into
 // the output fields at the end.
+
+struct Chunk2 {
+  int64_t begin, end;
+};
+
+__device__ inline Chunk2 chunk_of(int64_t total, int nblocks, int lb) {
+  int64_t per = (total + nblocks - 1) / nblocks;
+  per = (per + kBlock - 1) / kBlock * kBlock;
+  int64_t b = per * lb;
+  int64_t e = b + per < total ? b + per : total;
+  return Chunk2{b, e};
+}
 
 __device__ inline float mrow_diag_inv(uint8_t code, float alpha) {
   return (code & FC_ACTIVE) ? 1.f / (1.f + alpha * (float)__popc(code & 63u)) : 0.f;
@@ -464,7 +1045,7 @@ __device__ inline T mrow(const V* __restrict__ f, int64_t idx, uint8_t code, int
 __global__ void __launch_bounds__(kBlock)
     k_dcg_init(int n, const uint8_t* __restrict__ fcode, float alpha, const float* __restrict__ b,
                double* __restrict__ x, float* __restrict__ r, float* __restrict__ d0, int64_t F,
-               double* partials, unsigned* counter, double* scal, int* flags, double tol2) {
+               double* partials) {
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
   const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
@@ -492,25 +1073,15 @@ __global__ void __launch_bounds__(kBlock)
     v[1] += (double)rf * rf * mrow_diag_inv(cd, alpha);
     v[2] += rv * rv;
   }
-  double tot[3];
-  if (finish_sums<3>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0) {
-    scal[S_BB] = tot[0];
-    scal[S_RZ] = tot[1];
-    scal[S_RZ_PREV] = tot[1];
-    scal[S_RR] = tot[2];
-    scal[S_BETA] = 0.0;
-    flags[F_DONE] = tot[2] <= tol2 * tot[0] ? 1 : 0;
-    flags[F_ITERS] = 0;
-    flags[F_ITERS_AT_DONE] = 0;
-  }
+  store_partials<3>(v, partials, comp * gridDim.x + lb);
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_dcg_dir_spmv(int n, const uint8_t* __restrict__ fcode, float alpha,
                    const float* __restrict__ r, const float* __restrict__ d_in,
-                   float* __restrict__ d_out, float* __restrict__ q, int64_t F, double* partials,
-                   unsigned* counter, double* scal, int* flags) {
+                   float* __restrict__ d_out, float* __restrict__ q, int64_t F,
+                   const double* __restrict__ scal, const int* __restrict__ flags,
+                   double* partials) {
   if (flags[F_DONE]) return;
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
@@ -545,18 +1116,14 @@ __global__ void __launch_bounds__(kBlock)
     qc[idx] = qv;
     v[0] += (double)dcur * (double)qv;
   }
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0) {
-    scal[S_DQ] = tot[0];
-    if (!(tot[0] > 0.0)) flags[F_DONE] = 2;
-  }
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_dcg_update(const uint8_t* __restrict__ fcode, float alpha, double* __restrict__ x,
                  float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
-                 int64_t F, double* partials, unsigned* counter, double* scal, int* flags) {
+                 int64_t F, const double* __restrict__ scal, const int* __restrict__ flags,
+                 double* partials) {
   if (flags[F_DONE]) return;
   const int comp = blockIdx.y;
   const double a = scal[S_RZ] / scal[S_DQ];
@@ -577,21 +1144,13 @@ __global__ void __launch_bounds__(kBlock)
     rc[idx] = rn;
     v[0] += (double)rn * (double)rn * mrow_diag_inv(cd, alpha);
   }
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0) {
-    const double rz_old = scal[S_RZ];
-    scal[S_RZ_PREV] = rz_old;
-    scal[S_RZ] = tot[0];
-    scal[S_BETA] = tot[0] / rz_old;
-    flags[F_ITERS] += 1;
-  }
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_dcg_check(int n, const uint8_t* __restrict__ fcode, float alpha, const float* __restrict__ b,
-                const double* __restrict__ x, float* __restrict__ r, int64_t F, double tol2,
-                double* partials, unsigned* counter, double* scal, int* flags) {
+                const double* __restrict__ x, float* __restrict__ r, int64_t F,
+                const int* __restrict__ flags, double* partials) {
   if (flags[F_DONE]) return;
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
@@ -612,17 +1171,7 @@ __global__ void __launch_bounds__(kBlock)
     v[0] += rv * rv;
     v[1] += (double)rf * rf * mrow_diag_inv(cd, alpha);
   }
-  double tot[2];
-  if (finish_sums<2>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0) {
-    scal[S_RR] = tot[0];
-    scal[S_RZ] = tot[1];
-    scal[S_BETA] = scal[S_RZ_PREV] > 0.0 ? tot[1] / scal[S_RZ_PREV] : 0.0;
-    if (tot[0] <= tol2 * scal[S_BB]) {
-      flags[F_DONE] = 1;
-      flags[F_ITERS_AT_DONE] = flags[F_ITERS];
-    }
-  }
+  store_partials<2>(v, partials, comp * gridDim.x + lb);
 }
 
 // out = (float) x on active faces, 0 elsewhere
@@ -639,26 +1188,31 @@ __global__ void __launch_bounds__(kBlock)
 
 void launch_dcg_init(sim_ctx* c, float alpha) {
   hipLaunchKernelGGL(k_dcg_init, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
-                     c->fcode, alpha, c->tmp, c->fx, c->fr, c->fdA, c->F, c->partials, c->counter,
-                     c->scal, c->flags, c->desc.diff_tol * c->desc.diff_tol);
+                     c->fcode, alpha, c->tmp, c->fx, c->fr, c->fdA, c->F, c->partials);
+  launch_finalize(c, 3 * c->grid_faces, 3, FIN_DCG_INIT, tol_sq(c->desc.diff_tol), 1, 0, 0.0, 0);
 }
 
 void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_out) {
+  prof_mark(c, SIM_KERN_DCG_DIR_SPMV, true);
   hipLaunchKernelGGL(k_dcg_dir_spmv, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
-                     c->fcode, alpha, c->fr, d_in, d_out, c->fq, c->F, c->partials, c->counter,
-                     c->scal, c->flags);
+                     c->fcode, alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags,
+                     c->partials);
+  prof_mark(c, SIM_KERN_DCG_DIR_SPMV, false);
+  launch_finalize(c, 3 * c->grid_faces, 1, FIN_DQ, 0.0, 0, 0, 0.0, 0);
 }
 
 void launch_dcg_update(sim_ctx* c, float alpha, const float* d) {
+  prof_mark(c, SIM_KERN_DCG_UPDATE, true);
   hipLaunchKernelGGL(k_dcg_update, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->fcode,
-                     alpha, c->fx, c->fr, d, c->fq, c->F, c->partials, c->counter, c->scal,
-                     c->flags);
+                     alpha, c->fx, c->fr, d, c->fq, c->F, c->scal, c->flags, c->partials);
+  prof_mark(c, SIM_KERN_DCG_UPDATE, false);
+  launch_finalize(c, 3 * c->grid_faces, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }
 
 void launch_dcg_check(sim_ctx* c, float alpha, double tol) {
   hipLaunchKernelGGL(k_dcg_check, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
-                     c->fcode, alpha, c->tmp, c->fx, c->fr, c->F, tol * tol, c->partials,
-                     c->counter, c->scal, c->flags);
+                     c->fcode, alpha, c->tmp, c->fx, c->fr, c->F, c->flags, c->partials);
+  launch_finalize(c, 3 * c->grid_faces, 2, FIN_CHECK, tol_sq(tol), 1, 0, 0.0, 0);
 }
 
 void launch_dcg_finish(sim_ctx* c, F3 out) {

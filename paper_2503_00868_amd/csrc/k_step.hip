@@ -189,8 +189,10 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void launch_advect(sim_ctx* c, CF3 in, F3 out, float dth, const float force[3]) {
+  prof_mark(c, SIM_KERN_ADVECT, true);
   hipLaunchKernelGGL(k_advect, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n, c->fcode,
                      in, out, dth, force[0], force[1], force[2], c->F);
+  prof_mark(c, SIM_KERN_ADVECT, false);
 }
 
 // --------------------------------------------------------------- viscosity
@@ -229,8 +231,10 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void launch_diffuse_explicit(sim_ctx* c, CF3 in, F3 out, float alpha) {
+  prof_mark(c, SIM_KERN_DIFFUSE_EXPLICIT, true);
   hipLaunchKernelGGL(k_diffuse_explicit, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
                      c->fcode, in, out, alpha, c->F);
+  prof_mark(c, SIM_KERN_DIFFUSE_EXPLICIT, false);
 }
 
 // --------------------------------------------------- Poisson right-hand side
@@ -349,7 +353,7 @@ void launch_axpy_faces(sim_ctx* c, CF3 a, F3 y, float alpha) {
 // scal[slot] = sum over faces of a*b (active faces only when masked).
 __global__ void __launch_bounds__(kBlock)
     k_dot_faces(const uint8_t* __restrict__ fcode, CF3 a, CF3 b, int masked, int64_t F,
-                double* partials, unsigned* counter, double* scal, int slot) {
+                double* partials) {
   const int comp = blockIdx.y;
   const uint8_t* __restrict__ code = fcode + comp * F;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -357,21 +361,19 @@ __global__ void __launch_bounds__(kBlock)
   double v[1] = {0.0};
   for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock)
     if (!masked || (code[idx] & FC_ACTIVE)) v[0] += (double)a.c[comp][idx] * (double)b.c[comp][idx];
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0)
-    scal[slot] = tot[0];
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
 void launch_dot_faces(sim_ctx* c, CF3 a, CF3 b, int slot, int masked) {
   hipLaunchKernelGGL(k_dot_faces, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->fcode, a,
-                     b, masked, c->F, c->partials, c->counter, c->scal, slot);
+                     b, masked, c->F, c->partials);
+  launch_finalize(c, 3 * c->grid_faces, 1, FIN_SLOT, 0.0, 0, slot, 1.0, 0);
 }
 
-// scal[slot] = <a, L y> with L the viscous Laplacian including 1/h^2.
+// scal[slot] = (accumulate ? scal[slot] : 0) + scale * <a, L y>, with L the
+// viscous Laplacian including 1/h^2.
 __global__ void __launch_bounds__(kBlock)
-    k_dot_lap(int n, const uint8_t* __restrict__ fcode, CF3 a, CF3 y, int64_t F, double* partials,
-              unsigned* counter, double* scal, int slot, double scale, int accumulate) {
+    k_dot_lap(int n, const uint8_t* __restrict__ fcode, CF3 a, CF3 y, int64_t F, double* partials) {
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
   const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
@@ -385,22 +387,20 @@ __global__ void __launch_bounds__(kBlock)
     if (cd & FC_ACTIVE) v[0] += (double)a.c[comp][idx] * (double)lap_sum(y.c[comp], idx, cd, sy, sz);
   }
   v[0] *= inv_h2;
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0)
-    scal[slot] = (accumulate ? scal[slot] : 0.0) + scale * tot[0];
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
 void launch_dot_lap(sim_ctx* c, CF3 a, CF3 y, int slot, double scale, int accumulate) {
   hipLaunchKernelGGL(k_dot_lap, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n, c->fcode,
-                     a, y, c->F, c->partials, c->counter, c->scal, slot, scale, accumulate);
+                     a, y, c->F, c->partials);
+  launch_finalize(c, 3 * c->grid_faces, 1, FIN_SLOT, 0.0, 0, slot, scale, accumulate);
 }
 
 // MSE over active faces: scal[slot] = sum (u - t)^2 (the caller divides by
 // the active-face count); g (nullable components) = 2 (u - t) / count.
 __global__ void __launch_bounds__(kBlock)
     k_loss_mse(const uint8_t* __restrict__ fcode, CF3 u, CF3 t, F3 g, float inv_count, int64_t F,
-               double* partials, unsigned* counter, double* scal, int slot) {
+               double* partials) {
   const int comp = blockIdx.y;
   const uint8_t* __restrict__ code = fcode + comp * F;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -413,16 +413,14 @@ __global__ void __launch_bounds__(kBlock)
     v[0] += (double)diff * (double)diff;
     if (gc) gc[idx] = 2.f * diff * inv_count;
   }
-  double tot[1];
-  if (finish_sums<1>(v, partials, counter, gridDim.x * gridDim.y, comp * gridDim.x + lb, tot) &&
-      threadIdx.x == 0)
-    scal[slot] = tot[0];
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
 void launch_loss_mse(sim_ctx* c, CF3 u, CF3 t, F3 g, int slot) {
   float inv = c->n_active > 0 ? 1.0f / (float)c->n_active : 0.f;
   hipLaunchKernelGGL(k_loss_mse, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->fcode, u, t,
-                     g, inv, c->F, c->partials, c->counter, c->scal, slot);
+                     g, inv, c->F, c->partials);
+  launch_finalize(c, 3 * c->grid_faces, 1, FIN_SLOT, 0.0, 0, slot, 1.0, 0);
 }
 
 // ------------------------------------------------------- advection adjoint
@@ -531,8 +529,10 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth) {
+  prof_mark(c, SIM_KERN_ADVECT_ADJOINT, true);
   hipLaunchKernelGGL(k_advect_adjoint, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
                      c->fcode, u, lam, g, dth, c->F);
+  prof_mark(c, SIM_KERN_ADVECT_ADJOINT, false);
 }
 
 }  // namespace fs

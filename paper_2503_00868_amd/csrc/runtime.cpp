@@ -20,6 +20,33 @@
 
 using namespace fs;
 
+struct Profiler {
+  static constexpr int kPairs = 1 << 15;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 per timed launch
+  std::vector<int> kind;
+  int used = 0;   // events recorded
+  int open = -1;  // index of an unmatched begin event
+  double ms[SIM_KERN_COUNT] = {};
+  int64_t launches[SIM_KERN_COUNT] = {};
+};
+
+void fs::prof_mark(sim_ctx* c, int kind, bool begin) {
+  Profiler* p = c->prof;
+  if (!p || !p->on) return;
+  if (begin) {
+    if (p->used + 2 > (int)p->ev.size()) return;
+    if (hipEventRecord(p->ev[p->used], c->stream) != hipSuccess) return;
+    p->kind[p->used / 2] = kind;
+    p->open = p->used++;
+  } else {
+    if (p->open < 0) return;
+    if (hipEventRecord(p->ev[p->used], c->stream) != hipSuccess) return;
+    p->used++;
+    p->open = -1;
+  }
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -83,7 +110,6 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   char* ctrl = cv.take<char>(kCtrlBytes);
   t->scal = reinterpret_cast<double*>(ctrl);
   t->flags = ctrl ? reinterpret_cast<int*>(ctrl + S_COUNT * sizeof(double)) : nullptr;
-  t->counter = cv.take<unsigned>(16);
   if (recording_enabled(d)) {
     t->ckpt_slots = (d.max_steps + d.checkpoint_every - 1) / d.checkpoint_every;
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
@@ -296,10 +322,19 @@ int pcg_solve(sim_ctx* c, int prec_kind, int restart, sim_stats* st) {
   float* din = c->dA;
   float* dout = c->dB;
   const double tol = c->desc.tol;
+  // Jacobi: the FP64 iterate is updated every second iteration (two
+  // directions at once), so blocks hold an even number of iterations and
+  // every check sees an up-to-date x.
+  const bool two_step = pk == PK_JACOBI;
+  const int m = two_step ? (c->desc.check_every + 1) / 2 * 2 : c->desc.check_every;
+  const int max_it = two_step ? (c->desc.max_iter + 1) / 2 * 2 : c->desc.max_iter;
   auto block = [&](int todo) {
     for (int t = 0; t < todo; ++t) {
       launch_pcg_dir_spmv(c, pk, din, dout);
-      launch_pcg_update(c, pk, dout);
+      if (two_step)
+        launch_pcg_update2(c, dout, din, (t & 1) != 0);
+      else
+        launch_pcg_update(c, pk, dout);
       if (t == todo - 1) launch_pcg_check(c, pk, tol);
       if (pk == PK_ZARRAY) {
         launch_mic0_apply(c, c->r, c->z, c->flags);
@@ -309,7 +344,7 @@ int pcg_solve(sim_ctx* c, int prec_kind, int restart, sim_stats* st) {
     }
   };
   LoopResult lr{};
-  int rc = run_blocks(c, c->desc.check_every, c->desc.max_iter, block, lr);
+  int rc = run_blocks(c, m, max_it, block, lr);
   if (rc) return rc;
   if (st) {
     st->iters += lr.iters;
@@ -500,8 +535,6 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
     return fail(SIM_ERR_HIP);
   if (hipMemcpyAsync(c->cell, h_cell_type, c->C, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return fail(SIM_ERR_HIP);
-  if (hipMemsetAsync(c->counter, 0, 16 * sizeof(unsigned), c->stream) != hipSuccess)
-    return fail(SIM_ERR_HIP);
   if (hipMemsetAsync(c->scal, 0, kCtrlBytes, c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
   launch_setup_tables(c);
   if (c->precon) {
@@ -516,8 +549,63 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   return SIM_OK;
 }
 
+int sim_profile_enable(sim_ctx* c, int32_t on) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  if (on && !c->prof) {
+    Profiler* p = new (std::nothrow) Profiler();
+    if (!p) return SIM_ERR_INVALID_ARG;
+    p->ev.resize(2 * Profiler::kPairs);
+    p->kind.resize(Profiler::kPairs);
+    for (auto& e : p->ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        c->err = "hipEventCreate failed";
+        return SIM_ERR_HIP;
+      }
+    }
+    c->prof = p;
+  }
+  if (c->prof) {
+    c->prof->on = on != 0;
+    c->prof->used = 0;
+    c->prof->open = -1;
+    for (int k = 0; k < SIM_KERN_COUNT; ++k) c->prof->ms[k] = 0.0, c->prof->launches[k] = 0;
+  }
+  return SIM_OK;
+}
+
+int sim_profile_read(sim_ctx* c, double* h_ms, int64_t* h_launches) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  if (!h_ms || !h_launches) {
+    c->err = "NULL output";
+    return SIM_ERR_INVALID_ARG;
+  }
+  Profiler* p = c->prof;
+  for (int k = 0; k < SIM_KERN_COUNT; ++k) h_ms[k] = 0.0, h_launches[k] = 0;
+  if (!p) return SIM_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int q = 0; q + 1 < p->used; q += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, p->ev[q], p->ev[q + 1]));
+    p->ms[p->kind[q / 2]] += t;
+    p->launches[p->kind[q / 2]] += 1;
+  }
+  p->used = 0;
+  p->open = -1;
+  for (int k = 0; k < SIM_KERN_COUNT; ++k) {
+    h_ms[k] = p->ms[k];
+    h_launches[k] = p->launches[k];
+    p->ms[k] = 0.0;
+    p->launches[k] = 0;
+  }
+  return SIM_OK;
+}
+
 int sim_destroy(sim_ctx* c) {
   if (!c) return SIM_ERR_INVALID_ARG;
+  if (c->prof) {
+    for (auto& e : c->prof->ev) (void)hipEventDestroy(e);
+    delete c->prof;
+  }
   net_destroy(c);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   delete c;

@@ -26,6 +26,8 @@ SIM_ERR_SINGULAR_MASK = -5
 SIM_ERR_STATE = -6
 
 SIM_PRECOND_JACOBI, SIM_PRECOND_MIC0, SIM_PRECOND_LEARNED = 0, 1, 2
+KERNEL_KINDS = ["pcg_dir_spmv", "pcg_update", "pcg_check", "advect", "diffuse_explicit",
+                "dcg_dir_spmv", "dcg_update", "mic0", "net", "advect_adjoint"]
 SIM_DIFFUSION_AUTO, SIM_DIFFUSION_EXPLICIT, SIM_DIFFUSION_IMPLICIT = 0, 1, 2
 
 PRECONDS = {"jacobi": SIM_PRECOND_JACOBI, "mic0": SIM_PRECOND_MIC0, "learned": SIM_PRECOND_LEARNED}
@@ -82,6 +84,8 @@ SIGNATURES = {
     "sim_op_poisson_apply": (c_int32, [_P, _P, _P]),
     "sim_op_precond_apply": (c_int32, [_P, c_int32, _P, _P]),
     "sim_op_advect_adjoint": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_profile_enable": (c_int32, [_P, c_int32]),
+    "sim_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
     "sim_destroy": (c_int32, [_P]),
     "sim_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -280,6 +284,17 @@ class Sim:
         self._chk(lib().sim_op_advect_adjoint(self.ctx, *map(_ptr, u), *map(_ptr, lam),
                                               *map(_ptr, out)))
         return out
+
+    # -- kernel timing
+    def profile_enable(self, on=True):
+        self._chk(lib().sim_profile_enable(self.ctx, int(on)))
+
+    def profile_read(self):
+        k = len(KERNEL_KINDS)
+        ms = (c_double * k)()
+        cnt = (c_int64 * k)()
+        self._chk(lib().sim_profile_read(self.ctx, ms, cnt))
+        return {name: (ms[q], cnt[q]) for q, name in enumerate(KERNEL_KINDS)}
 
     # -- learned preconditioner
     def net_set_weights(self, w):

@@ -214,12 +214,13 @@ def test_not_converged_reports_status(torch_gpu, orc):
     from paper_2503_00868_amd.fluidsim import SIM_ERR_NOT_CONVERGED
     n = 16
     cell, u = case(n, 10)
-    sim = _sim(cell, max_iter=3, check_every=2)
-    sim.set_params(nu=1e-3, dt=DT)
-    U = sim.to_faces(orc.mask_faces(cell, u))
-    st, _ = sim.project(U, allow=(SIM_ERR_NOT_CONVERGED,))
-    assert st["status"] == SIM_ERR_NOT_CONVERGED and st["iters"] == 3
-    assert st["rel_residual"] > 1e-6
+    for precond, want in (("jacobi", 4), ("mic0", 3)):  # Jacobi iterates in pairs
+        sim = _sim(cell, precond=precond, max_iter=3, check_every=2)
+        sim.set_params(nu=1e-3, dt=DT)
+        U = sim.to_faces(orc.mask_faces(cell, u))
+        st, _ = sim.project(U, allow=(SIM_ERR_NOT_CONVERGED,))
+        assert st["status"] == SIM_ERR_NOT_CONVERGED and st["iters"] == want, st
+        assert st["rel_residual"] > 1e-6
 
 
 def test_loss_parity(torch_gpu, orc):
