@@ -1,0 +1,121 @@
+"""Pins for the network oracle: convolution against brute-force loops, the
+autograd gradient against central FD, the loss against its geometric
+meaning, and invariances of the architecture."""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import unet
+from paper_2503_00868_amd import inputs
+
+
+def test_param_count():
+    assert unet.param_count() == 353808
+
+
+def test_conv3d_matches_brute_force_loops():
+    """The library conv used by the oracle is the cross-correlation with
+    zero padding and tap (kz, ky, kx) -> offset (kz-1, ky-1, kx-1)."""
+    rng = np.random.default_rng(0)
+    cin, cout, n = 3, 2, 4
+    x = rng.standard_normal((cin, n, n, n))
+    w = rng.standard_normal((cout, cin, 3, 3, 3))
+    y = F.conv3d(torch.tensor(x)[None], torch.tensor(w), padding=1)[0].numpy()
+    ref = np.zeros((cout, n, n, n))
+    for co in range(cout):
+        for z in range(n):
+            for yy in range(n):
+                for xx in range(n):
+                    s = 0.0
+                    for ci in range(cin):
+                        for kz in range(3):
+                            for ky in range(3):
+                                for kx in range(3):
+                                    zz, y2, x2 = z + kz - 1, yy + ky - 1, xx + kx - 1
+                                    if 0 <= zz < n and 0 <= y2 < n and 0 <= x2 < n:
+                                        s += w[co, ci, kz, ky, kx] * x[ci, zz, y2, x2]
+                    ref[co, z, yy, xx] = s
+    np.testing.assert_allclose(y, ref, atol=1e-12)
+
+
+def test_pool_and_upsample_semantics():
+    x = torch.arange(64, dtype=torch.float64).reshape(1, 1, 4, 4, 4)
+    p = F.avg_pool3d(x, 2)
+    assert p[0, 0, 0, 0, 0] == np.mean([0, 1, 4, 5, 16, 17, 20, 21])
+    u = F.interpolate(p, scale_factor=2, mode="nearest")
+    assert u[0, 0, 1, 1, 1] == p[0, 0, 0, 0, 0] and u[0, 0, 2, 3, 2] == p[0, 0, 1, 1, 1]
+
+
+def test_forward_positively_homogeneous_and_masked():
+    n = 8
+    cell = inputs.gen_mask(n, 1)
+    mask = cell == 1
+    rng = np.random.default_rng(2)
+    r = np.where(mask, rng.standard_normal((n, n, n)), 0.0)
+    w = unet.init_weights(3)
+    z1 = unet.forward(w, r, mask, emulate_bf16=False)
+    z2 = unet.forward(w, 3.7 * r, mask, emulate_bf16=False)
+    np.testing.assert_allclose(z2, 3.7 * z1, rtol=1e-12, atol=1e-15)
+    assert np.all(z1[~mask] == 0) and np.abs(z1).max() > 0
+    assert np.all(unet.forward(w, 0 * r, mask) == 0)
+
+
+def test_bf16_emulation_is_close_to_exact():
+    n = 8
+    cell = inputs.gen_mask(n, 1)
+    mask = cell == 1
+    rng = np.random.default_rng(4)
+    r = np.where(mask, rng.standard_normal((n, n, n)), 0.0)
+    w = unet.init_weights(5)
+    za = unet.forward(w, r, mask, emulate_bf16=False)
+    zb = unet.forward(w, r, mask, emulate_bf16=True)
+    assert np.linalg.norm(za - zb) / np.linalg.norm(za) < 3e-2
+
+
+def test_anorm_loss_geometry(orc):
+    """Loss is 0 for z parallel to the true error e and 1 - cos^2 in the A
+    inner product otherwise."""
+    n = 8
+    cell = inputs.gen_mask(n, 2)
+    rng = np.random.default_rng(5)
+    e = np.where(cell == 1, rng.standard_normal((n, n, n)), 0.0)
+    r = orc.poisson_apply(cell, e)
+    assert abs(unet.anorm_loss(2.5 * e, r, e, orc.poisson_apply(cell, 2.5 * e))) < 1e-12
+    z = np.where(cell == 1, rng.standard_normal((n, n, n)), 0.0)
+    Az = orc.poisson_apply(cell, z)
+    cos2 = (z * r).sum() ** 2 / ((e * r).sum() * (z * Az).sum())
+    assert abs(unet.anorm_loss(z, r, e, Az) - (1 - cos2)) < 1e-12
+    assert 0 < unet.anorm_loss(z, r, e, Az) < 1
+
+
+def test_loss_gradient_matches_fd(orc):
+    """Autograd gradient of the loss (without bf16 rounding, so the map is
+    piecewise smooth) against central FD on random weight directions."""
+    n = 8
+    cell = inputs.gen_mask(n, 3)
+    mask = cell == 1
+    rng = np.random.default_rng(6)
+    e = np.where(mask, rng.standard_normal((n, n, n)), 0.0)
+    r = orc.poisson_apply(cell, e)
+    w = unet.init_weights(7).astype(np.float64)
+    A = lambda x: orc.poisson_apply(cell, x)
+
+    def loss_exact(wv):
+        z = unet.forward(wv, r, mask, emulate_bf16=False)
+        return unet.anorm_loss(z, r, e, A(z))
+
+    # gradient without rounding: reuse loss_and_grad's graph with rounding off
+    import oracle.unet as U
+    saved = U.bf16
+    U.bf16 = lambda t: t
+    try:
+        L, g, _ = U.loss_and_grad(w, r, e, mask, A)
+    finally:
+        U.bf16 = saved
+    assert abs(L - loss_exact(w)) < 1e-12
+    for _ in range(3):
+        d = rng.standard_normal(w.size)
+        h = 1e-7  # small: larger steps cross ReLU kinks of the piecewise-linear net
+        fd = (loss_exact(w + h * d) - loss_exact(w - h * d)) / (2 * h)
+        assert abs(fd - g @ d) < 1e-5 * max(1.0, abs(fd)), (fd, g @ d)
