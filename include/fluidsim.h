@@ -162,11 +162,20 @@ int sim_net_param_count(int64_t* count);
 int sim_net_set_weights(sim_ctx* ctx, const float* d_weights, int64_t count);
 int sim_net_forward(sim_ctx* ctx, const float* d_r, float* d_z);
 
-/* One Adam step of the U-Net on a batch of (r, e) pairs, e = A^-1 r (cell
- * arrays, batch-major): loss 1 - (r.z)^2 / ((r.e)(z.Az)) averaged over the
- * batch (A-norm angle between the correction z = net(r) and the true error).
- * d_master: float32 weights (updated), d_adam: 2*count float32 moments,
- * step: 1-based Adam step.  h_loss receives the batch loss before the update. */
+/* Loss and weight gradient of the U-Net with its current weights on a batch
+ * of (r, e) pairs, e = A^-1 r (cell arrays, batch-major, zero off liquid):
+ * loss = mean over the batch of 1 - (r.z)^2 / ((r.e)(z.Az)), the squared sine
+ * of the A-norm angle between z = net(r) and the true error e.  d_grad
+ * receives dloss/dweights (float32 blob, sim_net_param_count entries) with
+ * the bf16 rounding of weights and activations treated as the identity. */
+int sim_net_grad(sim_ctx* ctx, const float* d_r, const float* d_e, int32_t batch, float* d_grad,
+                 double* h_loss);
+
+/* One Adam step (beta 0.9/0.999, eps 1e-8) of the U-Net on a batch of pairs
+ * (as sim_net_grad).  d_master: float32 weights (updated in place, then used
+ * by the preconditioner), d_adam: 2*count float32 moments (zero before the
+ * first step), step: 1-based Adam step.  h_loss receives the batch loss
+ * before the update. */
 int sim_net_train_step(sim_ctx* ctx, const float* d_r, const float* d_e, int32_t batch,
                        float* d_master, float* d_adam, int32_t step, float lr, double* h_loss);
 

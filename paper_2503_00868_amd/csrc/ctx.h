@@ -25,6 +25,11 @@ enum ScalarSlot {
   S_DOT1,
   S_DOT2,
   S_ALPHA_PREV,  // alpha of the previous iteration (two-step iterate update)
+  S_NET_SUMSQ,   // learned preconditioner: |r|^2 of its input
+  S_NET_RMS,     //   rms of r over liquid cells
+  S_NET_RZ,      //   training: r.z, r.e, z.Az (contiguous)
+  S_NET_RE,
+  S_NET_ZAZ,
   S_COUNT = 32
 };
 enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };

@@ -24,6 +24,7 @@
 // shuffle; y and z neighbours are vector loads served mostly by L2.
 #include "common.h"
 #include "ctx.h"
+#include "net.h"
 
 namespace fs {
 
@@ -916,6 +917,14 @@ void launch_pcg_rz_first(sim_ctx* c, int first) {
 }
 
 void launch_pcg_rz(sim_ctx* c) { launch_pcg_rz_first(c, 0); }
+
+void launch_dot_cells_slot(sim_ctx* c, const float* a, const float* b, int slot,
+                           const int* flags) {
+#define ARGS c->n, a, b, flags, c->partials
+  FS_CELL_LAUNCH(k_dot_cells);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 1, FIN_SLOT, 0.0, 0, slot, 1.0, 0);
+}
 
 void launch_pcg_check(sim_ctx* c, int prec, double tol) {
   prof_mark(c, SIM_KERN_PCG_CHECK, true);

@@ -1,40 +1,379 @@
-// Placeholder until the U-Net kernels land: the learned preconditioner
-// reports itself unavailable, so LEARNED contexts solve with MIC(0).
+// Learned preconditioner: workspace layout, weight packing, the U-Net forward
+// pass used inside flexible CG, and one batched training step (forward,
+// A-norm loss, backward, Adam) on (residual, error) pairs.
+//
+// Architecture (a reading of the paper's learned pressure solver, Section
+// 3.4.1, used here as a preconditioner):
+//   x0 = (r/rms(r), mask) -> c1 2->16 -> c2 16->16 = e1          (level 1, n^3)
+//   pool -> c3 16->32 -> c4 32->32 = e2                          (level 2)
+//   pool -> c5 32->64 -> c6 64->64 = e3                          (level 3)
+//   cat(up e3, e2) -> c7 96->32 -> c8 32->32 = d2                (level 2)
+//   cat(up d2, e1) -> c9 48->16 -> c10 16->16 = d1               (level 1)
+//   c11 16->1 -> o ; z = mask * rms * o
+// ReLU after every convolution except c11; all convolutions 3x3x3, bias free.
 #include "net.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "common.h"
 
 namespace fs {
 
-size_t net_workspace_bytes(int) { return 256; }
-int net_init(sim_ctx*) { return SIM_OK; }
-void net_destroy(sim_ctx*) {}
-bool net_ready(const sim_ctx*) { return false; }
-int net_apply(sim_ctx* c, const float*, float*, const int*) {
-  c->err = "learned preconditioner not available";
-  return SIM_ERR_STATE;
+struct Layer {
+  int cin, cout;   // real channel counts
+  int cin_p;       // forward input channels as stored (multiple of 8)
+  int cout_p;      // forward output channels as computed (multiple of 16)
+  int cout_pd;     // data-gradient input channels (multiple of 8)
+};
+
+static const Layer kLayers[11] = {
+    {2, 16, 8, 16, 16},   {16, 16, 16, 16, 16}, {16, 32, 16, 32, 32}, {32, 32, 32, 32, 32},
+    {32, 64, 32, 64, 64}, {64, 64, 64, 64, 64}, {96, 32, 96, 32, 32}, {32, 32, 32, 32, 32},
+    {48, 16, 48, 16, 16}, {16, 16, 16, 16, 16}, {16, 1, 16, 16, 8},
+};
+
+static int64_t param_offset(int l) {
+  int64_t o = 0;
+  for (int q = 0; q < l; ++q) o += 27LL * kLayers[q].cin * kLayers[q].cout;
+  return o;
+}
+
+static int64_t param_total() { return param_offset(11); }
+
+}  // namespace fs
+
+struct UNetState {
+  int n1, n2, n3;
+  // activations (bf16, channels-last)
+  __bf16 *X0, *A1, *E1, *B1, *D1, *P1, *A2, *E2, *B2, *D2, *P2, *A3, *E3;
+  // gradients
+  __bf16 *G11, *L1a, *L1b, *L1T, *L2a, *L2b, *L2T, *L2c, *L3a, *L3b, *L3c;
+  // weights: forward and data-gradient layouts
+  __bf16* wf[11];
+  __bf16* wd[11];
+  float* dW;
+  float* zbuf;
+  float* Az;
+  bool ready = false;
+};
+
+namespace fs {
+
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t o = off;
+    off = (off + count * sizeof(T) + 255) / 256 * 256;
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+size_t carve_net(int n, char* base, UNetState* s) {
+  Carve cv{base};
+  UNetState dummy;
+  UNetState* t = s ? s : &dummy;
+  const int64_t V1 = (int64_t)n * n * n, V2 = V1 / 8, V3 = V1 / 64;
+  t->n1 = n;
+  t->n2 = n / 2;
+  t->n3 = n / 4;
+  t->X0 = cv.take<__bf16>(V1 * 8);
+  t->A1 = cv.take<__bf16>(V1 * 16);
+  t->E1 = cv.take<__bf16>(V1 * 16);
+  t->B1 = cv.take<__bf16>(V1 * 16);
+  t->D1 = cv.take<__bf16>(V1 * 16);
+  t->P1 = cv.take<__bf16>(V2 * 16);
+  t->A2 = cv.take<__bf16>(V2 * 32);
+  t->E2 = cv.take<__bf16>(V2 * 32);
+  t->B2 = cv.take<__bf16>(V2 * 32);
+  t->D2 = cv.take<__bf16>(V2 * 32);
+  t->P2 = cv.take<__bf16>(V3 * 32);
+  t->A3 = cv.take<__bf16>(V3 * 64);
+  t->E3 = cv.take<__bf16>(V3 * 64);
+  t->G11 = cv.take<__bf16>(V1 * 8);
+  t->L1a = cv.take<__bf16>(V1 * 16);
+  t->L1b = cv.take<__bf16>(V1 * 16);
+  t->L1T = cv.take<__bf16>(V1 * 48);
+  t->L2a = cv.take<__bf16>(V2 * 32);
+  t->L2b = cv.take<__bf16>(V2 * 32);
+  t->L2T = cv.take<__bf16>(V2 * 96);
+  t->L2c = cv.take<__bf16>(V2 * 16);
+  t->L3a = cv.take<__bf16>(V3 * 64);
+  t->L3b = cv.take<__bf16>(V3 * 64);
+  t->L3c = cv.take<__bf16>(V3 * 32);
+  for (int l = 0; l < 11; ++l) {
+    const Layer& L = kLayers[l];
+    t->wf[l] = cv.take<__bf16>((size_t)L.cout_p * 28 * L.cin_p);
+    t->wd[l] = cv.take<__bf16>((size_t)L.cin * 28 * L.cout_pd);
+  }
+  t->dW = cv.take<float>(param_total());
+  t->zbuf = cv.take<float>(V1);
+  t->Az = cv.take<float>(V1);
+  return cv.off;
+}
+
+NetSrc src1(const __bf16* a, int ca) { return NetSrc{a, nullptr, ca, 0, 0}; }
+NetSrc srcup(const __bf16* coarse, int cc, const __bf16* skip, int cs) {
+  return NetSrc{coarse, skip, cc, cs, 1};
+}
+NetOut out_bf(__bf16* p) { return NetOut{p, nullptr, nullptr, nullptr, nullptr}; }
+NetOut out_mask(__bf16* p, const __bf16* relu_of) { return NetOut{p, nullptr, nullptr, nullptr, relu_of}; }
+
+int conv(sim_ctx* c, int n, int l, int epi, NetSrc src, NetOut out, const int* flags) {
+  const Layer& L = kLayers[l];
+  if (!net_conv(c, n, L.cin_p, L.cout_p, epi, src, c->net->wf[l], out, flags)) {
+    c->err = "no convolution kernel for this channel configuration";
+    return SIM_ERR_INVALID_ARG;
+  }
+  return SIM_OK;
+}
+
+int dgrad(sim_ctx* c, int n, int l, int epi, const __bf16* G, NetOut out) {
+  const Layer& L = kLayers[l];
+  if (!net_conv(c, n, L.cout_pd, L.cin, epi, src1(G, L.cout_pd), c->net->wd[l], out, nullptr)) {
+    c->err = "no data-gradient kernel for this channel configuration";
+    return SIM_ERR_INVALID_ARG;
+  }
+  return SIM_OK;
+}
+
+void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, float* dW) {
+  const Layer& L = kLayers[l];
+  net_wgrad(c, n, src, L.cin, L.cin_p, G, g_stride, L.cout, dW + param_offset(l));
+}
+
+// U-Net forward pass into z (fp32, n^3); activations stay in the workspace.
+int forward(sim_ctx* c, const float* r, float* z, const int* flags) {
+  UNetState* s = c->net;
+  const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
+  launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
+  net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
+  int rc = SIM_OK;
+  rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
+  rc |= conv(c, n1, 1, NET_EPI_RELU, src1(s->A1, 16), out_bf(s->E1), flags);
+  net_pool(c, n1, 16, s->E1, s->P1, flags);
+  rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2), flags);
+  rc |= conv(c, n2, 3, NET_EPI_RELU, src1(s->A2, 32), out_bf(s->E2), flags);
+  net_pool(c, n2, 32, s->E2, s->P2, flags);
+  rc |= conv(c, n3, 4, NET_EPI_RELU, src1(s->P2, 32), out_bf(s->A3), flags);
+  rc |= conv(c, n3, 5, NET_EPI_RELU, src1(s->A3, 64), out_bf(s->E3), flags);
+  rc |= conv(c, n2, 6, NET_EPI_RELU, srcup(s->E3, 64, s->E2, 32), out_bf(s->B2), flags);
+  rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32), out_bf(s->D2), flags);
+  rc |= conv(c, n1, 8, NET_EPI_RELU, srcup(s->D2, 32, s->E1, 16), out_bf(s->B1), flags);
+  rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1), flags);
+  NetOut o{nullptr, z, c->cdiag, c->scal + S_NET_RMS, nullptr};
+  rc |= conv(c, n1, 10, NET_EPI_OUT, src1(s->D1, 16), o, flags);
+  return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
+}
+
+// Gradient of the loss of one pair with respect to every weight, added to dW.
+int backward(sim_ctx* c) {
+  UNetState* s = c->net;
+  const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
+  float* dW = s->dW;
+  int rc = SIM_OK;
+  // output convolution
+  wgrad(c, n1, 10, src1(s->D1, 16), s->G11, 8, dW);
+  rc |= dgrad(c, n1, 10, NET_EPI_MASKGRAD, s->G11, out_mask(s->L1a, s->D1));   // G10
+  wgrad(c, n1, 9, src1(s->B1, 16), s->L1a, 16, dW);
+  rc |= dgrad(c, n1, 9, NET_EPI_MASKGRAD, s->L1a, out_mask(s->L1b, s->B1));    // G9
+  wgrad(c, n1, 8, srcup(s->D2, 32, s->E1, 16), s->L1b, 16, dW);
+  rc |= dgrad(c, n1, 8, NET_EPI_RAW, s->L1b, out_bf(s->L1T));                  // T48
+  net_upsum_mask(c, n1, 32, 48, s->L1T, s->D2, s->L2a);                        // G8
+  wgrad(c, n2, 7, src1(s->B2, 32), s->L2a, 32, dW);
+  rc |= dgrad(c, n2, 7, NET_EPI_MASKGRAD, s->L2a, out_mask(s->L2b, s->B2));    // G7
+  wgrad(c, n2, 6, srcup(s->E3, 64, s->E2, 32), s->L2b, 32, dW);
+  rc |= dgrad(c, n2, 6, NET_EPI_RAW, s->L2b, out_bf(s->L2T));                  // T96
+  net_upsum_mask(c, n2, 64, 96, s->L2T, s->E3, s->L3a);                        // G6
+  wgrad(c, n3, 5, src1(s->A3, 64), s->L3a, 64, dW);
+  rc |= dgrad(c, n3, 5, NET_EPI_MASKGRAD, s->L3a, out_mask(s->L3b, s->A3));    // G5
+  wgrad(c, n3, 4, src1(s->P2, 32), s->L3b, 64, dW);
+  rc |= dgrad(c, n3, 4, NET_EPI_RAW, s->L3b, out_bf(s->L3c));                  // grad P2
+  net_skip_grad(c, n2, 32, s->L2T, 96, 64, s->L3c, s->E2, s->L2a);             // G4
+  wgrad(c, n2, 3, src1(s->A2, 32), s->L2a, 32, dW);
+  rc |= dgrad(c, n2, 3, NET_EPI_MASKGRAD, s->L2a, out_mask(s->L2b, s->A2));    // G3
+  wgrad(c, n2, 2, src1(s->P1, 16), s->L2b, 32, dW);
+  rc |= dgrad(c, n2, 2, NET_EPI_RAW, s->L2b, out_bf(s->L2c));                  // grad P1
+  net_skip_grad(c, n1, 16, s->L1T, 48, 32, s->L2c, s->E1, s->L1a);             // G2
+  wgrad(c, n1, 1, src1(s->A1, 16), s->L1a, 16, dW);
+  rc |= dgrad(c, n1, 1, NET_EPI_MASKGRAD, s->L1a, out_mask(s->L1b, s->A1));    // G1
+  wgrad(c, n1, 0, src1(s->X0, 8), s->L1b, 16, dW);
+  return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
+}
+
+void pack_all(sim_ctx* c, const float* master) {
+  for (int l = 0; l < 11; ++l) {
+    const Layer& L = kLayers[l];
+    net_pack_weights(c, master + param_offset(l), L.cin, L.cout, L.cin_p, L.cout_p, L.cout_pd,
+                     c->net->wf[l], c->net->wd[l]);
+  }
+}
+
+}  // namespace
+
+size_t net_workspace_bytes(int n) { return carve_net(n, nullptr, nullptr); }
+
+int net_init(sim_ctx* c) {
+  UNetState* s = new (std::nothrow) UNetState();
+  if (!s) return SIM_ERR_INVALID_ARG;
+  carve_net(c->n, reinterpret_cast<char*>(c->net_ws), s);
+  c->net = s;
+  return SIM_OK;
+}
+
+void net_destroy(sim_ctx* c) {
+  delete c->net;
+  c->net = nullptr;
+}
+
+bool net_ready(const sim_ctx* c) { return c->net && c->net->ready; }
+
+int net_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
+  prof_mark(c, SIM_KERN_NET, true);
+  int rc = forward(c, r, z, flags);
+  prof_mark(c, SIM_KERN_NET, false);
+  return rc;
 }
 
 }  // namespace fs
 
+using namespace fs;
+
 extern "C" {
+
 int sim_net_param_count(int64_t* count) {
   if (!count) return SIM_ERR_INVALID_ARG;
-  *count = 353808;
+  *count = param_total();
   return SIM_OK;
 }
-int sim_net_set_weights(sim_ctx* c, const float*, int64_t) {
+
+int sim_net_set_weights(sim_ctx* c, const float* w, int64_t count) {
   if (!c) return SIM_ERR_INVALID_ARG;
-  c->err = "learned preconditioner not available";
-  return SIM_ERR_STATE;
+  if (!c->net) {
+    c->err = "context was not created with the learned preconditioner";
+    return SIM_ERR_STATE;
+  }
+  if (!w || count != param_total()) {
+    c->err = "weights must be a device float32 blob of sim_net_param_count entries";
+    return SIM_ERR_INVALID_ARG;
+  }
+  pack_all(c, w);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "weight packing launch failed";
+    return SIM_ERR_HIP;
+  }
+  c->net->ready = true;
+  return SIM_OK;
 }
-int sim_net_forward(sim_ctx* c, const float*, float*) {
+
+int sim_net_forward(sim_ctx* c, const float* r, float* z) {
   if (!c) return SIM_ERR_INVALID_ARG;
-  c->err = "learned preconditioner not available";
-  return SIM_ERR_STATE;
+  if (!net_ready(c)) {
+    c->err = "learned preconditioner has no weights";
+    return SIM_ERR_STATE;
+  }
+  if (!r || !z) {
+    c->err = "NULL pointer";
+    return SIM_ERR_INVALID_ARG;
+  }
+  int rc = net_apply(c, r, z, nullptr);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? SIM_OK : SIM_ERR_HIP;
 }
-int sim_net_train_step(sim_ctx* c, const float*, const float*, int32_t, float*, float*, int32_t,
-                       float, double*) {
+
+// Loss and gradient (added into s->dW after zeroing it) of a batch.
+static int batch_grad(sim_ctx* c, const float* r, const float* e, int batch, double* loss_out) {
+  UNetState* s = c->net;
+  const int64_t P = param_total();
+  if (hipMemsetAsync(s->dW, 0, sizeof(float) * P, c->stream) != hipSuccess) return SIM_ERR_HIP;
+  double loss_sum = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    const float* rb = r + (int64_t)b * c->C;
+    const float* eb = e + (int64_t)b * c->C;
+    int rc = forward(c, rb, s->zbuf, nullptr);
+    if (rc) return rc;
+    launch_poisson_apply(c, s->zbuf, s->Az);
+    launch_dot_cells_slot(c, rb, s->zbuf, S_NET_RZ, nullptr);
+    launch_dot_cells_slot(c, rb, eb, S_NET_RE, nullptr);
+    launch_dot_cells_slot(c, s->zbuf, s->Az, S_NET_ZAZ, nullptr);
+    net_loss_grad(c, rb, s->Az, c->scal + S_NET_RZ, c->scal + S_NET_RMS, s->G11);
+    rc = backward(c);
+    if (rc) return rc;
+    double d[3];
+    if (hipMemcpyAsync(d, c->scal + S_NET_RZ, sizeof d, hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      c->err = "device error in the training step";
+      return SIM_ERR_HIP;
+    }
+    loss_sum += 1.0 - d[0] * d[0] / (d[1] * d[2]);
+  }
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "training launch failed";
+    return SIM_ERR_HIP;
+  }
+  *loss_out = loss_sum / batch;
+  return SIM_OK;
+}
+
+static int check_train_args(sim_ctx* c, const float* r, const float* e, int32_t batch,
+                            const double* h_loss) {
+  if (!c->net) {
+    c->err = "context was not created with the learned preconditioner";
+    return SIM_ERR_STATE;
+  }
+  if (!r || !e || !h_loss || batch < 1) {
+    c->err = "invalid training arguments";
+    return SIM_ERR_INVALID_ARG;
+  }
+  return SIM_OK;
+}
+
+int sim_net_grad(sim_ctx* c, const float* r, const float* e, int32_t batch, float* grad,
+                 double* h_loss) {
   if (!c) return SIM_ERR_INVALID_ARG;
-  c->err = "learned preconditioner not available";
-  return SIM_ERR_STATE;
+  int rc = check_train_args(c, r, e, batch, h_loss);
+  if (rc) return rc;
+  if (!grad) {
+    c->err = "NULL gradient output";
+    return SIM_ERR_INVALID_ARG;
+  }
+  if (!net_ready(c)) {
+    c->err = "learned preconditioner has no weights";
+    return SIM_ERR_STATE;
+  }
+  rc = batch_grad(c, r, e, batch, h_loss);
+  if (rc) return rc;
+  const int64_t P = param_total();
+  launch_scale_copy(c, c->net->dW, grad, P, 1.f / (float)batch);
+  return hipGetLastError() == hipSuccess ? SIM_OK : SIM_ERR_HIP;
 }
+
+int sim_net_train_step(sim_ctx* c, const float* r, const float* e, int32_t batch, float* master,
+                       float* adam, int32_t step, float lr, double* h_loss) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  int rc = check_train_args(c, r, e, batch, h_loss);
+  if (rc) return rc;
+  if (!master || !adam || step < 1 || !(lr > 0.f)) {
+    c->err = "invalid optimiser arguments";
+    return SIM_ERR_INVALID_ARG;
+  }
+  UNetState* s = c->net;
+  const int64_t P = param_total();
+  pack_all(c, master);
+  s->ready = true;
+  rc = batch_grad(c, r, e, batch, h_loss);
+  if (rc) return rc;
+  net_adam(c, P, master, adam, adam + P, s->dW, 1.f / (float)batch, lr, step);
+  pack_all(c, master);
+  return hipGetLastError() == hipSuccess ? SIM_OK : SIM_ERR_HIP;
 }
+
+}  // extern "C"

@@ -1,4 +1,5 @@
-// Learned preconditioner (3-level 3-D U-Net) used inside flexible CG.
+// Learned preconditioner (3-level 3-D U-Net) used inside flexible CG, and the
+// launchers of its kernels (k_unet.hip).
 #pragma once
 
 #include <stddef.h>
@@ -7,6 +8,24 @@
 
 namespace fs {
 
+// Input of a convolution: channels [0, ca) from a (nearest-upsampled from the
+// half-resolution level when up != 0), channels [ca, ca+cb) from b.
+struct NetSrc {
+  const __bf16* a;
+  const __bf16* b;
+  int ca, cb, up;
+};
+
+enum NetEpi { NET_EPI_RELU = 0, NET_EPI_RAW = 1, NET_EPI_MASKGRAD = 2, NET_EPI_OUT = 3 };
+
+struct NetOut {
+  __bf16* bf;               // bf16 output [voxel][c_out] (RELU, RAW, MASKGRAD)
+  float* f32;               // OUT: z = mask * rms * o
+  const uint8_t* mask;      // OUT: liquid where non-zero
+  const double* rms;        // OUT: device scalar
+  const __bf16* relu_of;    // MASKGRAD: post-activation whose ReLU the gradient passes
+};
+
 size_t net_workspace_bytes(int n);
 int net_init(sim_ctx* c);
 void net_destroy(sim_ctx* c);
@@ -14,5 +33,31 @@ bool net_ready(const sim_ctx* c);
 // z = mask * rms(r) * U(r / rms(r), mask); returns at once when flags (nullable)
 // has the done flag raised.
 int net_apply(sim_ctx* c, const float* r, float* z, const int* flags);
+
+// kernel launchers
+int conv_tiles(int n);
+bool net_conv(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const __bf16* w,
+              NetOut out, const int* flags);
+void net_wgrad(sim_ctx* c, int n, NetSrc src, int cin_real, int cin_pad, const __bf16* G,
+               int g_stride, int cout_real, float* dW);
+void net_pool(sim_ctx* c, int n, int C, const __bf16* in, __bf16* out, const int* flags);
+void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out, __bf16* x0,
+               const int* flags);
+void net_loss_grad(sim_ctx* c, const float* r, const float* Az, const double* dots,
+                   const double* rms, __bf16* g11);
+void net_upsum_mask(sim_ctx* c, int n_fine, int Cc, int Ct, const __bf16* T, const __bf16* P,
+                    __bf16* out);
+void net_skip_grad(sim_ctx* c, int n, int C, const __bf16* T, int Ct, int off, const __bf16* gp,
+                   const __bf16* E, __bf16* out);
+void net_pack_weights(sim_ctx* c, const float* W, int cin, int cout, int cin_p, int cout_p,
+                      int cout_pd, __bf16* wf, __bf16* wd);
+void net_adam(sim_ctx* c, int64_t count, float* W, float* m, float* v, const float* dW,
+              float inv_batch, float lr, int step);
+void launch_scale_copy(sim_ctx* c, const float* a, float* out, int64_t count, float s);
+
+// cell-domain helpers from k_pcg.hip used by the network
+// scal[slot] = a.b over cells (skipped when flags, nullable, has done raised)
+void launch_dot_cells_slot(sim_ctx* c, const float* a, const float* b, int slot,
+                           const int* flags);
 
 }  // namespace fs

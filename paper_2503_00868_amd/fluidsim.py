@@ -76,6 +76,7 @@ SIGNATURES = {
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
     "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
     "sim_net_forward": (c_int32, [_P, _P, _P]),
+    "sim_net_grad": (c_int32, [_P, _P, _P, c_int32, _P, POINTER(c_double)]),
     "sim_net_train_step": (c_int32, [_P, _P, _P, c_int32, _P, _P, c_int32, c_float,
                                      POINTER(c_double)]),
     "sim_op_advect": (c_int32, [_P, _P, _P, _P, _P, _P, _P]),
@@ -304,6 +305,11 @@ class Sim:
         z = z if z is not None else self.cells_tensor()
         self._chk(lib().sim_net_forward(self.ctx, _ptr(r), _ptr(z)))
         return z
+
+    def net_grad(self, r, e, batch, grad):
+        loss = c_double()
+        self._chk(lib().sim_net_grad(self.ctx, _ptr(r), _ptr(e), batch, _ptr(grad), byref(loss)))
+        return loss.value
 
     def net_train_step(self, r, e, batch, master, adam, step, lr):
         loss = c_double()

@@ -1,0 +1,165 @@
+"""GPU parity of the learned preconditioner: the U-Net forward pass and its
+weight gradient (MFMA bf16 kernels through the C ABI) against the fp64 oracle
+with bf16 emulation, the Adam step against its closed form, and flexible CG
+with the network inside (including the MIC(0) fallback).
+
+Tolerances: bf16 has 8 mantissa bits (relative step 2^-8 = 3.9e-3); the
+oracle rounds at the same points, so the two differ only where fp32 and fp64
+accumulation round an activation to different bf16 neighbours.  The forward
+output is compared at 1e-2 relative L2; gradients, whose intermediate
+tensors the GPU also stores in bf16, at 3e-2 relative L2 and a cosine above
+0.999.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as oracle_unet
+from paper_2503_00868_amd import inputs
+from paper_2503_00868_amd import unet as net_weights
+from tests.gpu_util import banner, case, f32, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+DT = 1.0 / 120
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _sim(cell, **kw):
+    from paper_2503_00868_amd.fluidsim import Sim
+    return Sim(cell, precond="learned", **kw)
+
+
+def test_param_count_matches_oracle():
+    assert net_weights.param_count() == oracle_unet.param_count()
+
+
+@pytest.mark.parametrize("n,seed", [(16, 0), (20, 1), (32, 2)])
+def test_net_forward_parity(torch_gpu, n, seed):
+    torch = torch_gpu
+    banner(f"unet forward n={n}")
+    cell = inputs.gen_mask(n, seed)
+    mask = cell == 1
+    rng = np.random.default_rng(seed)
+    r = np.where(mask, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    w = net_weights.init_weights(seed)
+    sim = _sim(cell)
+    sim.net_set_weights(torch.as_tensor(w, device="cuda"))
+    z = sim.net_forward(sim.cells_tensor(r)).cpu().numpy().astype(np.float64)
+    zr = oracle_unet.forward(w, r.astype(np.float64), mask, emulate_bf16=True)
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    assert err < 1e-2, err
+    assert np.all(z[~mask] == 0)
+    # positive homogeneity survives the bf16 pipeline up to rounding
+    z2 = sim.net_forward(sim.cells_tensor(4.0 * r)).cpu().numpy()
+    assert np.linalg.norm(z2 - 4.0 * z) / np.linalg.norm(4.0 * z) < 1e-5
+
+
+def test_net_zero_input(torch_gpu):
+    torch = torch_gpu
+    n = 16
+    cell = inputs.gen_mask(n, 0)
+    sim = _sim(cell)
+    sim.net_set_weights(torch.as_tensor(net_weights.init_weights(1), device="cuda"))
+    z = sim.net_forward(sim.cells_tensor(np.zeros((n, n, n), np.float32)))
+    assert float(z.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n,batch", [(16, 1), (16, 2)])
+def test_net_grad_parity(torch_gpu, orc, n, batch):
+    torch = torch_gpu
+    banner(f"unet grad n={n} batch={batch}")
+    cell = inputs.gen_mask(n, 3)
+    mask = cell == 1
+    rng = np.random.default_rng(7)
+    es, rs = [], []
+    for _ in range(batch):
+        e = np.where(mask, rng.standard_normal((n, n, n)), 0.0)
+        es.append(e.astype(np.float32))
+        rs.append(orc.poisson_apply(cell, e).astype(np.float32))
+    w = net_weights.init_weights(5)
+    sim = _sim(cell)
+    sim.net_set_weights(torch.as_tensor(w, device="cuda"))
+    R = torch.as_tensor(np.stack(rs), device="cuda")
+    E = torch.as_tensor(np.stack(es), device="cuda")
+    G = torch.zeros(w.size, dtype=torch.float32, device="cuda")
+    loss = sim.net_grad(R, E, batch, G)
+    A = lambda x: orc.poisson_apply(cell, x)
+    ref_l, ref_g = 0.0, np.zeros(w.size)
+    for b in range(batch):
+        l, g, _ = oracle_unet.loss_and_grad(w, rs[b].astype(np.float64), es[b].astype(np.float64),
+                                            mask, A)
+        ref_l += l / batch
+        ref_g += g / batch
+    g = G.cpu().numpy().astype(np.float64)
+    assert abs(loss - ref_l) < 1e-2 * abs(ref_l), (loss, ref_l)
+    err = np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)
+    cos = g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g))
+    banner(f"  loss {loss:.6f} vs {ref_l:.6f}; grad rel err {err:.2e} cos {cos:.6f}")
+    assert err < 3e-2 and cos > 0.999, (err, cos)
+    # per-layer: every convolution receives a gradient of the right size
+    off = 0
+    for cin, cout in net_weights.CONVS:
+        m = 27 * cin * cout
+        gl, rl = g[off:off + m], ref_g[off:off + m]
+        assert np.linalg.norm(gl - rl) <= 0.1 * np.linalg.norm(rl) + 1e-12
+        off += m
+
+
+def test_adam_step_closed_form(torch_gpu, orc):
+    torch = torch_gpu
+    n = 16
+    cell = inputs.gen_mask(n, 4)
+    mask = cell == 1
+    rng = np.random.default_rng(9)
+    e = np.where(mask, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    r = orc.poisson_apply(cell, e.astype(np.float64)).astype(np.float32)
+    w = net_weights.init_weights(6)
+    sim = _sim(cell)
+    R = torch.as_tensor(r[None], device="cuda")
+    E = torch.as_tensor(e[None], device="cuda")
+    master = torch.as_tensor(w.copy(), device="cuda")
+    sim.net_set_weights(master)
+    G = torch.zeros(w.size, dtype=torch.float32, device="cuda")
+    sim.net_grad(R, E, 1, G)
+    adam = torch.zeros(2 * w.size, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    sim.net_train_step(R, E, 1, master, adam, 1, lr)
+    g = G.cpu().numpy().astype(np.float64)
+    # first Adam step: m_hat = g, v_hat = g^2 -> w - lr g / (|g| + eps)
+    expect = w - lr * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(master.cpu().numpy(), expect, rtol=0, atol=2e-6)
+
+
+def test_fcg_with_untrained_net_falls_back_and_converges(torch_gpu, orc):
+    """With random weights the flexible CG may stall; the MIC(0) restart from
+    its iterate must still deliver the 1e-6 projection."""
+    torch = torch_gpu
+    from paper_2503_00868_amd.fluidsim import SIM_OK, SIM_OK_FALLBACK
+    banner("fcg fallback n=24")
+    n = 24
+    cell, u = case(n, 8)
+    u = orc.add_force(cell, orc.mask_faces(cell, u), DT)
+    sim = _sim(cell, learned_max_iter=6, check_every=2)
+    sim.net_set_weights(torch.as_tensor(net_weights.init_weights(2), device="cuda"))
+    U = sim.to_faces(u)
+    st, _ = sim.project(U)
+    assert st["rel_residual"] <= 1e-6
+    assert st["status"] in (SIM_OK, SIM_OK_FALLBACK)
+    ref, _, _, _ = orc.project(cell, u, 1e-12)
+    l2, mx = rel_err(to_np(U), ref)
+    assert mx < 1e-5, (l2, mx)
+
+
+def test_learned_context_without_weights_uses_mic0(torch_gpu, orc):
+    n = 16
+    cell, u = case(n, 9)
+    u = orc.add_force(cell, orc.mask_faces(cell, u), DT)
+    sim = _sim(cell)
+    U = sim.to_faces(u)
+    st, _ = sim.project(U)
+    assert st["rel_residual"] <= 1e-6 and st["fallback_used"] == 0
