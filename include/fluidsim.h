@@ -171,6 +171,21 @@ int sim_net_forward(sim_ctx* ctx, const float* d_r, float* d_z);
 int sim_net_grad(sim_ctx* ctx, const float* d_r, const float* d_e, int32_t batch, float* d_grad,
                  double* h_loss);
 
+/* Training pairs for the network, taken from the projection the way the
+ * paper fits its learned solver on pressure before and after an implicit
+ * solve (Section 3.4.1).  For the projection of (u, v, w) (not modified),
+ * iterate A x = b and at each requested iteration k (strictly increasing,
+ * h_iters[count]; even for mode 0) record the true residual
+ * r_k = b - A x_k and the error e_k = x* - x_k into d_r_out[j], d_e_out[j]
+ * (count x n^3 float32 each), x* from a Jacobi-PCG solve to tol.
+ * mode 0: the iterates of Jacobi-PCG itself; mode 1: the iterates of the
+ * flexible CG with the current network (its own residuals, for on-policy
+ * training; needs weights).  h_stats->fallback_used = 1 reports that the
+ * flexible CG broke down, so pairs from later iterations are not its iterates. */
+int sim_harvest_pairs(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                      const int32_t* h_iters, int32_t count, int32_t mode, double tol,
+                      float* d_r_out, float* d_e_out, sim_stats* h_stats);
+
 /* One Adam step (beta 0.9/0.999, eps 1e-8) of the U-Net on a batch of pairs
  * (as sim_net_grad).  d_master: float32 weights (updated in place, then used
  * by the preconditioner), d_adam: 2*count float32 moments (zero before the

@@ -160,6 +160,8 @@ void launch_pcg_check(sim_ctx* c, int prec, double tol);
 void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
 void launch_x_to_double(sim_ctx* c, const double* x, double* out);
+// out = (float) x (err = 0) or (float)(x - out) (err = 1), over cells
+void launch_x_snapshot(sim_ctx* c, float* out, int err);
 
 // flexible CG pieces (learned preconditioner)
 void launch_fcg_init(sim_ctx* c);

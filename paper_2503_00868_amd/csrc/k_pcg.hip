@@ -156,10 +156,12 @@ __global__ void __launch_bounds__(kBlock)
       }
       break;
     case FIN_FCG_DQDR:
+      // d.r may have either sign (the step alpha = d.r / d.q takes it); only
+      // a direction with no positive curvature, or a NaN, is a breakdown
       scal[S_DQ] = v[0];
       scal[S_DR] = v[1];
       flags[F_ITERS] += 1;
-      if (!(v[0] > 0.0) || !(v[1] > 0.0)) flags[F_DONE] = 2;  // not a descent direction
+      if (!(v[0] > 0.0) || !(v[1] == v[1])) flags[F_DONE] = 2;
       break;
     case FIN_FCG_BETA:
       scal[S_BETA] = -v[0] / scal[S_DQ];
@@ -816,6 +818,18 @@ __global__ void __launch_bounds__(kBlock)
   for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
        idx += (int64_t)gridDim.x * kBlock)
     z[idx] = r[idx] * c_inv_count[cdiag[idx]];
+}
+
+// out = (float) x, or out = (float)(x - (double) out) when err != 0.
+__global__ void __launch_bounds__(kBlock)
+    k_x_snapshot(int64_t C, const double* __restrict__ x, float* __restrict__ out, int err) {
+  for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
+       idx += (int64_t)gridDim.x * kBlock)
+    out[idx] = err ? (float)(x[idx] - (double)out[idx]) : (float)x[idx];
+}
+
+void launch_x_snapshot(sim_ctx* c, float* out, int err) {
+  hipLaunchKernelGGL(k_x_snapshot, dim3(2048), dim3(kBlock), 0, c->stream, c->C, c->x, out, err);
 }
 
 __global__ void __launch_bounds__(kBlock)

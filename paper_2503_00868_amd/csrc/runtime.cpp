@@ -849,6 +849,105 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
   return worst;
 }
 
+int sim_harvest_pairs(sim_ctx* c, const float* u, const float* v, const float* w,
+                      const int32_t* iters, int32_t count, int32_t mode, double tol, float* r_out,
+                      float* e_out, sim_stats* stats) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  if (!u || !v || !w || !iters || count < 1 || !r_out || !e_out || !(tol > 0.0 && tol < 1.0) ||
+      (mode != 0 && mode != 1)) {
+    c->err = "invalid harvest arguments";
+    return SIM_ERR_INVALID_ARG;
+  }
+  for (int j = 0; j < count; ++j)
+    if (iters[j] < 0 || (mode == 0 && iters[j] % 2) || (j && iters[j] <= iters[j - 1])) {
+      c->err = "harvest iterations must be strictly increasing (and even for Jacobi-PCG)";
+      return SIM_ERR_INVALID_ARG;
+    }
+  if (mode == 1 && !net_ready(c)) {
+    c->err = "learned preconditioner has no weights";
+    return SIM_ERR_STATE;
+  }
+  auto snap = [&](int j) -> int {
+    // r = b - A x_k (replaced; for Jacobi-PCG also r.z and beta); tol 0: never "done"
+    launch_pcg_check(c, mode == 0 ? PK_JACOBI : PK_ZARRAY, 0.0);
+    HIPCHK(hipMemcpyAsync(r_out + (int64_t)j * c->C, c->r, sizeof(float) * c->C,
+                          hipMemcpyDeviceToDevice, c->stream));
+    launch_x_snapshot(c, e_out + (int64_t)j * c->C, 0);
+    return SIM_OK;
+  };
+  launch_divergence(c, cf3(u, v, w), c->b);
+  float* din = c->dA;
+  float* dout = c->dB;
+  int done_it = 0;
+  bool fcg_broke = false;
+  if (mode == 0) {
+    launch_pcg_init(c, PK_JACOBI);
+    for (int j = 0; j < count; ++j) {
+      for (int t = 0; done_it < iters[j]; ++t, ++done_it) {
+        launch_pcg_dir_spmv(c, PK_JACOBI, din, dout);
+        launch_pcg_update2(c, dout, din, (t & 1) != 0);
+        std::swap(din, dout);
+      }
+      if (snap(j)) return SIM_ERR_HIP;
+    }
+  } else {
+    launch_fcg_init(c);
+    int j = 0;
+    if (iters[0] == 0 && snap(j++)) return SIM_ERR_HIP;
+    int rc = net_apply(c, c->r, c->z, c->flags);
+    if (rc) return rc;
+    launch_fcg_beta_first(c, 1);
+    while (j < count) {
+      launch_fcg_dir_spmv(c, din, dout);
+      launch_fcg_update(c, dout);
+      ++done_it;
+      if (done_it == iters[j] && snap(j++)) return SIM_ERR_HIP;
+      rc = net_apply(c, c->r, c->z, c->flags);
+      if (rc) return rc;
+      launch_fcg_beta(c);
+      std::swap(din, dout);
+    }
+    // did the flexible CG break down (later pairs would not be its iterates)?
+    int fl[F_COUNT];
+    HIPCHK(hipMemcpyAsync(fl, c->flags, sizeof fl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    fcg_broke = fl[F_DONE] == 2;
+    // reference solution: Jacobi-PCG from scratch
+    launch_pcg_init(c, PK_JACOBI);
+    din = c->dA;
+    dout = c->dB;
+  }
+  // finish (mode 0) or solve (mode 1) to tol with Jacobi-PCG
+  const double tol_keep = c->desc.tol;
+  c->desc.tol = tol;
+  auto block = [&](int todo) {
+    for (int t = 0; t < todo; ++t) {
+      launch_pcg_dir_spmv(c, PK_JACOBI, din, dout);
+      launch_pcg_update2(c, dout, din, (t & 1) != 0);
+      if (t == todo - 1) launch_pcg_check(c, PK_JACOBI, tol);
+      std::swap(din, dout);
+    }
+  };
+  LoopResult lr{};
+  const int m = (c->desc.check_every + 1) / 2 * 2;
+  const int max_it = (c->desc.max_iter + 1) / 2 * 2;
+  int rc = run_blocks(c, m, max_it, block, lr);
+  c->desc.tol = tol_keep;
+  if (rc) return rc;
+  for (int j = 0; j < count; ++j) launch_x_snapshot(c, e_out + (int64_t)j * c->C, 1);
+  rc = launch_status(c);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (stats) {
+    stats->iters = lr.iters + (mode == 0 ? done_it : 0);
+    stats->rel_residual = relres_of(lr);
+    stats->fallback_used = fcg_broke ? 1 : 0;
+    stats->status = lr.status;
+  }
+  if (lr.status != SIM_OK) c->err = "harvest solve did not reach tol within max_iter";
+  return lr.status;
+}
+
 // ---------------------------------------------------------- single operators
 
 int sim_op_advect(sim_ctx* c, const float* u, const float* v, const float* w, float* au, float* av,

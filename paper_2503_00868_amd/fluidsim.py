@@ -76,6 +76,8 @@ SIGNATURES = {
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
     "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
     "sim_net_forward": (c_int32, [_P, _P, _P]),
+    "sim_harvest_pairs": (c_int32, [_P, _P, _P, _P, POINTER(c_int32), c_int32, c_int32, c_double,
+                                    _P, _P, POINTER(sim_stats)]),
     "sim_net_grad": (c_int32, [_P, _P, _P, c_int32, _P, POINTER(c_double)]),
     "sim_net_train_step": (c_int32, [_P, _P, _P, c_int32, _P, _P, c_int32, c_float,
                                      POINTER(c_double)]),
@@ -285,6 +287,18 @@ class Sim:
         self._chk(lib().sim_op_advect_adjoint(self.ctx, *map(_ptr, u), *map(_ptr, lam),
                                               *map(_ptr, out)))
         return out
+
+    def harvest_pairs(self, u, iters, tol=1e-10, r_out=None, e_out=None, mode=0):
+        t = self.torch
+        k = len(iters)
+        shape = (k,) + (self.n,) * 3
+        r_out = r_out if r_out is not None else t.zeros(shape, dtype=t.float32, device=self.device)
+        e_out = e_out if e_out is not None else t.zeros(shape, dtype=t.float32, device=self.device)
+        arr = (c_int32 * k)(*iters)
+        st = sim_stats()
+        self._chk(lib().sim_harvest_pairs(self.ctx, *map(_ptr, u), arr, k, mode, tol,
+                                          _ptr(r_out), _ptr(e_out), byref(st)))
+        return r_out, e_out, st.as_dict()
 
     # -- kernel timing
     def profile_enable(self, on=True):

@@ -163,3 +163,24 @@ def test_learned_context_without_weights_uses_mic0(torch_gpu, orc):
     U = sim.to_faces(u)
     st, _ = sim.project(U)
     assert st["rel_residual"] <= 1e-6 and st["fallback_used"] == 0
+
+
+def test_harvest_pairs_consistent(torch_gpu, orc):
+    """r_0 = b, A e_k = r_k, and e_0 = x* (the exact solve) for harvested pairs."""
+    from paper_2503_00868_amd.fluidsim import Sim
+    banner("harvest n=24")
+    n = 24
+    cell, u = case(n, 10)
+    u = orc.add_force(cell, orc.mask_faces(cell, u), DT)
+    sim = Sim(cell)
+    R, E, st = sim.harvest_pairs(sim.to_faces(u), [0, 4, 10], tol=1e-10, mode=0)
+    R = R.cpu().numpy().astype(np.float64)
+    E = E.cpu().numpy().astype(np.float64)
+    b = orc.divergence_rhs(cell, u)
+    np.testing.assert_allclose(R[0], b, rtol=0, atol=1e-6 * np.abs(b).max())
+    for j in range(3):
+        Ae = orc.poisson_apply(cell, E[j])
+        assert np.linalg.norm(Ae - R[j]) <= 1e-4 * np.linalg.norm(R[j]), j
+    x_ref, _, _ = orc.pcg(cell, b, orc.PRECOND_NONE, 1e-12)
+    assert np.linalg.norm(E[0] - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+    assert np.linalg.norm(R[2]) < np.linalg.norm(R[0])
