@@ -7,7 +7,9 @@ gravity (0,-9.8,0), dt = 1/120): u0 = s * mask(ugen), `--rollout` steps of
 advection + viscosity + pressure projection to a 1e-6 FP64 relative
 residual (recorded, checkpoint every 16 steps), the MSE loss against a
 target rollout, and the full checkpointed reverse pass (adjoint projection
-solves included).  Inputs are resident in HBM before timing starts.
+solves included).  Each solve starts from the previous step's pressure
+(--cold: from zero); the stopping test is the same.  Inputs are resident in
+HBM before timing starts.
 
 value = cell-steps/s = n^3 * rollout / (seconds per bench step).
 
@@ -67,10 +69,50 @@ def parse():
     p.add_argument("--weights", default=os.path.join(ROOT, "paper_2503_00868_amd", "weights",
                                                      "unet.safetensors"))
     p.add_argument("--seed", type=int, default=4)
+    p.add_argument("--cold", action="store_true",
+                   help="start every pressure solve of the rollout at zero (default: from the "
+                        "previous step's pressure)")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-n", type=int, default=128)
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
+                        "byte counters) and exit")
     return p.parse_args()
+
+
+def copy_probe(mib):
+    """Twenty device-to-device copies of `mib` MiB with torch's copy kernel:
+    the reference for scaling FETCH_SIZE / WRITE_SIZE counter readings."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: 20 copies of {mib} MiB")
+
+
+def load_traffic(kind, n):
+    """HBM bytes per launch of `kind` at n^3 from the committed counter
+    summary, or None when there is none or the kernel source changed since
+    the counters were taken (the summary stores the source's SHA-256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kind}_{n}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("bench-traffic:"):
+                rec = json.loads(line.split(":", 1)[1])
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(n, seed):
@@ -99,6 +141,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import numpy as np
     import torch
 
@@ -132,7 +177,7 @@ def main():
         f"eval nu={nu_e:.3e} s={s_e:.3f}")
 
     sim = Sim(cell, precond=precond, tol=1e-6, diff_tol=1e-6, max_iter=20000, check_every=8,
-              checkpoint_every=K, max_steps=T, device=dev)
+              checkpoint_every=K, max_steps=T, warm_start=not args.cold, device=dev)
     if weights is not None:
         sim.net_set_weights(weights)
     ugen = sim.to_faces(ug)
@@ -144,11 +189,13 @@ def main():
     sim.init_state(ugen, target)
     sim.step(target, T)
     torch.cuda.synchronize()
+    log("target rollout done")
 
     def bench_step(rollout):
         sim.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
         sim.init_state(ugen, u)
         st = sim.step(u, rollout, record=True)
+        log(f"forward rollout of {rollout} steps done")  # progress line (host only)
         J, gT = sim.loss_mse(u, target)
         _, dnu, ds, bst = sim.backward(gT, ugen=ugen)
         return st, bst, J, dnu, ds
@@ -156,6 +203,7 @@ def main():
     for _ in range(args.warmup):
         bench_step(args.warmup_rollout)
     torch.cuda.synchronize()
+    log("warmup done")
 
     sim.profile_enable(True)
     torch.cuda.synchronize()
@@ -191,7 +239,7 @@ def main():
     achieved = per_launch / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_us": round(avg_s * 1e6, 2), "launches": launches,
+                "traffic": load_traffic(dom, n), "avg_us": round(avg_s * 1e6, 2), "launches": launches,
                 "bytes_per_launch": per_launch}
     log("kernel time in the timed region (ms, launches): " +
         ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items() if v[1]))
@@ -244,9 +292,10 @@ def main():
         "data": "synthetic (seeded slab + ellipsoids mask, curl-of-potential velocity)",
         "config": {"workload": f"differentiable rollout {n}^3 x {T} steps, forward + "
                                f"checkpointed adjoint (K={K}), {precond} pressure "
-                               f"preconditioner, tol 1e-6",
+                               f"preconditioner, {'cold' if args.cold else 'warm'}-started "
+                               f"solves, tol 1e-6",
                    "n": n, "rollout": T, "checkpoint_every": K, "precond": precond,
-                   "seed": args.seed, "nu": nu_e, "s": s_e},
+                   "seed": args.seed, "nu": nu_e, "s": s_e, "warm_start": not args.cold},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "compare": compare,

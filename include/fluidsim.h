@@ -80,6 +80,10 @@ typedef struct {
     int32_t learned_max_iter;  /* flexible-CG iterations before the MIC(0) restart */
     double tol;                /* relative L2 true residual of the pressure solve, (0, 1) */
     double diff_tol;           /* same for the implicit viscosity solve, (0, 1) */
+    int32_t warm_start;        /* 1: each pressure solve of a rollout starts from the previous
+                                  step's pressure, each adjoint solve of sim_backward from the
+                                  previous adjoint solve's (the stopping test, relative to the
+                                  right-hand side, is unchanged); 0: every solve starts at 0 */
 } sim_desc;
 
 /* Dynamic parameters (sim_set_params).  Density is 1: the solver works with
@@ -214,7 +218,8 @@ int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, cons
  * the kernels below (the finalize reductions are not included); durations
  * accumulate per kind until read.  sim_profile_read synchronises the
  * stream, writes SIM_KERN_COUNT totals in milliseconds and launch counts,
- * and resets them.  At most 1<<15 launches are timed between reads. */
+ * and resets them.  Every 1<<15 timed launches the library waits for the
+ * stream once to fold the recorded events into the totals. */
 enum {
     SIM_KERN_PCG_DIR_SPMV = 0,  /* d = M^-1 r + beta d ; q = A d ; d.q            */
     SIM_KERN_PCG_UPDATE,        /* x += alpha d ; r -= alpha q ; r.M^-1 r          */

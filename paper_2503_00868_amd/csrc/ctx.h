@@ -90,6 +90,8 @@ struct sim_ctx {
   float* rprev = nullptr;   // flexible CG
   float* precon = nullptr;  // MIC(0) factor
   float* mq = nullptr;      // MIC(0) forward-sweep result
+  double* xw = nullptr;     // warm start: pressure of the previous rollout step
+  double* xwa = nullptr;    // warm start: previous adjoint pressure
 
   // face-domain buffers, each 3F stacked
   float* tmp = nullptr;  // advection output / diffusion right-hand side
@@ -108,6 +110,7 @@ struct sim_ctx {
 
   // rollout recording
   float* ckpt = nullptr;  // (ckpt_slots) x 3F
+  double* ckpt_x = nullptr;  // warm start: (ckpt_slots) x C pressures at the checkpoints
   int ckpt_slots = 0;
   float* seg = nullptr;  // (2 * checkpoint_every) x 3F: state and diffusion operand per step
   int rec_steps = 0;
@@ -159,7 +162,8 @@ void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);
 void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
-void launch_x_to_double(sim_ctx* c, const double* x, double* out);
+// out = x over the cells; skipped when flags (nullable) has the done flag raised
+void launch_x_to_double(sim_ctx* c, const double* x, double* out, const int* flags = nullptr);
 // out = (float) x (err = 0) or (float)(x - out) (err = 1), over cells
 void launch_x_snapshot(sim_ctx* c, float* out, int err);
 

@@ -833,7 +833,9 @@ void launch_x_snapshot(sim_ctx* c, float* out, int err) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_copy_double(int64_t C, const double* __restrict__ a, double* __restrict__ o) {
+    k_copy_double(int64_t C, const double* __restrict__ a, double* __restrict__ o,
+                  const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
   for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
        idx += (int64_t)gridDim.x * kBlock)
     o[idx] = a[idx];
@@ -977,8 +979,9 @@ void launch_jacobi_apply(sim_ctx* c, const float* r, float* z) {
                      c->cdiag, r, z);
 }
 
-void launch_x_to_double(sim_ctx* c, const double* xin, double* out) {
-  hipLaunchKernelGGL(k_copy_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, xin, out);
+void launch_x_to_double(sim_ctx* c, const double* xin, double* out, const int* flags) {
+  hipLaunchKernelGGL(k_copy_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, xin, out,
+                     flags);
 }
 
 // ---------------------------------------------------------- flexible CG

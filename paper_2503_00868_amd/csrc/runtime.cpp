@@ -31,11 +31,29 @@ struct Profiler {
   int64_t launches[SIM_KERN_COUNT] = {};
 };
 
+// Folds the recorded event pairs into the per-kind totals and frees the
+// events for reuse (waits for the last recorded event).
+static hipError_t prof_drain(Profiler* p) {
+  int pairs = p->used / 2;
+  if (pairs == 0) return hipSuccess;
+  hipError_t e = hipEventSynchronize(p->ev[2 * pairs - 1]);
+  if (e != hipSuccess) return e;
+  for (int q = 0; q < pairs; ++q) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, p->ev[2 * q], p->ev[2 * q + 1]);
+    if (e != hipSuccess) return e;
+    p->ms[p->kind[q]] += t;
+    p->launches[p->kind[q]] += 1;
+  }
+  p->used = 0;
+  return hipSuccess;
+}
+
 void fs::prof_mark(sim_ctx* c, int kind, bool begin) {
   Profiler* p = c->prof;
   if (!p || !p->on) return;
   if (begin) {
-    if (p->used + 2 > (int)p->ev.size()) return;
+    if (p->used + 2 > (int)p->ev.size() && prof_drain(p) != hipSuccess) return;
     if (hipEventRecord(p->ev[p->used], c->stream) != hipSuccess) return;
     p->kind[p->used / 2] = kind;
     p->open = p->used++;
@@ -97,6 +115,8 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->precon = mic ? cv.take<float>(C) : nullptr;
   t->mq = mic ? cv.take<float>(C) : nullptr;
   t->rprev = d.precond == SIM_PRECOND_LEARNED ? cv.take<float>(C) : nullptr;
+  t->xw = d.warm_start ? cv.take<double>(C) : nullptr;
+  t->xwa = d.warm_start ? cv.take<double>(C) : nullptr;
   t->tmp = cv.take<float>(F3n);
   t->fx = cv.take<double>(F3n);
   t->fr = cv.take<float>(F3n);
@@ -113,10 +133,12 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   if (recording_enabled(d)) {
     t->ckpt_slots = (d.max_steps + d.checkpoint_every - 1) / d.checkpoint_every;
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
+    t->ckpt_x = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
     t->seg = cv.take<float>((size_t)2 * d.checkpoint_every * F3n);
   } else {
     t->ckpt_slots = 0;
     t->ckpt = nullptr;
+    t->ckpt_x = nullptr;
     t->seg = nullptr;
   }
   if (d.precond == SIM_PRECOND_LEARNED) {
@@ -147,6 +169,7 @@ const char* validate_desc(const sim_desc* d) {
     return "learned_max_iter must be >= 1";
   if (!(d->tol > 0.0 && d->tol < 1.0)) return "tol must be in (0, 1)";
   if (!(d->diff_tol > 0.0 && d->diff_tol < 1.0)) return "diff_tol must be in (0, 1)";
+  if (d->warm_start != 0 && d->warm_start != 1) return "warm_start must be 0 or 1";
   return nullptr;
 }
 
@@ -303,17 +326,30 @@ int run_blocks(sim_ctx* c, int m, int max_iter, Block block, LoopResult& res) {
 
 double relres_of(const LoopResult& r) { return r.bb > 0 ? std::sqrt(r.rr / r.bb) : 0.0; }
 
+// Starting iterate of a solve.
+enum Start { START_ZERO, START_GUESS, START_CURRENT };
+
+// x = x0 (FP64 copy) after the zero-start setup, then r = b - A x through the
+// FP64 check (tolerance 0: it only stops when r is exactly zero).  With b = 0
+// the setup has already raised the done flag and x stays 0.
+void start_from_guess(sim_ctx* c, int prec_kind, const double* x0) {
+  launch_x_to_double(c, x0, c->x, c->flags);
+  launch_pcg_check(c, prec_kind, 0.0);
+}
+
 // PCG on the Poisson matrix with rhs c->b, result in c->x.  Jacobi is fused
-// into the CG kernels; MIC(0) is applied between them.  x0 = 0, or the
-// current c->x when restart != 0.
-int pcg_solve(sim_ctx* c, int prec_kind, int restart, sim_stats* st) {
+// into the CG kernels; MIC(0) is applied between them.  The iterate starts at
+// 0, at x0 (START_GUESS), or at the current c->x (START_CURRENT, a restart
+// that keeps the scale ||b|| of the interrupted solve).
+int pcg_solve(sim_ctx* c, int prec_kind, int start, const double* x0, sim_stats* st) {
   const int pk = prec_kind;
-  if (!restart) {
-    launch_pcg_init(c, pk);
-  } else {
+  if (start == START_CURRENT) {
     // restart from the current x: r = b - A x, fresh direction
     launch_pcg_check(c, pk, 0.0);
     HIPCHK(hipMemsetAsync(c->dA, 0, sizeof(float) * c->C, c->stream));
+  } else {
+    launch_pcg_init(c, pk);
+    if (start == START_GUESS) start_from_guess(c, pk, x0);
   }
   if (pk == PK_ZARRAY) {
     launch_mic0_apply(c, c->r, c->z, c->flags);
@@ -360,8 +396,9 @@ int pcg_solve(sim_ctx* c, int prec_kind, int restart, sim_stats* st) {
 
 // Flexible CG with the learned preconditioner; on breakdown or after
 // learned_max_iter iterations it restarts MIC(0)-PCG from the current x.
-int fcg_solve(sim_ctx* c, sim_stats* st) {
+int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   launch_fcg_init(c);
+  if (x0) start_from_guess(c, PK_ZARRAY, x0);
   int rc = net_apply(c, c->r, c->z, c->flags);
   if (rc) return rc;
   launch_fcg_beta_first(c, 1);
@@ -393,14 +430,16 @@ int fcg_solve(sim_ctx* c, sim_stats* st) {
   // fallback: MIC(0)-PCG from the current iterate, judged by the same FP64 check
   if (st) st->fallback_used = 1;
   HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int) * F_COUNT, c->stream));
-  rc = pcg_solve(c, PK_ZARRAY, 1, st);
+  rc = pcg_solve(c, PK_ZARRAY, START_CURRENT, nullptr, st);
   if (rc == SIM_OK) return SIM_OK_FALLBACK;
   return rc;
 }
 
-int poisson_solve(sim_ctx* c, sim_stats* st) {
-  if (c->desc.precond == SIM_PRECOND_LEARNED && net_ready(c)) return fcg_solve(c, st);
-  return pcg_solve(c, c->desc.precond == SIM_PRECOND_JACOBI ? PK_JACOBI : PK_ZARRAY, 0, st);
+// x0 (nullable): starting iterate.
+int poisson_solve(sim_ctx* c, const double* x0, sim_stats* st) {
+  if (c->desc.precond == SIM_PRECOND_LEARNED && net_ready(c)) return fcg_solve(c, x0, st);
+  return pcg_solve(c, c->desc.precond == SIM_PRECOND_JACOBI ? PK_JACOBI : PK_ZARRAY,
+                   x0 ? START_GUESS : START_ZERO, x0, st);
 }
 
 bool diffusion_explicit(sim_ctx* c) {
@@ -453,13 +492,15 @@ int diffuse_into(sim_ctx* c, F3 out, sim_stats* st) {
 }
 
 // Pressure projection of (u, v, w) in place; non-active faces are zeroed
-// first (the adjoint state can carry values there).
-int project_inplace(sim_ctx* c, F3 u, sim_stats* st) {
+// first (the adjoint state can carry values there).  warm (nullable): the
+// solve starts from it and the new pressure is stored back into it.
+int project_inplace(sim_ctx* c, F3 u, sim_stats* st, double* warm = nullptr) {
   CF3 cu = cf3(u.c[0], u.c[1], u.c[2]);
   launch_mask_scale(c, cu, u, 1.0f);
   launch_divergence(c, cu, c->b);
-  int rc = poisson_solve(c, st);
+  int rc = poisson_solve(c, warm, st);
   if (rc != SIM_OK && rc != SIM_OK_FALLBACK) return rc;
+  if (warm) launch_x_to_double(c, c->x, warm);
   launch_pressure_update(c, c->x, u);
   int lr = launch_status(c);
   return lr ? lr : rc;
@@ -478,7 +519,7 @@ int step_once(sim_ctx* c, F3 u, sim_stats* st) {
   advect_force(c, cf3(u.c[0], u.c[1], u.c[2]), stacked(c, c->tmp));
   int rc = diffuse_into(c, u, st);
   if (rc) return rc;
-  return project_inplace(c, u, st);
+  return project_inplace(c, u, st, c->xw);
 }
 
 int combine(int a, int b) {
@@ -536,6 +577,9 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   if (hipMemcpyAsync(c->cell, h_cell_type, c->C, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return fail(SIM_ERR_HIP);
   if (hipMemsetAsync(c->scal, 0, kCtrlBytes, c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
+  for (double* wbuf : {c->xw, c->xwa})
+    if (wbuf && hipMemsetAsync(wbuf, 0, sizeof(double) * c->C, c->stream) != hipSuccess)
+      return fail(SIM_ERR_HIP);
   launch_setup_tables(c);
   if (c->precon) {
     if (hipMemsetAsync(c->precon, 0, sizeof(float) * c->C, c->stream) != hipSuccess)
@@ -583,13 +627,8 @@ int sim_profile_read(sim_ctx* c, double* h_ms, int64_t* h_launches) {
   for (int k = 0; k < SIM_KERN_COUNT; ++k) h_ms[k] = 0.0, h_launches[k] = 0;
   if (!p) return SIM_OK;
   HIPCHK(hipStreamSynchronize(c->stream));
-  for (int q = 0; q + 1 < p->used; q += 2) {
-    float t = 0.f;
-    HIPCHK(hipEventElapsedTime(&t, p->ev[q], p->ev[q + 1]));
-    p->ms[p->kind[q / 2]] += t;
-    p->launches[p->kind[q / 2]] += 1;
-  }
-  p->used = 0;
+  if (p->open >= 0) p->used = p->open;  // drop an unmatched begin
+  HIPCHK(prof_drain(p));
   p->open = -1;
   for (int k = 0; k < SIM_KERN_COUNT; ++k) {
     h_ms[k] = p->ms[k];
@@ -657,6 +696,7 @@ int sim_init_state(sim_ctx* c, const float* gu, const float* gv, const float* gw
     return SIM_ERR_STATE;
   }
   launch_mask_scale(c, cf3(gu, gv, gw), f3(u, v, w), (float)c->params.s);
+  if (c->xw) HIPCHK(hipMemsetAsync(c->xw, 0, sizeof(double) * c->C, c->stream));
   return launch_status(c);
 }
 
@@ -684,8 +724,10 @@ int sim_step(sim_ctx* c, float* u, float* v, float* w, int32_t nsteps, int32_t r
   const int64_t F3n = 3 * c->F;
   int worst = SIM_OK;
   for (int s = 0; s < nsteps; ++s) {
-    if (record && s % K == 0)
+    if (record && s % K == 0) {
       launch_copy_faces(c, cf3(u, v, w), stacked(c, c->ckpt + (int64_t)(s / K) * F3n));
+      if (c->ckpt_x) launch_x_to_double(c, c->xw, c->ckpt_x + (int64_t)(s / K) * c->C);
+    }
     sim_stats st{};
     int rc = step_once(c, U, &st);
     st.status = rc;
@@ -770,11 +812,14 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
   int worst = SIM_OK;
   launch_copy_faces(c, cf3(gu, gv, gw), lam);
   HIPCHK(hipMemsetAsync(c->scal + S_DOT1, 0, sizeof(double), c->stream));
+  if (c->xwa) HIPCHK(hipMemsetAsync(c->xwa, 0, sizeof(double) * c->C, c->stream));
   for (int s0 = ((T - 1) / K) * K; T > 0 && s0 >= 0; s0 -= K) {
     const int s1 = std::min(s0 + K, T);
     // recompute the segment
     float* state0 = c->seg;  // slot q: state of step s0+q; slot K+q: viscosity operand
     launch_copy_faces(c, cstacked(c, c->ckpt + (int64_t)(s0 / K) * F3n), stacked(c, state0));
+    // the recompute repeats the forward solves from the same starting iterates
+    if (c->ckpt_x) launch_x_to_double(c, c->ckpt_x + (int64_t)(s0 / K) * c->C, c->xw);
     for (int s = s0; s < s1; ++s) {
       const int q = s - s0;
       F3 us = stacked(c, c->seg + (int64_t)q * F3n);
@@ -788,7 +833,7 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
           launch_copy_faces(c, cstacked(c, c->tmp), op);
         else
           launch_copy_faces(c, cf3(nxt.c[0], nxt.c[1], nxt.c[2]), op);
-        rc = project_inplace(c, nxt, nullptr);
+        rc = project_inplace(c, nxt, nullptr, c->xw);
         worst = combine(worst, rc);
         if (rc < 0) return rc;
       } else {
@@ -805,7 +850,7 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
       const int q = s - s0;
       F3 us = stacked(c, c->seg + (int64_t)q * F3n);
       F3 op = stacked(c, c->seg + (int64_t)(K + q) * F3n);
-      int rc = project_inplace(c, lam, &st);
+      int rc = project_inplace(c, lam, &st, c->xwa);
       worst = combine(worst, rc);
       if (rc < 0) return rc;
       if (explicit_d) {

@@ -52,11 +52,23 @@ def test_workspace_size_rejects_bad_desc(bad):
     assert rc == fsb.SIM_ERR_INVALID_ARG
 
 
+def test_workspace_size_rejects_bad_warm_start():
+    d = _desc()
+    d.warm_start = 2
+    assert _ws_size(d)[0] == fsb.SIM_ERR_INVALID_ARG
+
+
 def test_workspace_size_grows_with_recording_and_precond():
     _, base = _ws_size(_desc(max_steps=0))
     _, rec = _ws_size(_desc(max_steps=16))
     _, mic = _ws_size(_desc(max_steps=0, precond="mic0"))
     assert rec > base and mic > base
+    # warm start: two FP64 pressures, plus one per checkpoint (16 / 4 = 4) when recording
+    n = 16
+    _, warm = _ws_size(_desc(max_steps=0, warm_start=True))
+    _, warm_rec = _ws_size(_desc(max_steps=16, warm_start=True))
+    assert warm - base >= 2 * 8 * n ** 3
+    assert warm_rec - rec >= 6 * 8 * n ** 3
     n = 16
     assert base > (3 * (n + 1) * n * n) * 4 * 7  # at least the face-domain buffers
 

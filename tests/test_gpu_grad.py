@@ -20,18 +20,24 @@ def torch_gpu():
     return torch
 
 
-@pytest.mark.parametrize("mode,nu_t,nu_e,K", [("explicit", 4e-3, 2e-3, 2), ("implicit", 8e-2, 5e-2, 3)])
-def test_gradient_matches_oracle(torch_gpu, orc, mode, nu_t, nu_e, K):
+@pytest.mark.parametrize("mode,nu_t,nu_e,K,warm", [("explicit", 4e-3, 2e-3, 2, False),
+                                                   ("implicit", 8e-2, 5e-2, 3, False),
+                                                   ("explicit", 4e-3, 2e-3, 2, True),
+                                                   ("implicit", 8e-2, 5e-2, 3, True)])
+def test_gradient_matches_oracle(torch_gpu, orc, mode, nu_t, nu_e, K, warm):
+    """With warm starts the solves begin from the previous pressures (forward
+    and adjoint) and the segment recompute from the pressures stored at the
+    checkpoints; the gradient is the same to the solver tolerance."""
     torch = torch_gpu
     from paper_2503_00868_amd.fluidsim import Sim
     from paper_2503_00868_amd.autograd import mse_loss, rollout
-    banner(f"gradient 16^3 {mode} K={K}")
+    banner(f"gradient 16^3 {mode} K={K} warm={warm}")
     n, steps, s_t, s_e = 16, 5, 1.2, 0.8
     cell, ug = case(n, 100, 2.0)
     target = orc.rollout(cell, ug, nu_t, s_t, steps, DT, mode=mode, tol=1e-12)[-1]
     ref = orc.rollout_grad(cell, ug, nu_e, s_e, steps, DT, target, mode=mode, tol=1e-12)
     sim = Sim(cell, precond="mic0", diffusion=mode, tol=1e-9, diff_tol=1e-9, max_steps=steps,
-              checkpoint_every=K)
+              checkpoint_every=K, warm_start=warm)
     th_nu = torch.tensor(math.log(nu_e), dtype=torch.float64, requires_grad=True)
     th_s = torch.tensor(math.log(s_e), dtype=torch.float64, requires_grad=True)
     ugen = tuple(t.requires_grad_(True) for t in sim.to_faces(ug))

@@ -156,6 +156,33 @@ def test_rollout_parity(torch_gpu, orc, precond, nu, steps):
     assert all(s["rel_residual"] <= 1e-6 for s in stats)
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "mic0"])
+def test_rollout_warm_start_parity(torch_gpu, orc, precond):
+    """Each solve of a warm-started rollout begins at the previous step's
+    pressure: the fields still match the oracle's cold 1e-12 solves, every
+    solve meets the 1e-6 residual, and the later solves need fewer
+    iterations than the cold ones."""
+    banner(f"warm rollout n=24 {precond}")
+    n, steps, nu = 24, 4, 2e-3
+    cell, u = case(n, 7, 2.0)
+    u0 = orc.mask_faces(cell, u)
+    iters = {}
+    for warm in (False, True):
+        sim = _sim(cell, precond=precond, warm_start=warm)
+        sim.set_params(nu=nu, dt=DT)
+        U = sim.to_faces(u0)
+        stats = sim.step(U, steps)
+        iters[warm] = [s["iters"] for s in stats]
+        assert all(s["rel_residual"] <= 1e-6 for s in stats)
+    ref = u0
+    for _ in range(steps):
+        ref, _ = orc.step(cell, ref, nu, DT)
+    l2, mx = rel_err(to_np(U), ref)
+    assert mx <= 1e-5 * steps and l2 <= 1e-5 * steps, (l2, mx)
+    assert iters[True][0] == iters[False][0]
+    assert sum(iters[True][1:]) < sum(iters[False][1:]), iters
+
+
 def test_solid_cells_and_ragged_size(torch_gpu, orc):
     banner("solid obstacle n=18")
     n = 18
