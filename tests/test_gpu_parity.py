@@ -138,6 +138,25 @@ def test_step_parity_small_config(torch_gpu, orc):
     banner(f"  iters gpu={st['iters']} oracle(1e-12)={info.proj_iters} rel={l2:.2e}/{mx:.2e}")
 
 
+def test_step32_matches_stored_fixture(torch_gpu):
+    """The same step against the stored oracle values (tests/golden)."""
+    from tests.test_golden import load
+    g = load("step32_seed0.txt")
+    n, seed, nu = int(g["n"][0]), int(g["seed"][0]), float(g["nu"][0])
+    cell, u = case(n, seed)
+    sim = _sim(cell, precond="jacobi")
+    sim.set_params(nu=nu, dt=DT)
+    from oracle import fluid as orc
+    U = sim.to_faces(orc.mask_faces(cell, u))
+    assert sim.step(U, 1)[0]["rel_residual"] <= 1e-6
+    for c, f in enumerate(to_np(U)):
+        k = f"u1_{'uvw'[c]}"
+        flat = f.reshape(-1)
+        idx = np.array([int(v) for v in g[k + "_idx"]])
+        want = np.array([float(v) for v in g[k + "_val"]])
+        assert np.abs(flat[idx] - want).max() <= 1e-5 * np.abs(flat).max(), k
+
+
 @pytest.mark.parametrize("precond,nu,steps", [("mic0", 5e-2, 3), ("jacobi", 2e-3, 4)])
 def test_rollout_parity(torch_gpu, orc, precond, nu, steps):
     banner(f"rollout n=24 {precond} nu={nu}")
