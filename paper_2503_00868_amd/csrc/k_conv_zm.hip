@@ -1,0 +1,332 @@
+// Full-resolution convolutions of the learned preconditioner (the 16-channel
+// level of the U-Net and the layers around it): a z-marching implicit GEMM on
+// the 16x16x32 bf16 MFMA of gfx950.
+//
+// A block owns a 16 x 16 tile of the xy-plane and walks a run of z-planes.
+// The three input planes z-1, z, z+1 (with a one-voxel xy halo, 18 x 18
+// voxels, all input channels) sit in an LDS ring; while the MFMAs work on
+// plane z, the global loads of plane z+2 are already in flight, and they land
+// in the ring slot that plane z-1 frees.  Each input voxel is thus read from
+// memory about once per layer (1.27x for the xy halo), instead of once per
+// overlapping 3-D tile.
+//
+// MFMA mapping (lane layout checked on the device): M = 16 output voxels
+// along x, N = 16 output channels, K = 32.  A K-step pairs two taps of one
+// 16-channel chunk: lanes 0-31 carry tap T0, lanes 32-63 tap T1.  The 27
+// taps form 15 steps per chunk:
+//   steps 0-8    (dx, dy) = (s % 3, s / 3), T0 = dz 0, T1 = dz 1
+//   steps 9-11   dy = s - 9,  T0 = (0, dy, 2), T1 = (1, dy, 2)
+//   steps 12-14  dy = s - 12, T0 = (2, dy, 2), T1 = the zero tap
+// Within a step group the A fragment depends only on halo row a + dy, so a
+// wave (4 output rows) loads 6 fragments and issues 12 MFMAs per group.
+// Weight fragments stay in registers for the whole block.
+#include "common.h"
+#include "ctx.h"
+#include "net.h"
+
+namespace fs {
+
+typedef __bf16 bf16x8z __attribute__((ext_vector_type(8)));
+typedef float f32x4z __attribute__((ext_vector_type(4)));
+
+constexpr int ZT = 16;              // output tile edge in x and y
+constexpr int ZR = ZT + 2;          // ring plane edge with halo
+constexpr int ZRV = ZR * ZR;        // 324 voxels per ring plane
+constexpr int ZSTEPS = 15;          // K-steps per 16-channel chunk
+constexpr int ZTAPS = 28;           // packed taps per weight row (27 + zero)
+
+__device__ inline int zm_tap0(int s) {
+  if (s < 9) return (s % 3) + 3 * (s / 3);              // dz 0
+  if (s < 12) return 0 + 3 * (s - 9) + 18;              // (0, dy, 2)
+  return 2 + 3 * (s - 12) + 18;                         // (2, dy, 2)
+}
+__device__ inline int zm_tap1(int s) {
+  if (s < 9) return (s % 3) + 3 * (s / 3) + 9;          // dz 1
+  if (s < 12) return 1 + 3 * (s - 9) + 18;              // (1, dy, 2)
+  return 27;                                            // zero tap
+}
+
+struct ZmGrid {
+  int tx, ty, zc, nchunks, blocks;
+};
+
+static ZmGrid zm_grid(int n) {
+  ZmGrid g;
+  g.tx = (n + ZT - 1) / ZT;
+  g.ty = g.tx;
+  const int tiles = g.tx * g.ty;
+  int chunks = (1024 + tiles - 1) / tiles;
+  if (chunks > n) chunks = n;
+  g.zc = (n + chunks - 1) / chunks;
+  if (g.zc < 2 && n >= 2) g.zc = 2;
+  g.nchunks = (n + g.zc - 1) / g.zc;
+  g.blocks = tiles * g.nchunks;
+  return g;
+}
+
+// CIN: channels held per ring voxel (multiple of 16; the source may have
+// fewer, the rest is zero).  WS: channel stride of the packed weights.
+// COUT: output channels (16 or 48).
+template <int CIN, int WS, int COUT, int EPI>
+__global__ void __launch_bounds__(kBlock)
+    k_conv_zm(int n, int zc, NetSrc src, const __bf16* __restrict__ w, NetOut out,
+              const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts");
+  constexpr int NCH = CIN / 16;          // 16-channel chunks
+  constexpr int NT = COUT / 16;          // 16-channel output groups
+  constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
+  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
+  constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
+  constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
+  __shared__ __attribute__((aligned(16))) __bf16 ring[3 * SLOT];
+  __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * ZT * COUT];
+
+  const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % tiles, chunk = lb / tiles;
+  const int tpr = (n + ZT - 1) / ZT;
+  const int x0 = (tile % tpr) * ZT, y0 = (tile / tpr) * ZT;
+  const int z0 = chunk * zc;
+  const int z1 = min(z0 + zc, n);
+  if (z0 >= n) return;
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int nc = n >> 1;
+
+  // weight fragments: bw[q][s][t] for chunk q, step s, output group t
+  bf16x8z bw[NCH][ZSTEPS][NT];
+#pragma unroll
+  for (int q = 0; q < NCH; ++q)
+#pragma unroll
+    for (int s = 0; s < ZSTEPS; ++s) {
+      const int tap = g < 2 ? zm_tap0(s) : zm_tap1(s);
+      const int ci = q * 16 + (g & 1) * 8;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        bf16x8z v;
+        if (ci < WS) {
+          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)(t * 16 + col) * ZTAPS + tap) * WS + ci);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+        }
+        bw[q][s][t] = v;
+      }
+    }
+
+  // global -> registers for input plane zi (zero outside the volume)
+  uint4 pf[PF];
+  auto load_plane = [&](int zi) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int it = threadIdx.x + k * kBlock;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
+        const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
+        const int c = p * 8;
+        if ((unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n && (unsigned)zi < (unsigned)n) {
+          if (c < src.ca) {
+            const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * ((gy >> 1) + (int64_t)nc * (zi >> 1))
+                                     : (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi);
+            val = *reinterpret_cast<const uint4*>(src.a + v * src.ca + c);
+          } else if (c < src.ca + src.cb) {
+            const int64_t v = (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi);
+            val = *reinterpret_cast<const uint4*>(src.b + v * src.cb + (c - src.ca));
+          }
+        }
+      }
+      pf[k] = val;
+    }
+  };
+  auto store_plane = [&](int zi) {
+    __bf16* slot = ring + ((zi + 3) % 3) * SLOT;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int it = threadIdx.x + k * kBlock;
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
+        *reinterpret_cast<uint4*>(slot + ((p >> 1) * ZRV + hv) * 16 + (p & 1) * 8) = pf[k];
+      }
+    }
+  };
+
+  // output layer: rms once per block; each lane owns one voxel of its wave's
+  // 4 x 16 output rows for the mask and the store
+  const float rms_f = EPI == NET_EPI_OUT ? (float)*out.rms : 0.f;
+  const int oy = y0 + 4 * wv + (lane >> 4), ox = x0 + (lane & 15);
+  const bool own = ox < n && oy < n;
+
+  load_plane(z0 - 1);
+  store_plane(z0 - 1);
+  load_plane(z0);
+  store_plane(z0);
+  load_plane(z0 + 1);
+
+  for (int z = z0; z < z1; ++z) {
+    __syncthreads();  // the compute of plane z-1 no longer reads slot (z+1) % 3
+    store_plane(z + 1);
+    __syncthreads();
+    if (z + 2 <= z1) load_plane(z + 2);
+
+    // issued before the MFMAs, consumed in the epilogue
+    uint8_t own_mask = 0;
+    if (EPI == NET_EPI_OUT && own)
+      own_mask = out.mask[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)];
+
+    f32x4z acc[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
+
+    const __bf16* sm = ring + ((z - 1 + 3) % 3) * SLOT;  // plane z-1 (dz = 0)
+    const __bf16* s0 = ring + ((z + 3) % 3) * SLOT;      // plane z   (dz = 1)
+    const __bf16* sp = ring + ((z + 1 + 3) % 3) * SLOT;  // plane z+1 (dz = 2)
+    const int half = (g & 1) * 8;
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      // groups 0-2: dx = 0..2, taps dz 0 | dz 1
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)q * ZRV * 16;
+        bf16x8z f[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 16 + half);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][dx + 3 * dy][t],
+                                                                  acc[a][t], 0, 0, 0);
+      }
+      // groups 3-4: dz 2 with (dx 0 | dx 1) and (dx 2 | zero)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int xo = h == 0 ? (g < 2 ? 0 : 1) : 2;
+        const __bf16* base = sp + (int64_t)q * ZRV * 16;
+        bf16x8z f[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 16 + half);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  f[a + dy], bw[q][9 + 3 * h + dy][t], acc[a][t], 0, 0, 0);
+      }
+    }
+
+    // epilogue: rows y0 + 4 wv + a, voxels x0 + 4 g + i, channel t*16 + col
+    if (EPI == NET_EPI_OUT) {
+      // channel 0 (lanes with col 0) through LDS: lane l then stores voxel
+      // (row l / 16, x l % 16) of the wave's rows, coalesced
+      float* so = reinterpret_cast<float*>(stage) + wv * 64;
+      if (col == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) so[a * 16 + 4 * g + i] = acc[a][0][i];
+      }
+      __syncthreads();
+      if (own)
+        out.f32[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)] =
+            own_mask ? rms_f * so[lane] : 0.f;
+      continue;
+    }
+    __bf16* st = stage + wv * (4 * ZT * COUT);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float v = acc[a][t][i];
+          if (EPI == NET_EPI_RELU) v = v > 0.f ? v : 0.f;
+          st[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = (__bf16)v;
+        }
+    __syncthreads();
+    constexpr int PV = COUT / 8;
+#pragma unroll
+    for (int k = 0; k < (4 * ZT * PV + 63) / 64; ++k) {
+      const int it = lane + 64 * k;
+      if (it >= 4 * ZT * PV) break;
+      const int lv = it / PV, part = it - lv * PV;
+      const int a = lv / ZT, xl = lv % ZT;
+      const int x = x0 + xl, y = y0 + 4 * wv + a;
+      if (x >= n || y >= n) continue;
+      const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+      uint4 val = *reinterpret_cast<const uint4*>(st + lv * COUT + part * 8);
+      if (EPI == NET_EPI_MASKGRAD) {
+        const uint4 pm = *reinterpret_cast<const uint4*>(out.relu_of + v * COUT + part * 8);
+        const uint32_t* pw = reinterpret_cast<const uint32_t*>(&pm);
+        uint32_t* vw = reinterpret_cast<uint32_t*>(&val);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t lo = pw[e] & 0xffffu, hi = pw[e] >> 16;
+          const uint32_t keep_lo = (lo != 0u && !(lo & 0x8000u)) ? 0xffffu : 0u;
+          const uint32_t keep_hi = (hi != 0u && !(hi & 0x8000u)) ? 0xffff0000u : 0u;
+          vw[e] &= (keep_lo | keep_hi);
+        }
+      }
+      *reinterpret_cast<uint4*>(out.bf + v * COUT + part * 8) = val;
+    }
+  }
+}
+
+template <int CIN, int WS, int COUT, int EPI>
+static void zm_launch(sim_ctx* c, int n, NetSrc src, const __bf16* w, NetOut out,
+                      const int* flags) {
+  const ZmGrid g = zm_grid(n);
+  hipLaunchKernelGGL((k_conv_zm<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream, n,
+                     g.zc, src, w, out, flags);
+}
+
+template <int CIN, int WS, int COUT>
+static void zm_epi(sim_ctx* c, int n, int epi, NetSrc src, const __bf16* w, NetOut out,
+                   const int* flags) {
+  switch (epi) {
+    case NET_EPI_RELU: zm_launch<CIN, WS, COUT, NET_EPI_RELU>(c, n, src, w, out, flags); break;
+    case NET_EPI_RAW: zm_launch<CIN, WS, COUT, NET_EPI_RAW>(c, n, src, w, out, flags); break;
+    case NET_EPI_MASKGRAD: zm_launch<CIN, WS, COUT, NET_EPI_MASKGRAD>(c, n, src, w, out, flags); break;
+    default: zm_launch<CIN, WS, COUT, NET_EPI_OUT>(c, n, src, w, out, flags); break;
+  }
+}
+
+bool net_conv_zm(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const __bf16* w,
+                 NetOut out, const int* flags) {
+  if (cin == 8 && cout == 16) {
+    zm_epi<16, 8, 16>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  if (cin == 16 && cout == 16) {
+    zm_epi<16, 16, 16>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  if (cin == 48 && cout == 16) {
+    zm_epi<48, 48, 16>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  if (cin == 16 && cout == 32) {
+    zm_epi<16, 16, 32>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  if (cin == 32 && cout == 32) {
+    zm_epi<32, 32, 32>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  if (cin == 16 && cout == 48) {
+    zm_epi<16, 16, 48>(c, n, epi, src, w, out, flags);
+    return true;
+  }
+  return false;
+}
+
+}  // namespace fs
