@@ -50,6 +50,15 @@ BYTES_PER_UNIT = {
 }
 FACE_KINDS = {"advect", "diffuse_explicit", "dcg_dir_spmv", "dcg_update", "advect_adjoint"}
 
+# Algorithmic FLOPs of one U-Net application per fine cell: 2 * 27 * c_in *
+# c_out per voxel of each convolution (real channel counts), with the level-2
+# and level-3 voxel counts 1/8 and 1/64 of the fine level.
+UNET_LEVEL_CONVS = {1: [(2, 16), (16, 16), (48, 16), (16, 16), (16, 1)],
+                    2: [(16, 32), (32, 32), (96, 32), (32, 32)],
+                    3: [(32, 64), (64, 64)]}
+NET_FLOP_PER_CELL = sum(54 * a * b / 8 ** (lvl - 1)
+                        for lvl, convs in UNET_LEVEL_CONVS.items() for a, b in convs)
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -72,6 +81,10 @@ def parse():
     p.add_argument("--cold", action="store_true",
                    help="start every pressure solve of the rollout at zero (default: from the "
                         "previous step's pressure)")
+    p.add_argument("--check-every", type=int, default=0,
+                   help="FP64 residual-check period (0: 16 for Jacobi, 4 otherwise)")
+    p.add_argument("--no-plain", action="store_true",
+                   help="skip the plain (Jacobi) PCG rollout timed beside a learned headline")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-n", type=int, default=128)
@@ -135,6 +148,41 @@ def cpu_baseline(n, seed):
                       f" viscosity), {dt:.1f} s"}
 
 
+def rooflines(prof, n, precond):
+    """Roofline of the kernel kind with the most time in the timed region
+    (the U-Net against the BF16 MFMA peak, every other kind against HBM),
+    and of the top HBM-bound kind."""
+    C, F3 = n ** 3, 3 * (n + 1) * n * n
+
+    def hbm(kind):
+        ms_tot, launches = prof[kind]
+        units = F3 if kind in FACE_KINDS else C
+        per_unit = BYTES_PER_UNIT[kind]
+        if kind == "pcg_update" and precond != "jacobi":
+            per_unit = 33.0
+        per_launch = per_unit * units
+        avg_s = ms_tot / launches / 1e3
+        achieved = per_launch / avg_s / 1e9
+        return {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(kind, n), "avg_us": round(avg_s * 1e6, 2),
+                "launches": launches, "bytes_per_launch": per_launch}
+
+    kinds = {k: v for k, v in prof.items() if k in BYTES_PER_UNIT and v[1] > 0}
+    r_hbm = hbm(max(kinds, key=lambda k: kinds[k][0]))
+    net_ms, net_launches = prof.get("net", (0.0, 0))
+    if net_launches and net_ms > max(v[0] for v in kinds.values()):
+        avg_s = net_ms / net_launches / 1e3
+        flop = NET_FLOP_PER_CELL * C
+        achieved = flop / avg_s / 1e12
+        return ({"bound": "mfma", "kernel": "net", "achieved": round(achieved, 1),
+                 "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                 "avg_us": round(avg_s * 1e6, 1), "launches": net_launches,
+                 "flop_per_launch": flop}, r_hbm)
+    return r_hbm, None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -176,20 +224,33 @@ def main():
     log(f"liquid fraction {inputs.liquid_fraction(cell):.3f}; nu*={nu_t:.3e} s*={s_t:.3f}; "
         f"eval nu={nu_e:.3e} s={s_e:.3f}")
 
-    sim = Sim(cell, precond=precond, tol=1e-6, diff_tol=1e-6, max_iter=20000, check_every=8,
-              checkpoint_every=K, max_steps=T, warm_start=not args.cold, device=dev)
-    if weights is not None:
-        sim.net_set_weights(weights)
-    ugen = sim.to_faces(ug)
-    u = sim.faces()
+    def check_period(pc):
+        return args.check_every or (16 if pc == "jacobi" else 4)
 
-    # target rollout (untimed setup)
-    sim.set_params(nu=nu_t, dt=dt, s=s_t, gravity=g)
-    target = sim.faces()
-    sim.init_state(ugen, target)
-    sim.step(target, T)
+    def make_sim(pc):
+        s = Sim(cell, precond=pc, tol=1e-6, diff_tol=1e-6, max_iter=20000,
+                check_every=check_period(pc), checkpoint_every=K, max_steps=T,
+                warm_start=not args.cold, device=dev)
+        if pc == "learned":
+            s.net_set_weights(weights)
+        return s
+
+    # target rollout (untimed setup; the target does not depend on the
+    # preconditioner, so the fastest plain one computes it)
+    tsim = Sim(cell, precond="jacobi", tol=1e-6, diff_tol=1e-6, max_iter=20000, check_every=16,
+               warm_start=True, device=dev)
+    ugen = tsim.to_faces(ug)
+    tsim.set_params(nu=nu_t, dt=dt, s=s_t, gravity=g)
+    target = tsim.faces()
+    tsim.init_state(ugen, target)
+    tsim.step(target, T)
     torch.cuda.synchronize()
+    tsim.close()
+    del tsim
     log("target rollout done")
+
+    sim = make_sim(precond)
+    u = sim.faces()
 
     def bench_step(rollout):
         sim.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
@@ -225,24 +286,39 @@ def main():
         f"fwd mean {np.mean(fwd_iters):.1f}; adjoint iters {bwd_stats[-1]['iters']}; J={J:.4e} "
         f"dJ/dnu={dnu:.4e} dJ/ds={ds:.4e}")
 
-    # roofline of the dominant bandwidth kernel
-    C, F3 = n ** 3, 3 * (n + 1) * n * n
-    kinds = {k: v for k, v in prof.items() if k in BYTES_PER_UNIT and v[1] > 0}
-    dom = max(kinds, key=lambda k: kinds[k][0])
-    ms_tot, launches = kinds[dom]
-    units = F3 if dom in FACE_KINDS else C
-    per_unit = BYTES_PER_UNIT[dom]
-    if dom == "pcg_update" and precond != "jacobi":
-        per_unit = 33.0
-    per_launch = per_unit * units
-    avg_s = ms_tot / launches / 1e3
-    achieved = per_launch / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(dom, n), "avg_us": round(avg_s * 1e6, 2), "launches": launches,
-                "bytes_per_launch": per_launch}
+    roofline, roofline_hbm = rooflines(prof, n, precond)
     log("kernel time in the timed region (ms, launches): " +
         ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items() if v[1]))
+
+    # the same workload with plain (Jacobi) PCG, beside a learned headline
+    plain = None
+    if precond != "jacobi" and not args.no_plain:
+        sim.close()
+        del sim
+        psim = make_sim("jacobi")
+        pu = psim.faces()
+
+        def plain_step(rollout):
+            psim.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
+            psim.init_state(ugen, pu)
+            st = psim.step(pu, rollout, record=True)
+            _, gT = psim.loss_mse(pu, target)
+            psim.backward(gT, ugen=ugen)
+            return st
+
+        plain_step(args.warmup_rollout)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pst = plain_step(T)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t1
+        plain = {"precond": "jacobi", "ms_per_step": round(pel * 1e3, 1),
+                 "value": n ** 3 * T / pel,
+                 "pressure_iters_mean": float(np.mean([s["iters"] for s in pst])),
+                 "check_every": check_period("jacobi")}
+        log(f"plain Jacobi-PCG rollout: {pel * 1e3:.1f} ms, {plain['value']:.3e} cell-steps/s")
+        psim.close()
+        del psim
 
     compare = None
     if not args.no_compare:
@@ -250,14 +326,11 @@ def main():
         for pc in ("jacobi", "mic0", "learned"):
             if pc == "learned" and weights is None:
                 continue
-            if pc == "mic0" and n > 128:
-                # hyperplane MIC(0) sweeps: 2 x (3n - 2) dependent launches per apply
-                pass
-            s2 = Sim(cell, precond=pc, tol=1e-6, check_every=8, device=dev)
+            s2 = Sim(cell, precond=pc, tol=1e-6, check_every=check_period(pc), device=dev)
             if pc == "learned":
                 s2.net_set_weights(weights)
             s2.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
-            uu = sim.faces()
+            uu = s2.faces()
             s2.init_state(ugen, uu)
             s2.step(uu, 1)
             torch.cuda.synchronize()
@@ -297,6 +370,8 @@ def main():
                    "n": n, "rollout": T, "checkpoint_every": K, "precond": precond,
                    "seed": args.seed, "nu": nu_e, "s": s_e, "warm_start": not args.cold},
         "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
+        "plain_pcg": plain,
         "cpu_baseline": cpu,
         "compare": compare,
         "pressure_iters_mean": float(np.mean(fwd_iters)),

@@ -181,7 +181,9 @@ int sim_net_grad(sim_ctx* ctx, const float* d_r, const float* d_e, int32_t batch
  * iterate A x = b and at each requested iteration k (strictly increasing,
  * h_iters[count]; even for mode 0) record the true residual
  * r_k = b - A x_k and the error e_k = x* - x_k into d_r_out[j], d_e_out[j]
- * (count x n^3 float32 each), x* from a Jacobi-PCG solve to tol.
+ * (count x n^3 float32 each).  x* comes first, from a Jacobi-PCG solve to
+ * tol kept in FP64, and e_k is formed in FP64 before rounding (late
+ * iterates differ from x* by less than FP32 resolves in x).
  * mode 0: the iterates of Jacobi-PCG itself; mode 1: the iterates of the
  * flexible CG with the current network (its own residuals, for on-policy
  * training; needs weights).  h_stats->fallback_used = 1 reports that the

@@ -164,8 +164,8 @@ void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
 // out = x over the cells; skipped when flags (nullable) has the done flag raised
 void launch_x_to_double(sim_ctx* c, const double* x, double* out, const int* flags = nullptr);
-// out = (float) x (err = 0) or (float)(x - out) (err = 1), over cells
-void launch_x_snapshot(sim_ctx* c, float* out, int err);
+// out = (float)(xref - x) over the cells (FP64 difference)
+void launch_err_snapshot(sim_ctx* c, const double* xref, float* out);
 
 // flexible CG pieces (learned preconditioner)
 void launch_fcg_init(sim_ctx* c);

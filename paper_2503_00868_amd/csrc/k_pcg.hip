@@ -822,14 +822,16 @@ __global__ void __launch_bounds__(kBlock)
 
 // out = (float) x, or out = (float)(x - (double) out) when err != 0.
 __global__ void __launch_bounds__(kBlock)
-    k_x_snapshot(int64_t C, const double* __restrict__ x, float* __restrict__ out, int err) {
+    k_err_snapshot(int64_t C, const double* __restrict__ xref, const double* __restrict__ x,
+                   float* __restrict__ out) {
   for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
        idx += (int64_t)gridDim.x * kBlock)
-    out[idx] = err ? (float)(x[idx] - (double)out[idx]) : (float)x[idx];
+    out[idx] = (float)(xref[idx] - x[idx]);
 }
 
-void launch_x_snapshot(sim_ctx* c, float* out, int err) {
-  hipLaunchKernelGGL(k_x_snapshot, dim3(2048), dim3(kBlock), 0, c->stream, c->C, c->x, out, err);
+void launch_err_snapshot(sim_ctx* c, const double* xref, float* out) {
+  hipLaunchKernelGGL(k_err_snapshot, dim3(2048), dim3(kBlock), 0, c->stream, c->C, xref, c->x,
+                     out);
 }
 
 __global__ void __launch_bounds__(kBlock)

@@ -54,6 +54,16 @@ def harvest(sim, seed, iters=HARVEST_ITERS, tol=1e-10, mode=0):
     return sim.harvest_pairs(u, list(iters), tol=tol, mode=mode)
 
 
+def usable_pairs(R, E, rel_floor=1e-7):
+    """Pairs whose error is resolved: r.e > 0 (e = A^-1 r makes it e^T A e)
+    and |r| above rel_floor of the largest residual of the batch (below it
+    the reference solution's own 1e-10 residual would dominate e)."""
+    re = (R.double() * E.double()).sum(dim=(1, 2, 3))
+    rn = R.double().flatten(1).norm(dim=1)
+    keep = (re > 0) & (rn > rel_floor * rn.max())
+    return R[keep], E[keep], int(keep.sum())
+
+
 def train(n=128, seeds=range(1000, 1400), lr=1e-3, lr_final=1e-4, init_seed=0, out=None,
           device="cuda", log_every=25, max_seconds=None, weights=None,
           plain_iters=(0, 12, 48), policy_iters=(1, 3, 8, 16, 32, 64)):
@@ -80,7 +90,14 @@ def train(n=128, seeds=range(1000, 1400), lr=1e-3, lr_final=1e-4, init_seed=0, o
         else:
             R = torch.cat([R0, R1])
             E = torch.cat([E0, E1])
+        R, E, kept = usable_pairs(R, E)
+        if kept == 0:
+            sim.close()
+            continue
         frac = (step - 1) / max(1, len(seeds) - 1)
+        if max_seconds:  # decay over whichever ends first: the seeds or the time
+            frac = max(frac, (time.perf_counter() - t0) / max_seconds)
+        frac = min(frac, 1.0)
         lr_t = lr * (lr_final / lr) ** frac  # exponential decay
         loss = sim.net_train_step(R, E, R.shape[0], master, adam, step, lr_t)
         sim.close()

@@ -184,3 +184,23 @@ def test_harvest_pairs_consistent(torch_gpu, orc):
     x_ref, _, _ = orc.pcg(cell, b, orc.PRECOND_NONE, 1e-12)
     assert np.linalg.norm(E[0] - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
     assert np.linalg.norm(R[2]) < np.linalg.norm(R[0])
+
+
+def test_harvest_pairs_from_flexible_cg_consistent(torch_gpu, orc):
+    """Mode 1 (iterates of the flexible CG with the network): A e_k = r_k with
+    e_k formed in FP64 against the reference solution."""
+    from paper_2503_00868_amd.fluidsim import Sim
+    banner("harvest mode 1 n=24")
+    n = 24
+    cell, u = case(n, 11)
+    u = orc.add_force(cell, orc.mask_faces(cell, u), DT)
+    sim = Sim(cell, precond="learned")
+    sim.net_set_weights(torch_gpu.as_tensor(net_weights.init_weights(4), device="cuda"))
+    R, E, st = sim.harvest_pairs(sim.to_faces(u), [0, 1, 2, 5], tol=1e-10, mode=1)
+    R = R.cpu().numpy().astype(np.float64)
+    E = E.cpu().numpy().astype(np.float64)
+    last = 4 if not st["fallback_used"] else 1
+    for j in range(last):
+        Ae = orc.poisson_apply(cell, E[j])
+        assert np.linalg.norm(Ae - R[j]) <= 1e-4 * np.linalg.norm(R[j]), j
+        assert float((R[j] * E[j]).sum()) > 0
