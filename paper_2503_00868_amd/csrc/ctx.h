@@ -30,6 +30,9 @@ enum ScalarSlot {
   S_NET_RZ,      //   training: r.z, r.e, z.Az (contiguous)
   S_NET_RE,
   S_NET_ZAZ,
+  S_ALPHA_Q0,    // alphas of the first three iterations of a four-step iterate update
+  S_ALPHA_Q1,
+  S_ALPHA_Q2,
   S_COUNT = 32
 };
 enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };
@@ -85,6 +88,8 @@ struct sim_ctx {
   float* z = nullptr;
   float* dA = nullptr;
   float* dB = nullptr;
+  float* dC = nullptr;      // Jacobi-PCG: four rotating direction buffers dA..dD
+  float* dD = nullptr;
   float* q = nullptr;
   float* b = nullptr;
   float* rprev = nullptr;   // flexible CG
@@ -157,6 +162,10 @@ void launch_pcg_dir_spmv(sim_ctx* c, int prec, const float* d_in, float* d_out);
 void launch_pcg_update(sim_ctx* c, int prec, const float* d);
 // Jacobi only: odd iterations update r; even ones also x += a_prev d_prev + a d
 void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool with_x);
+// Jacobi-PCG with the FP64 iterate updated every fourth iteration: phase =
+// iteration % 4; dirs[0..3] are the directions of iterations phase-3..phase
+// of the current group (only dirs[3] is read before phase 3).
+void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);

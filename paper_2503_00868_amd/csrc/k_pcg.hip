@@ -649,6 +649,62 @@ __global__ void __launch_bounds__(kBlock)
   if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_PREV] = alpha;
 }
 
+// Four-step variant: r -= alpha q every iteration; the alphas of the first
+// three iterations of a group of four are kept in scal, and on the fourth
+// x += a0 d0 + a1 d1 + a2 d2 + a3 d3 in FP64 (one read-modify-write of x per
+// four iterations).
+template <int V, bool WITH_X>
+__global__ void __launch_bounds__(kBlock)
+    k_update4(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
+              float* __restrict__ r, const float* __restrict__ d0, const float* __restrict__ d1,
+              const float* __restrict__ d2, const float* __restrict__ d3,
+              const float* __restrict__ q, double* __restrict__ scal, int phase,
+              const int* __restrict__ flags, double* partials) {
+  if (flags[F_DONE]) return;
+  const int64_t G = cells(n) / V;
+  const double alpha = scal[S_RZ] / scal[S_DQ];
+  const float alpha_f = (float)alpha;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const Run run = group_run(G, gridDim.x, lb);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (WITH_X) {
+    a0 = scal[S_ALPHA_Q0];
+    a1 = scal[S_ALPHA_Q1];
+    a2 = scal[S_ALPHA_Q2];
+  }
+  double v[1] = {0.0};
+  for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
+    const int64_t idx = g * V;
+    float qv[V], rv[V];
+    uint8_t dg[V];
+    ldf<V>(q + idx, qv);
+    ldf<V>(r + idx, rv);
+    ldg<V>(cdiag + idx, dg);
+    if (WITH_X) {
+      double xv[V];
+      float e0[V], e1[V], e2[V], e3[V];
+      ldd<V>(x + idx, xv);
+      ldf<V>(d0 + idx, e0);
+      ldf<V>(d1 + idx, e1);
+      ldf<V>(d2 + idx, e2);
+      ldf<V>(d3 + idx, e3);
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        xv[e] += (a0 * (double)e0[e] + a1 * (double)e1[e]) +
+                 (a2 * (double)e2[e] + alpha * (double)e3[e]);
+      std_<V>(x + idx, xv);
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      rv[e] -= alpha_f * qv[e];
+      v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+    }
+    stf<V>(r + idx, rv);
+  }
+  store_partials<1>(v, partials, lb);
+  if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_Q0 + phase] = alpha;
+}
+
 // x += alpha d ; r -= alpha q ; (Jacobi) partial r.M^-1 r.
 // alpha = RZ / DQ (PCG) or DR / DQ (flexible CG).
 template <int V, int PREC, bool FLEX>
@@ -922,6 +978,19 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
     FS_CELL_LAUNCH(k_update2, true);
   else
     FS_CELL_LAUNCH(k_update2, false);
+  prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+#undef ARGS
+  launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
+}
+
+void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
+#define ARGS c->n, c->cdiag, c->x, c->r, dirs[0], dirs[1], dirs[2], dirs[3], c->q, c->scal, \
+             phase, c->flags, c->partials
+  prof_mark(c, SIM_KERN_PCG_UPDATE, true);
+  if (phase == 3)
+    FS_CELL_LAUNCH(k_update4, true);
+  else
+    FS_CELL_LAUNCH(k_update4, false);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
 #undef ARGS
   launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);

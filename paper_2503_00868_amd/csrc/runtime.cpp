@@ -109,6 +109,8 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->z = cv.take<float>(C);
   t->dA = cv.take<float>(C);
   t->dB = cv.take<float>(C);
+  t->dC = d.precond == SIM_PRECOND_JACOBI ? cv.take<float>(C) : nullptr;
+  t->dD = d.precond == SIM_PRECOND_JACOBI ? cv.take<float>(C) : nullptr;
   t->q = cv.take<float>(C);
   t->b = cv.take<float>(C);
   const bool mic = d.precond == SIM_PRECOND_MIC0 || d.precond == SIM_PRECOND_LEARNED;
@@ -358,16 +360,30 @@ int pcg_solve(sim_ctx* c, int prec_kind, int start, const double* x0, sim_stats*
   float* din = c->dA;
   float* dout = c->dB;
   const double tol = c->desc.tol;
-  // Jacobi: the FP64 iterate is updated every second iteration (two
-  // directions at once), so blocks hold an even number of iterations and
-  // every check sees an up-to-date x.
-  const bool two_step = pk == PK_JACOBI;
-  const int m = two_step ? (c->desc.check_every + 1) / 2 * 2 : c->desc.check_every;
-  const int max_it = two_step ? (c->desc.max_iter + 1) / 2 * 2 : c->desc.max_iter;
+  // Jacobi: the FP64 iterate is updated every fourth iteration (four
+  // directions at once, from four rotating buffers; the initial direction
+  // buffer dA is zero), so blocks hold a multiple of 4 iterations and every
+  // check sees an up-to-date x.
+  const bool four_step = pk == PK_JACOBI && c->dC && c->dD;
+  const int group = four_step ? 4 : (pk == PK_JACOBI ? 2 : 1);
+  const int m = (c->desc.check_every + group - 1) / group * group;
+  const int max_it = (c->desc.max_iter + group - 1) / group * group;
+  float* const dbuf[4] = {c->dA, c->dB, c->dC, c->dD};
+  int it = 0;  // iterations enqueued in this solve
   auto block = [&](int todo) {
-    for (int t = 0; t < todo; ++t) {
+    for (int t = 0; t < todo; ++t, ++it) {
+      if (four_step) {
+        // iteration k reads dbuf[k % 4] (the previous direction) and writes dbuf[(k + 1) % 4]
+        const int ph = it & 3;
+        launch_pcg_dir_spmv(c, pk, dbuf[ph], dbuf[(ph + 1) & 3]);
+        const float* dirs[4] = {dbuf[(ph + 2) & 3], dbuf[(ph + 3) & 3], dbuf[ph],
+                                dbuf[(ph + 1) & 3]};
+        launch_pcg_update4(c, dirs, ph);
+        if (t == todo - 1) launch_pcg_check(c, pk, tol);
+        continue;
+      }
       launch_pcg_dir_spmv(c, pk, din, dout);
-      if (two_step)
+      if (pk == PK_JACOBI)
         launch_pcg_update2(c, dout, din, (t & 1) != 0);
       else
         launch_pcg_update(c, pk, dout);

@@ -260,7 +260,7 @@ def test_not_converged_reports_status(torch_gpu, orc):
     from paper_2503_00868_amd.fluidsim import SIM_ERR_NOT_CONVERGED
     n = 16
     cell, u = case(n, 10)
-    for precond, want in (("jacobi", 4), ("mic0", 3)):  # Jacobi iterates in pairs
+    for precond, want in (("jacobi", 4), ("mic0", 3)):  # Jacobi iterates in groups of 4
         sim = _sim(cell, precond=precond, max_iter=3, check_every=2)
         sim.set_params(nu=1e-3, dt=DT)
         U = sim.to_faces(orc.mask_faces(cell, u))
