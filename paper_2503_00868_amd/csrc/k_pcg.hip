@@ -350,8 +350,14 @@ __global__ void __launch_bounds__(kBlock)
 // registers, the current plane (plus a one-cell halo) goes through LDS for
 // the x and y neighbours.  Halo cells outside the box are written as zero,
 // which is also their contribution (every vector is zero off liquid).
+// Target launch size of the z-marching stencils (a compile-time setting):
+// fewer blocks mean longer z-runs and less halo re-reading, more blocks more
+// latency hiding.
+#ifndef FS_ZM_BLOCKS
+#define FS_ZM_BLOCKS 1024
+#endif
 constexpr int ZM_GX = 16;  // 4-cell groups per tile along x (64 cells)
-constexpr int ZM_TY = 16;  // rows per tile
+constexpr int ZM_TY = 16;  // rows per tile (ZM_GX * ZM_TY = kBlock threads)
 constexpr int ZM_W = 4 * ZM_GX + 2;
 
 struct ZTile {
@@ -594,7 +600,7 @@ struct ZmShape {
 
 static ZmShape zm_shape(int n) {
   const int tiles = ((n + 4 * ZM_GX - 1) / (4 * ZM_GX)) * ((n + ZM_TY - 1) / ZM_TY);
-  int chunks = 1024 / tiles;
+  int chunks = FS_ZM_BLOCKS / tiles;
   if (chunks < 1) chunks = 1;
   if (chunks > n / 4) chunks = n / 4 > 0 ? n / 4 : 1;
   int zc = (n + chunks - 1) / chunks;
