@@ -80,7 +80,9 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
   constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
   __shared__ __attribute__((aligned(16))) __bf16 ring[3 * SLOT];
-  __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * ZT * COUT];
+  constexpr int STAGE_BYTES = 4 * 4 * ZT * COUT * (EPI == NET_EPI_RELU_ADD ? 4 : 2);
+  __shared__ __attribute__((aligned(16))) char stage_raw[STAGE_BYTES];
+  __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
 
   const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -241,6 +243,40 @@ __global__ void __launch_bounds__(kBlock)
             own_mask ? rms_f * so[lane] : 0.f;
       continue;
     }
+    if (EPI == NET_EPI_RELU_ADD) {
+      // raw fp32 sums through LDS; each store adds the fp16 partial sums of
+      // the upsampled channels, then applies the ReLU
+      float* sf = reinterpret_cast<float*>(stage_raw) + wv * (4 * ZT * COUT);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = acc[a][t][i];
+      __syncthreads();
+      constexpr int PV8 = COUT / 8;
+#pragma unroll
+      for (int k = 0; k < (4 * ZT * PV8 + 63) / 64; ++k) {
+        const int it = lane + 64 * k;
+        if (it >= 4 * ZT * PV8) break;
+        const int lv = it / PV8, part = it - lv * PV8;
+        const int a = lv / ZT, xl = lv % ZT;
+        const int x = x0 + xl, y = y0 + 4 * wv + a;
+        if (x >= n || y >= n) continue;
+        const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+        const uint4 hv = *reinterpret_cast<const uint4*>(out.add + v * COUT + part * 8);
+        const _Float16* hp = reinterpret_cast<const _Float16*>(&hv);
+        const float* s8 = sf + lv * COUT + part * 8;
+        __bf16 o8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float sum = s8[e] + (float)hp[e];
+          o8[e] = (__bf16)(sum > 0.f ? sum : 0.f);
+        }
+        *reinterpret_cast<uint4*>(out.bf + v * COUT + part * 8) = *reinterpret_cast<const uint4*>(o8);
+      }
+      continue;
+    }
     __bf16* st = stage + wv * (4 * ZT * COUT);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -296,6 +332,7 @@ static void zm_epi(sim_ctx* c, int n, int epi, NetSrc src, const __bf16* w, NetO
     case NET_EPI_RELU: zm_launch<CIN, WS, COUT, NET_EPI_RELU>(c, n, src, w, out, flags); break;
     case NET_EPI_RAW: zm_launch<CIN, WS, COUT, NET_EPI_RAW>(c, n, src, w, out, flags); break;
     case NET_EPI_MASKGRAD: zm_launch<CIN, WS, COUT, NET_EPI_MASKGRAD>(c, n, src, w, out, flags); break;
+    case NET_EPI_RELU_ADD: zm_launch<CIN, WS, COUT, NET_EPI_RELU_ADD>(c, n, src, w, out, flags); break;
     default: zm_launch<CIN, WS, COUT, NET_EPI_OUT>(c, n, src, w, out, flags); break;
   }
 }

@@ -1,0 +1,203 @@
+// Upsampled half of the U-Net's concatenating convolutions (decoder layers
+// c7 and c9), evaluated on the coarse grid.
+//
+// The decoder convolves cat(up(coarse), skip) with a 3x3x3 kernel, where up
+// is the nearest x2 upsampling.  For a fine voxel x = 2X + p (p its parity
+// along one axis) a fine tap d in {-1, 0, 1} reads coarse voxel
+// floor((p + d) / 2) + X: parity 0 sees offsets {-1, 0, 0}, parity 1
+// {0, 0, +1}.  So per parity class (px, py, pz) the upsampled part is a
+// 2x2x2 convolution of the coarse tensor, whose weights are sums of the
+// fine taps that land on the same coarse voxel.  Evaluating it that way
+// takes 8 instead of 27 taps per output (and reads the coarse tensor, not
+// an 8x larger upsampled copy); the z-marching kernel then adds these fp16
+// partial sums to its skip-channel convolution before the ReLU.
+//
+// MFMA mapping (16x16x32 bf16): M = 16 coarse voxels along X, N = 16 output
+// channels, K = 32 coarse channels of one coarse tap offset.  A wave owns 4
+// coarse rows; for each of the 27 coarse offsets it loads the 4 row
+// fragments once and issues them against the weights of every parity class
+// that uses the offset (8 x 8 x 4 MFMAs per 64 coarse voxels).
+#include "common.h"
+#include "ctx.h"
+#include "net.h"
+
+namespace fs {
+
+typedef __bf16 bf16x8u __attribute__((ext_vector_type(8)));
+typedef float f32x4u __attribute__((ext_vector_type(4)));
+
+constexpr int UX = 16;   // coarse voxels per wave row (MFMA M)
+constexpr int UR = 4;    // coarse rows per wave
+constexpr int UY = 16;   // coarse rows per block (4 waves)
+
+// Coarse offset of fine tap d (-1, 0, 1) for parity q (0, 1).
+__host__ __device__ constexpr int up_off(int q, int d) { return (q + d + 2) / 2 - 1; }
+
+template <int CC, int COUT>
+__global__ void __launch_bounds__(kBlock)
+    k_upconv(int n, const __bf16* __restrict__ coarse, const __bf16* __restrict__ weff,
+             _Float16* __restrict__ out, const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  static_assert(CC % 32 == 0 && COUT % 16 == 0, "channel counts");
+  constexpr int KS = CC / 32;
+  constexpr int NT = COUT / 16;
+  __shared__ __attribute__((aligned(16))) _Float16 stage[4][8 * 2 * UX * 16];
+  const int nc = n / 2;
+  const int tx = (nc + UX - 1) / UX, ty = (nc + UY - 1) / UY;
+  const int b = blockIdx.x;
+  const int X0 = (b % tx) * UX;
+  const int Y0 = ((b / tx) % ty) * UY;
+  const int Z = b / (tx * ty);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int Yw = Y0 + UR * wv;
+
+#pragma unroll 1
+  for (int t = 0; t < NT; ++t) {
+    f32x4u acc[8][UR];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int r = 0; r < UR; ++r) acc[p][r] = f32x4u{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox)
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            bf16x8u a[UR];
+            const int cx = X0 + col + ox, cz = Z + oz;
+#pragma unroll
+            for (int r = 0; r < UR; ++r) {
+              const int cy = Yw + r + oy;
+              if ((unsigned)cx < (unsigned)nc && (unsigned)cy < (unsigned)nc &&
+                  (unsigned)cz < (unsigned)nc) {
+                a[r] = *reinterpret_cast<const bf16x8u*>(
+                    coarse + ((int64_t)cx + (int64_t)nc * (cy + (int64_t)nc * cz)) * CC + ks * 32 + 8 * g);
+              } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[r][e] = (__bf16)0.f;
+              }
+            }
+#pragma unroll
+            for (int pz = 0; pz < 2; ++pz) {
+              if (oz == (pz ? -1 : 1)) continue;  // parity 0 never reads +1, parity 1 never -1
+#pragma unroll
+              for (int py = 0; py < 2; ++py) {
+                if (oy == (py ? -1 : 1)) continue;
+#pragma unroll
+                for (int px = 0; px < 2; ++px) {
+                  if (ox == (px ? -1 : 1)) continue;
+                  const int p = px + 2 * py + 4 * pz;
+                  const int tap = (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
+                  const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
+                      weff + ((int64_t)(p * 8 + tap) * COUT + t * 16 + col) * CC + ks * 32 + 8 * g);
+#pragma unroll
+                  for (int r = 0; r < UR; ++r)
+                    acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bw, acc[p][r], 0, 0, 0);
+                }
+              }
+            }
+          }
+
+    // epilogue: one fine z-plane (pz) at a time through LDS, as rows of 2*UX
+    // fine voxels x 16 channels
+#pragma unroll
+    for (int pz = 0; pz < 2; ++pz) {
+      _Float16* st = stage[wv];
+#pragma unroll
+      for (int py = 0; py < 2; ++py)
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+          for (int r = 0; r < UR; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int fx = 2 * (4 * g + i) + px, fy = 2 * r + py;
+              st[(fy * 2 * UX + fx) * 16 + col] = (_Float16)acc[px + 2 * py + 4 * pz][r][i];
+            }
+      __syncthreads();
+      const int fz = 2 * Z + pz;
+#pragma unroll
+      for (int k = 0; k < (8 * 2 * UX * 2) / 64; ++k) {
+        const int it = lane + 64 * k;  // (fy, fx, half)
+        const int half = it & 1, fx = (it >> 1) % (2 * UX), fy = (it >> 1) / (2 * UX);
+        const int gx = 2 * X0 + fx, gy = 2 * Yw + fy;
+        if (gx < n && gy < n) {
+          const uint4 v = *reinterpret_cast<const uint4*>(st + (fy * 2 * UX + fx) * 16 + half * 8);
+          *reinterpret_cast<uint4*>(out + ((int64_t)gx + (int64_t)n * (gy + (int64_t)n * fz)) * COUT +
+                                    t * 16 + half * 8) = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// weff[p][tap][co][c] = sum of W[co][c][fine tap] over the fine taps of
+// parity class p that read coarse offset tap; wskip = the skip channels in
+// the forward layout [cout_p][28][cin - cc] (tap 27 and co >= cout zero).
+__global__ void __launch_bounds__(kBlock)
+    k_pack_split(const float* __restrict__ W, int cin, int cout, int cc, int cout_p,
+                 __bf16* __restrict__ weff, __bf16* __restrict__ wskip) {
+  const int cs = cin - cc;
+  const int64_t ne = (int64_t)8 * 8 * cout * cc;
+  const int64_t ns = (int64_t)cout_p * 28 * cs;
+  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < ne + ns;
+       q += (int64_t)gridDim.x * kBlock) {
+    if (q < ne) {
+      const int c = (int)(q % cc);
+      const int co = (int)((q / cc) % cout);
+      const int tap = (int)((q / ((int64_t)cc * cout)) % 8);
+      const int p = (int)(q / ((int64_t)cc * cout * 8));
+      const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+      const int tx = tap & 1, ty = (tap >> 1) & 1, tz = tap >> 2;
+      float s = 0.f;
+      for (int dz = -1; dz <= 1; ++dz) {
+        if (up_off(pz, dz) != tz - (pz ? 0 : 1)) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+          if (up_off(py, dy) != ty - (py ? 0 : 1)) continue;
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (up_off(px, dx) != tx - (px ? 0 : 1)) continue;
+            s += W[((int64_t)co * cin + c) * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)];
+          }
+        }
+      }
+      weff[q] = (__bf16)s;
+    } else {
+      const int64_t k = q - ne;
+      const int ci = (int)(k % cs), tap = (int)((k / cs) % 28), co = (int)(k / ((int64_t)cs * 28));
+      const float v = (co < cout && tap < 27) ? W[((int64_t)co * cin + cc + ci) * 27 + tap] : 0.f;
+      wskip[k] = (__bf16)v;
+    }
+  }
+}
+
+bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
+                _Float16* out, const int* flags) {
+  const int nc = n / 2;
+  const int blocks = ((nc + UX - 1) / UX) * ((nc + UY - 1) / UY) * nc;
+  if (cc == 32 && cout == 16) {
+    hipLaunchKernelGGL((k_upconv<32, 16>), dim3(blocks), dim3(kBlock), 0, c->stream, n, coarse,
+                       weff, out, flags);
+    return true;
+  }
+  if (cc == 64 && cout == 32) {
+    hipLaunchKernelGGL((k_upconv<64, 32>), dim3(blocks), dim3(kBlock), 0, c->stream, n, coarse,
+                       weff, out, flags);
+    return true;
+  }
+  return false;
+}
+
+void net_pack_split(sim_ctx* c, const float* W, int cin, int cout, int cc, int cout_p,
+                    __bf16* weff, __bf16* wskip) {
+  const int64_t e = (int64_t)8 * 8 * cout * cc + (int64_t)cout_p * 28 * (cin - cc);
+  const int64_t gb = (e + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_pack_split, dim3((unsigned)(gb < 4096 ? gb : 4096)), dim3(kBlock), 0,
+                     c->stream, W, cin, cout, cc, cout_p, weff, wskip);
+}
+
+}  // namespace fs

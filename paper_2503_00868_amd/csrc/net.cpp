@@ -55,6 +55,11 @@ struct UNetState {
   // weights: forward and data-gradient layouts
   __bf16* wf[11];
   __bf16* wd[11];
+  // decoder layers c7 (index 6) and c9 (index 8) in the forward pass: the
+  // upsampled half as per-parity coarse weights, the skip half separately,
+  // and the fp16 partial sums of the upsampled half (fine layout)
+  __bf16 *weff7, *wskip7, *weff9, *wskip9;
+  _Float16 *T2, *T1;
   float* dW;
   float* zbuf;
   float* Az;
@@ -113,6 +118,12 @@ size_t carve_net(int n, char* base, UNetState* s) {
     t->wf[l] = cv.take<__bf16>((size_t)L.cout_p * 28 * L.cin_p);
     t->wd[l] = cv.take<__bf16>((size_t)L.cin * 28 * L.cout_pd);
   }
+  t->weff7 = cv.take<__bf16>((size_t)8 * 8 * 32 * 64);
+  t->wskip7 = cv.take<__bf16>((size_t)32 * 28 * 32);
+  t->weff9 = cv.take<__bf16>((size_t)8 * 8 * 16 * 32);
+  t->wskip9 = cv.take<__bf16>((size_t)16 * 28 * 16);
+  t->T2 = cv.take<_Float16>(V2 * 32);
+  t->T1 = cv.take<_Float16>(V1 * 16);
   t->dW = cv.take<float>(param_total());
   t->zbuf = cv.take<float>(V1);
   t->Az = cv.take<float>(V1);
@@ -144,6 +155,19 @@ int dgrad(sim_ctx* c, int n, int l, int epi, const __bf16* G, NetOut out) {
   return SIM_OK;
 }
 
+// Concatenating layer: fp16 partial sums of the upsampled channels from the
+// coarse grid, then the skip channels' convolution adds them before the ReLU.
+int split_conv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
+               _Float16* T, NetSrc skip, const __bf16* wskip, __bf16* out, const int* flags) {
+  if (!net_upconv(c, n, cc, cout, coarse, weff, T, flags) ||
+      !net_conv(c, n, skip.ca, cout, NET_EPI_RELU_ADD, skip, wskip,
+                NetOut{out, nullptr, nullptr, nullptr, nullptr, T}, flags)) {
+    c->err = "no split convolution kernel for this channel configuration";
+    return SIM_ERR_INVALID_ARG;
+  }
+  return SIM_OK;
+}
+
 void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, float* dW) {
   const Layer& L = kLayers[l];
   net_wgrad(c, n, src, L.cin, L.cin_p, G, g_stride, L.cout, dW + param_offset(l));
@@ -164,9 +188,10 @@ int forward(sim_ctx* c, const float* r, float* z, const int* flags) {
   net_pool(c, n2, 32, s->E2, s->P2, flags);
   rc |= conv(c, n3, 4, NET_EPI_RELU, src1(s->P2, 32), out_bf(s->A3), flags);
   rc |= conv(c, n3, 5, NET_EPI_RELU, src1(s->A3, 64), out_bf(s->E3), flags);
-  rc |= conv(c, n2, 6, NET_EPI_RELU, srcup(s->E3, 64, s->E2, 32), out_bf(s->B2), flags);
+  // c7 = ReLU(upsampled half, on the coarse grid + skip half), likewise c9
+  rc |= split_conv(c, n2, 64, 32, s->E3, s->weff7, s->T2, src1(s->E2, 32), s->wskip7, s->B2, flags);
   rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32), out_bf(s->D2), flags);
-  rc |= conv(c, n1, 8, NET_EPI_RELU, srcup(s->D2, 32, s->E1, 16), out_bf(s->B1), flags);
+  rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16), s->wskip9, s->B1, flags);
   rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1), flags);
   NetOut o{nullptr, z, c->cdiag, c->scal + S_NET_RMS, nullptr};
   rc |= conv(c, n1, 10, NET_EPI_OUT, src1(s->D1, 16), o, flags);
@@ -214,6 +239,8 @@ void pack_all(sim_ctx* c, const float* master) {
     net_pack_weights(c, master + param_offset(l), L.cin, L.cout, L.cin_p, L.cout_p, L.cout_pd,
                      c->net->wf[l], c->net->wd[l]);
   }
+  net_pack_split(c, master + param_offset(6), 96, 32, 64, 32, c->net->weff7, c->net->wskip7);
+  net_pack_split(c, master + param_offset(8), 48, 16, 32, 16, c->net->weff9, c->net->wskip9);
 }
 
 }  // namespace

@@ -16,7 +16,13 @@ struct NetSrc {
   int ca, cb, up;
 };
 
-enum NetEpi { NET_EPI_RELU = 0, NET_EPI_RAW = 1, NET_EPI_MASKGRAD = 2, NET_EPI_OUT = 3 };
+enum NetEpi {
+  NET_EPI_RELU = 0,
+  NET_EPI_RAW = 1,
+  NET_EPI_MASKGRAD = 2,
+  NET_EPI_OUT = 3,
+  NET_EPI_RELU_ADD = 4  // ReLU(conv + out.add): the skip part of a concatenating layer
+};
 
 struct NetOut {
   __bf16* bf;               // bf16 output [voxel][c_out] (RELU, RAW, MASKGRAD)
@@ -24,6 +30,7 @@ struct NetOut {
   const uint8_t* mask;      // OUT: liquid where non-zero
   const double* rms;        // OUT: device scalar
   const __bf16* relu_of;    // MASKGRAD: post-activation whose ReLU the gradient passes
+  const _Float16* add;      // RELU_ADD: fp16 partial sums [voxel][c_out] added before ReLU
 };
 
 size_t net_workspace_bytes(int n);
@@ -45,6 +52,17 @@ bool net_conv(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const _
 void net_wgrad(sim_ctx* c, int n, NetSrc src, int cin_real, int cin_pad, const __bf16* G,
                int g_stride, int cout_real, float* dW);
 void net_pool(sim_ctx* c, int n, int C, const __bf16* in, __bf16* out, const int* flags);
+// Upsampled half of a concatenating layer, evaluated on the coarse grid: for
+// the fine level n, out[v][co] (fp16) = sum over taps and coarse channels of
+// the 3x3x3 convolution of up(coarse) (nearest x2), through the per-parity
+// 2x2x2 weights weff [8 parities][8 taps][cout][cc] (k_pack_subpixel).
+bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
+                _Float16* out, const int* flags);
+// Packs weff from the fp32 master weights W [cout][cin][27] of a layer whose
+// first cc input channels are the upsampled ones; and the skip channels
+// [cc, cin) into the forward layout [cout_p][28][cin - cc].
+void net_pack_split(sim_ctx* c, const float* W, int cin, int cout, int cc, int cout_p,
+                    __bf16* weff, __bf16* wskip);
 void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out, __bf16* x0,
                const int* flags);
 void net_loss_grad(sim_ctx* c, const float* r, const float* Az, const double* dots,

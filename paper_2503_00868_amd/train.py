@@ -128,7 +128,10 @@ def evaluate(weights, n=128, seeds=range(900, 908), device="cuda"):
         cell = inputs.gen_mask(n, seed)
         row = {"seed": seed}
         for pc in ("learned", "jacobi", "mic0"):
-            sim = Sim(cell, precond=pc, tol=1e-6, learned_max_iter=400, device=dev)
+            # check periods as in the benchmark: every 16 Jacobi iterations,
+            # every 4 of the (costlier) others
+            sim = Sim(cell, precond=pc, tol=1e-6, learned_max_iter=400,
+                      check_every=16 if pc == "jacobi" else 4, device=dev)
             if pc == "learned":
                 sim.net_set_weights(wt)
             u = pre_projection_field(sim, seed)
