@@ -1,0 +1,170 @@
+// First convolution of the learned preconditioner fused with its input:
+// x0 = (r / rms(r), liquid mask) -> c1 (2 -> 16 channels, 3x3x3), ReLU.
+//
+// With two input channels a K = 32 MFMA step holds 16 taps x 2 channels, so
+// the 27 taps take 2 steps per output row (instead of 15 steps of 2 taps x 16
+// zero-padded channels).  Lane (g, col) of the A operand carries voxel col and
+// k = 8g + 2j + ch, i.e. tap 16s + 4g + j, channel ch: it gathers 4 taps of
+// the (r, mask) pair, 4 bytes each, from an LDS ring of three input planes
+// (z-marching as in k_conv_zm.hip).  r and the mask are read directly from
+// the solver's arrays, so the 2-channel input tensor is never stored.
+#include "common.h"
+#include "ctx.h"
+#include "net.h"
+
+namespace fs {
+
+typedef __bf16 bf16x8i __attribute__((ext_vector_type(8)));
+typedef float f32x4i __attribute__((ext_vector_type(4)));
+
+constexpr int IT = 16;          // output tile edge in x and y
+constexpr int IR = IT + 2;      // ring plane edge with halo
+constexpr int IRV = IR * IR;    // 324 voxels per ring plane
+
+struct InGrid {
+  int zc, blocks;
+};
+
+static InGrid in_grid(int n) {
+  const int tiles = ((n + IT - 1) / IT) * ((n + IT - 1) / IT);
+  int chunks = (1024 + tiles - 1) / tiles;
+  if (chunks > n) chunks = n;
+  int zc = (n + chunks - 1) / chunks;
+  if (zc < 2) zc = 2;
+  return InGrid{zc, tiles * ((n + zc - 1) / zc)};
+}
+
+// w: packed c1 weights [16][28][8] (forward layout, channels 0 = r, 1 = mask).
+__global__ void __launch_bounds__(kBlock)
+    k_conv_in(int n, int zc, const float* __restrict__ r, const uint8_t* __restrict__ cdiag,
+              const double* __restrict__ sumsq, double n_liquid, double* __restrict__ rms_out,
+              const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  __shared__ uint32_t ring[3][IRV];  // (r / rms, mask) as two bf16
+  __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * IT * 16];
+  const double rms = n_liquid > 0.0 ? sqrt(*sumsq / n_liquid) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
+  const float inv = rms > 0.0 ? (float)(1.0 / rms) : 0.f;
+
+  const int tpr = (n + IT - 1) / IT;
+  const int tiles = tpr * tpr;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % tiles, chunk = lb / tiles;
+  const int x0 = (tile % tpr) * IT, y0 = (tile / tpr) * IT;
+  const int z0 = chunk * zc;
+  const int z1 = min(z0 + zc, n);
+  if (z0 >= n) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+
+  // B fragments: step s, k = 8g + i -> tap 16s + 4g + i/2, channel i % 2
+  bf16x8i bw[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int tap = 16 * s + 4 * g + (i >> 1);
+      bw[s][i] = tap < 27 ? w[((int64_t)col * 28 + tap) * 8 + (i & 1)] : (__bf16)0.f;
+    }
+
+  // halo plane loads: 324 voxels, two per thread at most.  The raw values
+  // stay in registers while the MFMAs of the current plane run; they are
+  // converted only when stored into the ring.
+  constexpr int PFI = (IRV + kBlock - 1) / kBlock;
+  float pr[PFI];
+  uint8_t pm[PFI];
+  bool pv_ok[PFI];
+  auto load_plane = [&](int zi) {
+#pragma unroll
+    for (int k = 0; k < PFI; ++k) {
+      const int hv = threadIdx.x + k * kBlock;
+      const int gx = x0 - 1 + hv % IR, gy = y0 - 1 + hv / IR;
+      const bool ok = hv < IRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n &&
+                      (unsigned)zi < (unsigned)n;
+      // clamped address: always a valid load, the value is dropped when !ok
+      const int64_t v = ok ? (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi) : 0;
+      pr[k] = r[v];
+      pm[k] = cdiag[v];
+      pv_ok[k] = ok;
+    }
+  };
+  auto store_plane = [&](int zi) {
+#pragma unroll
+    for (int k = 0; k < PFI; ++k) {
+      const int hv = threadIdx.x + k * kBlock;
+      if (hv < IRV) {
+        __bf16 pair[2];
+        pair[0] = (__bf16)(pv_ok[k] ? pr[k] * inv : 0.f);
+        pair[1] = (__bf16)(pv_ok[k] && pm[k] ? 1.f : 0.f);
+        ring[(zi + 3) % 3][hv] = *reinterpret_cast<const uint32_t*>(pair);
+      }
+    }
+  };
+
+  load_plane(z0 - 1);
+  store_plane(z0 - 1);
+  load_plane(z0);
+  store_plane(z0);
+  load_plane(z0 + 1);
+
+  for (int z = z0; z < z1; ++z) {
+    __syncthreads();
+    store_plane(z + 1);
+    __syncthreads();
+    if (z + 2 <= z1) load_plane(z + 2);
+
+    f32x4i acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a] = f32x4i{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        bf16x8i af;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int tap = 16 * s + 4 * g + j;
+          uint32_t pv = 0u;
+          if (tap < 27) {
+            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+            pv = ring[(z - 1 + dz + 3) % 3][(4 * wv + a + dy) * IR + col + dx];
+          }
+          const __bf16* pp = reinterpret_cast<const __bf16*>(&pv);
+          af[2 * j] = pp[0];
+          af[2 * j + 1] = pp[1];
+        }
+        acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[s], acc[a], 0, 0, 0);
+      }
+    }
+
+    // ReLU, bf16, coalesced stores through LDS (rows y0 + 4 wv + a)
+    __bf16* st = stage + wv * (4 * IT * 16);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = acc[a][i];
+        st[((a * IT) + 4 * g + i) * 16 + col] = (__bf16)(v > 0.f ? v : 0.f);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = lane + 64 * k;  // (row a, voxel, half)
+      const int lv = it >> 1, part = it & 1;
+      const int a = lv / IT, xl = lv % IT;
+      const int x = x0 + xl, y = y0 + 4 * wv + a;
+      if (x >= n || y >= n) continue;
+      const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+      *reinterpret_cast<uint4*>(out + v * 16 + part * 8) =
+          *reinterpret_cast<const uint4*>(st + lv * 16 + part * 8);
+    }
+  }
+}
+
+void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
+                 const __bf16* w, __bf16* out, const int* flags) {
+  const InGrid g = in_grid(c->n);
+  hipLaunchKernelGGL(k_conv_in, dim3(g.blocks), dim3(kBlock), 0, c->stream, c->n, g.zc, r,
+                     c->cdiag, sumsq, (double)c->n_liquid, rms_out, w, out, flags);
+}
+
+}  // namespace fs

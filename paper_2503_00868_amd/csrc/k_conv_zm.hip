@@ -58,7 +58,7 @@ static ZmGrid zm_grid(int n) {
   int chunks = (1024 + tiles - 1) / tiles;
   if (chunks > n) chunks = n;
   g.zc = (n + chunks - 1) / chunks;
-  if (g.zc < 2 && n >= 2) g.zc = 2;
+  g.zc += g.zc & 1;  // even: a block owns whole plane pairs (fused 2x2x2 pooling)
   g.nchunks = (n + g.zc - 1) / g.zc;
   g.blocks = tiles * g.nchunks;
   return g;
@@ -165,6 +165,9 @@ __global__ void __launch_bounds__(kBlock)
   load_plane(z0);
   store_plane(z0);
   load_plane(z0 + 1);
+  float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
+#pragma unroll
+  for (int e = 0; e < 8; ++e) pacc[e] = 0.f;
 
   for (int z = z0; z < z1; ++z) {
     __syncthreads();  // the compute of plane z-1 no longer reads slot (z+1) % 3
@@ -285,10 +288,45 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float v = acc[a][t][i];
-          if (EPI == NET_EPI_RELU) v = v > 0.f ? v : 0.f;
+          if (EPI == NET_EPI_RELU || EPI == NET_EPI_RELU_POOL) v = v > 0.f ? v : 0.f;
           st[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = (__bf16)v;
         }
     __syncthreads();
+    if (EPI == NET_EPI_RELU_POOL) {
+      // 2x2 in xy from the staged rows of this plane; the z pair (z even,
+      // z + 1) accumulates in pacc, the odd plane stores the average
+      constexpr int PP = COUT / 8;
+      if (lane < 2 * 8 * PP) {
+        const int part = lane % PP, cxy = lane / PP, cx = cxy % 8, cy = cxy / 8;
+        float s8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s8[e] = 0.f;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const uint4 pv = *reinterpret_cast<const uint4*>(
+                st + ((2 * cy + dy) * ZT + 2 * cx + dx) * COUT + part * 8);
+            const __bf16* pb = reinterpret_cast<const __bf16*>(&pv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s8[e] += (float)pb[e];
+          }
+        if ((z & 1) == 0) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) pacc[e] = s8[e];
+        } else {
+          const int nh = n >> 1;
+          const int px = (x0 >> 1) + cx, py = ((y0 + 4 * wv) >> 1) + cy;
+          if (px < nh && py < nh) {
+            __bf16 o8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o8[e] = (__bf16)(0.125f * (pacc[e] + s8[e]));
+            *reinterpret_cast<uint4*>(out.pool + ((int64_t)px + (int64_t)nh * (py + (int64_t)nh * (z >> 1))) * COUT + part * 8) =
+                *reinterpret_cast<const uint4*>(o8);
+          }
+        }
+      }
+    }
     constexpr int PV = COUT / 8;
 #pragma unroll
     for (int k = 0; k < (4 * ZT * PV + 63) / 64; ++k) {
@@ -333,6 +371,7 @@ static void zm_epi(sim_ctx* c, int n, int epi, NetSrc src, const __bf16* w, NetO
     case NET_EPI_RAW: zm_launch<CIN, WS, COUT, NET_EPI_RAW>(c, n, src, w, out, flags); break;
     case NET_EPI_MASKGRAD: zm_launch<CIN, WS, COUT, NET_EPI_MASKGRAD>(c, n, src, w, out, flags); break;
     case NET_EPI_RELU_ADD: zm_launch<CIN, WS, COUT, NET_EPI_RELU_ADD>(c, n, src, w, out, flags); break;
+    case NET_EPI_RELU_POOL: zm_launch<CIN, WS, COUT, NET_EPI_RELU_POOL>(c, n, src, w, out, flags); break;
     default: zm_launch<CIN, WS, COUT, NET_EPI_OUT>(c, n, src, w, out, flags); break;
   }
 }

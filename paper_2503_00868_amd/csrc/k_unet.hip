@@ -408,7 +408,8 @@ static void conv_launch(sim_ctx* c, int n, NetSrc src, const __bf16* w, NetOut o
 bool net_conv(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const __bf16* w,
               NetOut out, const int* flags) {
   if (net_conv_zm(c, n, cin, cout, epi, src, w, out, flags)) return true;
-  if (epi == NET_EPI_RELU_ADD) return false;  // only the z-marching kernels add partial sums
+  // only the z-marching kernels add partial sums or pool
+  if (epi == NET_EPI_RELU_ADD || epi == NET_EPI_RELU_POOL) return false;
 #define FS_CONV(CI, CO, CK)                                                   \
   if (cin == CI && cout == CO) {                                              \
     if (epi == NET_EPI_RELU) conv_launch<CI, CO, CK, NET_EPI_RELU>(c, n, src, w, out, flags);        \

@@ -14,9 +14,8 @@
 //
 // MFMA mapping (16x16x32 bf16): M = 16 coarse voxels along X, N = 16 output
 // channels, K = 32 coarse channels of one coarse tap offset.  A wave owns 4
-// coarse rows; for each of the 27 coarse offsets it loads the 4 row
-// fragments once and issues them against the weights of every parity class
-// that uses the offset (8 x 8 x 4 MFMAs per 64 coarse voxels).
+// coarse rows and issues 8 parities x 8 taps x 4 rows MFMAs per K-step and
+// 64 coarse voxels.
 #include "common.h"
 #include "ctx.h"
 #include "net.h"
@@ -33,105 +32,139 @@ constexpr int UY = 16;   // coarse rows per block (4 waves)
 // Coarse offset of fine tap d (-1, 0, 1) for parity q (0, 1).
 __host__ __device__ constexpr int up_off(int q, int d) { return (q + d + 2) / 2 - 1; }
 
+struct UpGrid {
+  int zr, blocks;
+};
+
+static UpGrid up_grid(int nc) {
+  const int tiles = ((nc + UX - 1) / UX) * ((nc + UY - 1) / UY);
+  int runs = (1024 + tiles - 1) / tiles;
+  if (runs > nc) runs = nc;
+  const int zr = (nc + runs - 1) / runs;
+  return UpGrid{zr, tiles * ((nc + zr - 1) / zr)};
+}
+
+// A block owns a 16 x 16 coarse tile and a run of zr coarse planes.  For each
+// 16-channel output group the group's per-parity weights are staged in LDS
+// once (8 x 8 x 16 x CC bf16), then every plane of the run is computed: per
+// (ox, oz, K-step) a wave loads the 6 coarse rows its 4 output rows need and
+// reuses them for the three oy offsets and every parity class using them.
 template <int CC, int COUT>
 __global__ void __launch_bounds__(kBlock)
-    k_upconv(int n, const __bf16* __restrict__ coarse, const __bf16* __restrict__ weff,
+    k_upconv(int n, int zr, const __bf16* __restrict__ coarse, const __bf16* __restrict__ weff,
              _Float16* __restrict__ out, const int* __restrict__ flags) {
   if (flags && flags[F_DONE]) return;
   static_assert(CC % 32 == 0 && COUT % 16 == 0, "channel counts");
   constexpr int KS = CC / 32;
   constexpr int NT = COUT / 16;
-  __shared__ __attribute__((aligned(16))) _Float16 stage[4][8 * 2 * UX * 16];
+  constexpr int WL = 8 * 8 * 16 * CC;  // bf16 of one output group's weights
+  __shared__ __attribute__((aligned(16))) __bf16 wl[WL];
+  __shared__ __attribute__((aligned(16))) _Float16 stage[4][UR * 2 * UX * 16];
   const int nc = n / 2;
   const int tx = (nc + UX - 1) / UX, ty = (nc + UY - 1) / UY;
-  const int b = blockIdx.x;
-  const int X0 = (b % tx) * UX;
-  const int Y0 = ((b / tx) % ty) * UY;
-  const int Z = b / (tx * ty);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % (tx * ty), run = lb / (tx * ty);
+  const int X0 = (tile % tx) * UX, Y0 = (tile / tx) * UY;
+  const int Z0 = run * zr, Z1 = min(Z0 + zr, nc);
+  if (Z0 >= nc) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   const int Yw = Y0 + UR * wv;
 
 #pragma unroll 1
   for (int t = 0; t < NT; ++t) {
-    f32x4u acc[8][UR];
+    __syncthreads();  // the previous group's weights are no longer read
+    for (int q = threadIdx.x; q < WL / 8; q += kBlock) {
+      const int e = q * 8;  // [p*8 + tap][col][c] -> global [p*8 + tap][t*16 + col][c]
+      const int c = e % CC, cl = (e / CC) % 16, pt = e / (CC * 16);
+      *reinterpret_cast<uint4*>(wl + e) = *reinterpret_cast<const uint4*>(
+          weff + ((int64_t)pt * COUT + t * 16 + cl) * CC + c);
+    }
+    __syncthreads();
+
+#pragma unroll 1
+    for (int Z = Z0; Z < Z1; ++Z) {
+      f32x4u acc[8][UR];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
+      for (int p = 0; p < 8; ++p)
 #pragma unroll
-      for (int r = 0; r < UR; ++r) acc[p][r] = f32x4u{0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < UR; ++r) acc[p][r] = f32x4u{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll
-    for (int oz = -1; oz <= 1; ++oz)
-#pragma unroll
-      for (int oy = -1; oy <= 1; ++oy)
+      for (int oz = -1; oz <= 1; ++oz)
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox)
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) {
-            bf16x8u a[UR];
+            // rows Yw-1 .. Yw+4 of coarse plane Z+oz, shifted by ox.  Branch-free:
+            // out-of-volume rows load a clamped (valid) address and are zeroed
+            // by a select, so the scheduler can issue these loads early.
+            bf16x8u f[UR + 2];
             const int cx = X0 + col + ox, cz = Z + oz;
+            const bool xz_ok = (unsigned)cx < (unsigned)nc && (unsigned)cz < (unsigned)nc;
 #pragma unroll
-            for (int r = 0; r < UR; ++r) {
-              const int cy = Yw + r + oy;
-              if ((unsigned)cx < (unsigned)nc && (unsigned)cy < (unsigned)nc &&
-                  (unsigned)cz < (unsigned)nc) {
-                a[r] = *reinterpret_cast<const bf16x8u*>(
-                    coarse + ((int64_t)cx + (int64_t)nc * (cy + (int64_t)nc * cz)) * CC + ks * 32 + 8 * g);
-              } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) a[r][e] = (__bf16)0.f;
-              }
+            for (int rr = 0; rr < UR + 2; ++rr) {
+              const int cy = Yw + rr - 1;
+              const bool ok = xz_ok && (unsigned)cy < (unsigned)nc;
+              const int64_t v = ok ? (int64_t)cx + (int64_t)nc * (cy + (int64_t)nc * cz) : 0;
+              const uint4 raw = *reinterpret_cast<const uint4*>(coarse + v * CC + ks * 32 + 8 * g);
+              const uint4 val = ok ? raw : make_uint4(0u, 0u, 0u, 0u);
+              f[rr] = *reinterpret_cast<const bf16x8u*>(&val);
             }
 #pragma unroll
-            for (int pz = 0; pz < 2; ++pz) {
-              if (oz == (pz ? -1 : 1)) continue;  // parity 0 never reads +1, parity 1 never -1
+            for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
-              for (int py = 0; py < 2; ++py) {
-                if (oy == (py ? -1 : 1)) continue;
+              for (int pz = 0; pz < 2; ++pz) {
+                if (oz == (pz ? -1 : 1)) continue;  // parity 0 never reads +1, parity 1 never -1
 #pragma unroll
-                for (int px = 0; px < 2; ++px) {
-                  if (ox == (px ? -1 : 1)) continue;
-                  const int p = px + 2 * py + 4 * pz;
-                  const int tap = (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
-                  const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
-                      weff + ((int64_t)(p * 8 + tap) * COUT + t * 16 + col) * CC + ks * 32 + 8 * g);
+                for (int py = 0; py < 2; ++py) {
+                  if (oy == (py ? -1 : 1)) continue;
 #pragma unroll
-                  for (int r = 0; r < UR; ++r)
-                    acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bw, acc[p][r], 0, 0, 0);
+                  for (int px = 0; px < 2; ++px) {
+                    if (ox == (px ? -1 : 1)) continue;
+                    const int p = px + 2 * py + 4 * pz;
+                    const int tap =
+                        (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
+                    const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
+                        wl + ((p * 8 + tap) * 16 + col) * CC + ks * 32 + 8 * g);
+#pragma unroll
+                    for (int r = 0; r < UR; ++r)
+                      acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[r + oy + 1], bw,
+                                                                          acc[p][r], 0, 0, 0);
+                  }
                 }
               }
-            }
           }
 
-    // epilogue: one fine z-plane (pz) at a time through LDS, as rows of 2*UX
-    // fine voxels x 16 channels
+      // epilogue: one fine (y-parity, z-parity) slab at a time through LDS,
+      // as UR rows of 2*UX fine voxels x 16 channels
 #pragma unroll
-    for (int pz = 0; pz < 2; ++pz) {
-      _Float16* st = stage[wv];
+      for (int pz = 0; pz < 2; ++pz)
 #pragma unroll
-      for (int py = 0; py < 2; ++py)
+        for (int py = 0; py < 2; ++py) {
+          _Float16* st = stage[wv];
 #pragma unroll
-        for (int px = 0; px < 2; ++px)
+          for (int px = 0; px < 2; ++px)
 #pragma unroll
-          for (int r = 0; r < UR; ++r)
+            for (int r = 0; r < UR; ++r)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int fx = 2 * (4 * g + i) + px, fy = 2 * r + py;
-              st[(fy * 2 * UX + fx) * 16 + col] = (_Float16)acc[px + 2 * py + 4 * pz][r][i];
+              for (int i = 0; i < 4; ++i)
+                st[(r * 2 * UX + 2 * (4 * g + i) + px) * 16 + col] =
+                    (_Float16)acc[px + 2 * py + 4 * pz][r][i];
+          __syncthreads();
+          const int fz = 2 * Z + pz;
+#pragma unroll
+          for (int k = 0; k < (UR * 2 * UX * 2) / 64; ++k) {
+            const int it = lane + 64 * k;  // (row, fx, half)
+            const int half = it & 1, fx = (it >> 1) % (2 * UX), r = (it >> 1) / (2 * UX);
+            const int gx = 2 * X0 + fx, gy = 2 * (Yw + r) + py;
+            if (gx < n && gy < n) {
+              const uint4 v = *reinterpret_cast<const uint4*>(st + (r * 2 * UX + fx) * 16 + half * 8);
+              *reinterpret_cast<uint4*>(out + ((int64_t)gx + (int64_t)n * (gy + (int64_t)n * fz)) * COUT +
+                                        t * 16 + half * 8) = v;
             }
-      __syncthreads();
-      const int fz = 2 * Z + pz;
-#pragma unroll
-      for (int k = 0; k < (8 * 2 * UX * 2) / 64; ++k) {
-        const int it = lane + 64 * k;  // (fy, fx, half)
-        const int half = it & 1, fx = (it >> 1) % (2 * UX), fy = (it >> 1) / (2 * UX);
-        const int gx = 2 * X0 + fx, gy = 2 * Yw + fy;
-        if (gx < n && gy < n) {
-          const uint4 v = *reinterpret_cast<const uint4*>(st + (fy * 2 * UX + fx) * 16 + half * 8);
-          *reinterpret_cast<uint4*>(out + ((int64_t)gx + (int64_t)n * (gy + (int64_t)n * fz)) * COUT +
-                                    t * 16 + half * 8) = v;
+          }
+          __syncthreads();
         }
-      }
-      __syncthreads();
     }
   }
 }
@@ -177,16 +210,15 @@ __global__ void __launch_bounds__(kBlock)
 
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
                 _Float16* out, const int* flags) {
-  const int nc = n / 2;
-  const int blocks = ((nc + UX - 1) / UX) * ((nc + UY - 1) / UY) * nc;
+  const UpGrid ug = up_grid(n / 2);
   if (cc == 32 && cout == 16) {
-    hipLaunchKernelGGL((k_upconv<32, 16>), dim3(blocks), dim3(kBlock), 0, c->stream, n, coarse,
-                       weff, out, flags);
+    hipLaunchKernelGGL((k_upconv<32, 16>), dim3(ug.blocks), dim3(kBlock), 0, c->stream, n, ug.zr,
+                       coarse, weff, out, flags);
     return true;
   }
   if (cc == 64 && cout == 32) {
-    hipLaunchKernelGGL((k_upconv<64, 32>), dim3(blocks), dim3(kBlock), 0, c->stream, n, coarse,
-                       weff, out, flags);
+    hipLaunchKernelGGL((k_upconv<64, 32>), dim3(ug.blocks), dim3(kBlock), 0, c->stream, n, ug.zr,
+                       coarse, weff, out, flags);
     return true;
   }
   return false;

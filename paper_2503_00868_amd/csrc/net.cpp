@@ -135,6 +135,9 @@ NetSrc srcup(const __bf16* coarse, int cc, const __bf16* skip, int cs) {
   return NetSrc{coarse, skip, cc, cs, 1};
 }
 NetOut out_bf(__bf16* p) { return NetOut{p, nullptr, nullptr, nullptr, nullptr}; }
+NetOut out_pool(__bf16* p, __bf16* pooled) {
+  return NetOut{p, nullptr, nullptr, nullptr, nullptr, nullptr, pooled};
+}
 NetOut out_mask(__bf16* p, const __bf16* relu_of) { return NetOut{p, nullptr, nullptr, nullptr, relu_of}; }
 
 int conv(sim_ctx* c, int n, int l, int epi, NetSrc src, NetOut out, const int* flags) {
@@ -174,18 +177,23 @@ void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, 
 }
 
 // U-Net forward pass into z (fp32, n^3); activations stay in the workspace.
-int forward(sim_ctx* c, const float* r, float* z, const int* flags) {
+// keep_input: store the 2-channel input tensor (the weight gradient of c1
+// reads it); otherwise c1 reads r and the mask directly.
+int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_input) {
   UNetState* s = c->net;
   const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
   launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
-  net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
   int rc = SIM_OK;
-  rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
-  rc |= conv(c, n1, 1, NET_EPI_RELU, src1(s->A1, 16), out_bf(s->E1), flags);
-  net_pool(c, n1, 16, s->E1, s->P1, flags);
+  if (keep_input) {
+    net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
+    rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
+  } else {
+    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags);
+  }
+  // c2 and c4 also write the 2x2x2 average pool of their output
+  rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1), flags);
   rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2), flags);
-  rc |= conv(c, n2, 3, NET_EPI_RELU, src1(s->A2, 32), out_bf(s->E2), flags);
-  net_pool(c, n2, 32, s->E2, s->P2, flags);
+  rc |= conv(c, n2, 3, NET_EPI_RELU_POOL, src1(s->A2, 32), out_pool(s->E2, s->P2), flags);
   rc |= conv(c, n3, 4, NET_EPI_RELU, src1(s->P2, 32), out_bf(s->A3), flags);
   rc |= conv(c, n3, 5, NET_EPI_RELU, src1(s->A3, 64), out_bf(s->E3), flags);
   // c7 = ReLU(upsampled half, on the coarse grid + skip half), likewise c9
@@ -264,7 +272,7 @@ bool net_ready(const sim_ctx* c) { return c->net && c->net->ready; }
 
 int net_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
   prof_mark(c, SIM_KERN_NET, true);
-  int rc = forward(c, r, z, flags);
+  int rc = forward(c, r, z, flags, false);
   prof_mark(c, SIM_KERN_NET, false);
   return rc;
 }
@@ -324,7 +332,7 @@ static int batch_grad(sim_ctx* c, const float* r, const float* e, int batch, dou
   for (int b = 0; b < batch; ++b) {
     const float* rb = r + (int64_t)b * c->C;
     const float* eb = e + (int64_t)b * c->C;
-    int rc = forward(c, rb, s->zbuf, nullptr);
+    int rc = forward(c, rb, s->zbuf, nullptr, true);
     if (rc) return rc;
     launch_poisson_apply(c, s->zbuf, s->Az);
     launch_dot_cells_slot(c, rb, s->zbuf, S_NET_RZ, nullptr);

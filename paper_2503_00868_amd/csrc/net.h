@@ -21,7 +21,8 @@ enum NetEpi {
   NET_EPI_RAW = 1,
   NET_EPI_MASKGRAD = 2,
   NET_EPI_OUT = 3,
-  NET_EPI_RELU_ADD = 4  // ReLU(conv + out.add): the skip part of a concatenating layer
+  NET_EPI_RELU_ADD = 4,  // ReLU(conv + out.add): the skip part of a concatenating layer
+  NET_EPI_RELU_POOL = 5  // ReLU, and the 2x2x2 average of the output into out.pool
 };
 
 struct NetOut {
@@ -31,6 +32,7 @@ struct NetOut {
   const double* rms;        // OUT: device scalar
   const __bf16* relu_of;    // MASKGRAD: post-activation whose ReLU the gradient passes
   const _Float16* add;      // RELU_ADD: fp16 partial sums [voxel][c_out] added before ReLU
+  __bf16* pool;             // RELU_POOL: pooled output at half resolution [voxel][c_out]
 };
 
 size_t net_workspace_bytes(int n);
@@ -65,6 +67,10 @@ void net_pack_split(sim_ctx* c, const float* W, int cin, int cout, int cc, int c
                     __bf16* weff, __bf16* wskip);
 void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out, __bf16* x0,
                const int* flags);
+// c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
+// rms written to rms_out; the 2-channel input is never stored
+void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
+                 const __bf16* w, __bf16* out, const int* flags);
 void net_loss_grad(sim_ctx* c, const float* r, const float* Az, const double* dots,
                    const double* rms, __bf16* g11);
 void net_upsum_mask(sim_ctx* c, int n_fine, int Cc, int Ct, const __bf16* T, const __bf16* P,
