@@ -55,7 +55,7 @@ typedef struct sim_ctx sim_ctx; /* opaque, host memory owned by the library */
 
 enum {
     SIM_OK = 0,
-    SIM_OK_FALLBACK = 1,           /* converged, but the learned solve fell back to MIC(0) */
+    SIM_OK_FALLBACK = 1,           /* converged, but the learned solve fell back to Jacobi-PCG */
     SIM_ERR_INVALID_ARG = -1,
     SIM_ERR_WORKSPACE_TOO_SMALL = -2,
     SIM_ERR_HIP = -3,
@@ -78,7 +78,9 @@ typedef struct {
                                   iterations) */
     int32_t checkpoint_every;  /* K: rollout checkpoint spacing for sim_backward, >= 1 */
     int32_t max_steps;         /* longest recordable rollout (0 = no recording) */
-    int32_t learned_max_iter;  /* flexible-CG iterations before the MIC(0) restart */
+    int32_t learned_max_iter;  /* flexible-CG iterations before the Jacobi-PCG restart (it also
+                                  restarts on breakdown, or when the residual falls by less
+                                  than a factor 0.9 per iteration between two checks) */
     double tol;                /* relative L2 true residual of the pressure solve, (0, 1) */
     double diff_tol;           /* same for the implicit viscosity solve, (0, 1) */
     int32_t warm_start;        /* 1: each pressure solve of a rollout starts from the previous
@@ -101,7 +103,7 @@ typedef struct {
     int32_t status;            /* SIM_* code of this step or solve */
     int32_t iters;             /* pressure (F)CG iterations, including any fallback */
     int32_t diff_iters;        /* implicit viscosity CG iterations (0 if explicit) */
-    int32_t fallback_used;     /* 1 if the learned solve restarted with MIC(0) */
+    int32_t fallback_used;     /* 1 if the learned solve restarted with Jacobi-PCG */
     double rel_residual;       /* final FP64 true relative residual of the pressure */
     double diff_rel_residual;  /* same for the viscosity solve */
 } sim_stats;

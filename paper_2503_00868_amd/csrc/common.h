@@ -71,6 +71,14 @@ __device__ inline int xcd_logical_block(int b, int nblocks) {
   return prefix + b / nx;
 }
 
+// Orders LDS traffic between the lanes of one wave (a wave's LDS operations
+// execute in order; this keeps the compiler from moving them across).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over a block of kBlock threads; result valid in thread 0.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV]) {

@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kBlock)
               const double* __restrict__ sumsq, double n_liquid, double* __restrict__ rms_out,
               const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags) {
   if (flags && flags[F_DONE]) return;
-  __shared__ uint32_t ring[3][IRV];  // (r / rms, mask) as two bf16
+  __shared__ uint32_t ring[4][IRV];  // (r / rms, mask) as two bf16; four slots as in k_conv_zm
   __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * IT * 16];
   const double rms = n_liquid > 0.0 ? sqrt(*sumsq / n_liquid) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kBlock)
         __bf16 pair[2];
         pair[0] = (__bf16)(pv_ok[k] ? pr[k] * inv : 0.f);
         pair[1] = (__bf16)(pv_ok[k] && pm[k] ? 1.f : 0.f);
-        ring[(zi + 3) % 3][hv] = *reinterpret_cast<const uint32_t*>(pair);
+        ring[(zi + 4) & 3][hv] = *reinterpret_cast<const uint32_t*>(pair);
       }
     }
   };
@@ -107,7 +107,6 @@ __global__ void __launch_bounds__(kBlock)
   load_plane(z0 + 1);
 
   for (int z = z0; z < z1; ++z) {
-    __syncthreads();
     store_plane(z + 1);
     __syncthreads();
     if (z + 2 <= z1) load_plane(z + 2);
@@ -126,7 +125,7 @@ __global__ void __launch_bounds__(kBlock)
           uint32_t pv = 0u;
           if (tap < 27) {
             const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-            pv = ring[(z - 1 + dz + 3) % 3][(4 * wv + a + dy) * IR + col + dx];
+            pv = ring[(z + 3 + dz) & 3][(4 * wv + a + dy) * IR + col + dx];
           }
           const __bf16* pp = reinterpret_cast<const __bf16*>(&pv);
           af[2 * j] = pp[0];
@@ -145,7 +144,7 @@ __global__ void __launch_bounds__(kBlock)
         const float v = acc[a][i];
         st[((a * IT) + 4 * g + i) * 16 + col] = (__bf16)(v > 0.f ? v : 0.f);
       }
-    __syncthreads();
+    wave_sync();  // per-wave staging
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int it = lane + 64 * k;  // (row a, voxel, half)

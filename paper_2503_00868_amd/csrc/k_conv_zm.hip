@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
   constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
   constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
-  __shared__ __attribute__((aligned(16))) __bf16 ring[3 * SLOT];
+  // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
+  // compute of plane z-2) needs no barrier of its own
+  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   constexpr int STAGE_BYTES = 4 * 4 * ZT * COUT * (EPI == NET_EPI_RELU_ADD ? 4 : 2);
   __shared__ __attribute__((aligned(16))) char stage_raw[STAGE_BYTES];
   __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(kBlock)
     }
   };
   auto store_plane = [&](int zi) {
-    __bf16* slot = ring + ((zi + 3) % 3) * SLOT;
+    __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * kBlock;
@@ -170,7 +172,6 @@ __global__ void __launch_bounds__(kBlock)
   for (int e = 0; e < 8; ++e) pacc[e] = 0.f;
 
   for (int z = z0; z < z1; ++z) {
-    __syncthreads();  // the compute of plane z-1 no longer reads slot (z+1) % 3
     store_plane(z + 1);
     __syncthreads();
     if (z + 2 <= z1) load_plane(z + 2);
@@ -186,9 +187,9 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
 
-    const __bf16* sm = ring + ((z - 1 + 3) % 3) * SLOT;  // plane z-1 (dz = 0)
-    const __bf16* s0 = ring + ((z + 3) % 3) * SLOT;      // plane z   (dz = 1)
-    const __bf16* sp = ring + ((z + 1 + 3) % 3) * SLOT;  // plane z+1 (dz = 2)
+    const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
+    const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
+    const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
     const int half = (g & 1) * 8;
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
           for (int i = 0; i < 4; ++i) so[a * 16 + 4 * g + i] = acc[a][0][i];
       }
-      __syncthreads();
+      wave_sync();  // per-wave staging
       if (own)
         out.f32[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)] =
             own_mask ? rms_f * so[lane] : 0.f;
@@ -256,7 +257,7 @@ __global__ void __launch_bounds__(kBlock)
         for (int t = 0; t < NT; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = acc[a][t][i];
-      __syncthreads();
+      wave_sync();  // per-wave staging
       constexpr int PV8 = COUT / 8;
 #pragma unroll
       for (int k = 0; k < (4 * ZT * PV8 + 63) / 64; ++k) {
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(kBlock)
           if (EPI == NET_EPI_RELU || EPI == NET_EPI_RELU_POOL) v = v > 0.f ? v : 0.f;
           st[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = (__bf16)v;
         }
-    __syncthreads();
+    wave_sync();  // per-wave staging
     if (EPI == NET_EPI_RELU_POOL) {
       // 2x2 in xy from the staged rows of this plane; the z pair (z even,
       // z + 1) accumulates in pacc, the odd plane stores the average

@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kBlock)
               for (int i = 0; i < 4; ++i)
                 st[(r * 2 * UX + 2 * (4 * g + i) + px) * 16 + col] =
                     (_Float16)acc[px + 2 * py + 4 * pz][r][i];
-          __syncthreads();
+          wave_sync();  // per-wave staging
           const int fz = 2 * Z + pz;
 #pragma unroll
           for (int k = 0; k < (UR * 2 * UX * 2) / 64; ++k) {
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kBlock)
                                         t * 16 + half * 8) = v;
             }
           }
-          __syncthreads();
+          wave_sync();
         }
     }
   }

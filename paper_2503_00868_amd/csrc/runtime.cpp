@@ -113,7 +113,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->dD = d.precond == SIM_PRECOND_JACOBI ? cv.take<float>(C) : nullptr;
   t->q = cv.take<float>(C);
   t->b = cv.take<float>(C);
-  const bool mic = d.precond == SIM_PRECOND_MIC0 || d.precond == SIM_PRECOND_LEARNED;
+  const bool mic = d.precond == SIM_PRECOND_MIC0;
   t->precon = mic ? cv.take<float>(C) : nullptr;
   t->mq = mic ? cv.take<float>(C) : nullptr;
   t->rprev = d.precond == SIM_PRECOND_LEARNED ? cv.take<float>(C) : nullptr;
@@ -282,10 +282,15 @@ struct LoopResult {
   int done;
   int iters;
   double rr, bb;
+  bool stalled;  // stopped early: the residual fell too slowly (see run_blocks)
 };
 
+// min_rate (0: off): stop early when, between two consecutive checks, the
+// true residual norm fell by less than a factor min_rate per iteration
+// (the block already enqueued still runs).
 template <typename Block>
-int run_blocks(sim_ctx* c, int m, int max_iter, Block block, LoopResult& res) {
+int run_blocks(sim_ctx* c, int m, int max_iter, Block block, LoopResult& res,
+               double min_rate = 0.0) {
   hipEvent_t ev[2];
   HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -294,6 +299,9 @@ int run_blocks(sim_ctx* c, int m, int max_iter, Block block, LoopResult& res) {
     (void)hipEventDestroy(ev[1]);
   };
   int enq = 0, blk = 0;
+  double rr_prev = -1.0;
+  int it_prev = 0;
+  res.stalled = false;
   for (;;) {
     int todo = std::min(m, max_iter - enq);
     block(todo);
@@ -308,7 +316,19 @@ int run_blocks(sim_ctx* c, int m, int max_iter, Block block, LoopResult& res) {
     HIPCHK(hipEventRecord(ev[blk & 1], c->stream));
     if (blk >= 1) {
       HIPCHK(hipEventSynchronize(ev[(blk - 1) & 1]));
-      if (host_slot(c, (blk - 1) & 1)->f[F_DONE]) break;
+      const HostCtrl* hp = host_slot(c, (blk - 1) & 1);
+      if (hp->f[F_DONE]) break;
+      if (min_rate > 0.0) {
+        const double rr = hp->s[S_RR];
+        const int it = hp->f[F_ITERS];
+        if (rr_prev > 0.0 && it > it_prev &&
+            std::pow(rr / rr_prev, 0.5 / (double)(it - it_prev)) > min_rate) {
+          res.stalled = true;
+          break;
+        }
+        rr_prev = rr;
+        it_prev = it;
+      }
     }
     if (enq >= max_iter) break;
     ++blk;
@@ -410,8 +430,14 @@ int pcg_solve(sim_ctx* c, int prec_kind, int start, const double* x0, sim_stats*
   return lr.status;
 }
 
-// Flexible CG with the learned preconditioner; on breakdown or after
-// learned_max_iter iterations it restarts MIC(0)-PCG from the current x.
+// Below this residual reduction per iteration the network does not pay for
+// itself: one application costs about 20 Jacobi-PCG iterations, so even a
+// factor 0.9 per iteration is slower than Jacobi-PCG on large grids.
+constexpr double kFcgMinRate = 0.9;
+
+// Flexible CG with the learned preconditioner.  On breakdown, after
+// learned_max_iter iterations, or when the residual stalls (kFcgMinRate),
+// it restarts Jacobi-PCG from the current x.
 int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   launch_fcg_init(c);
   if (x0) start_from_guess(c, PK_ZARRAY, x0);
@@ -435,7 +461,7 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   };
   LoopResult lr{};
   rc = run_blocks(c, c->desc.check_every, std::min(c->desc.learned_max_iter, c->desc.max_iter),
-                  block, lr);
+                  block, lr, kFcgMinRate);
   if (rc) return rc;
   if (inner_rc) return inner_rc;
   if (st) {
@@ -443,18 +469,21 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
     st->rel_residual = relres_of(lr);
   }
   if (lr.done == 1) return SIM_OK;
-  // fallback: MIC(0)-PCG from the current iterate, judged by the same FP64 check
+  // fallback: Jacobi-PCG from the current iterate, judged by the same FP64
+  // check (on this chip it beats MIC(0)-PCG, whose hyperplane sweeps are
+  // latency-bound, from 64^3 up)
   if (st) st->fallback_used = 1;
   HIPCHK(hipMemsetAsync(c->flags, 0, sizeof(int) * F_COUNT, c->stream));
-  rc = pcg_solve(c, PK_ZARRAY, START_CURRENT, nullptr, st);
+  rc = pcg_solve(c, PK_JACOBI, START_CURRENT, nullptr, st);
   if (rc == SIM_OK) return SIM_OK_FALLBACK;
   return rc;
 }
 
 // x0 (nullable): starting iterate.
+// A learned context without weights solves with Jacobi-PCG.
 int poisson_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   if (c->desc.precond == SIM_PRECOND_LEARNED && net_ready(c)) return fcg_solve(c, x0, st);
-  return pcg_solve(c, c->desc.precond == SIM_PRECOND_JACOBI ? PK_JACOBI : PK_ZARRAY,
+  return pcg_solve(c, c->desc.precond == SIM_PRECOND_MIC0 ? PK_ZARRAY : PK_JACOBI,
                    x0 ? START_GUESS : START_ZERO, x0, st);
 }
 

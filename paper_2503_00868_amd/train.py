@@ -46,11 +46,31 @@ def pre_projection_field(sim, seed):
     return d
 
 
-def harvest(sim, seed, iters=HARVEST_ITERS, tol=1e-10, mode=0):
+def rough_field(sim, seed):
+    """A right-hand side unlike a physical step's: white noise on the faces
+    under a Gaussian envelope (seeded centre and width 0.05-0.3), so the
+    network also sees localized, high-frequency residuals (the adjoint
+    solves of long rollouts produce such right-hand sides)."""
+    rng = np.random.default_rng([seed, 11])
+    n = sim.n
+    ctr = rng.uniform(0.2, 0.8, size=3)
+    sig = rng.uniform(0.05, 0.3)
+    fields = []
+    for c in range(3):
+        shape = [(n, n, n + 1), (n, n + 1, n), (n + 1, n, n)][c]
+        ax = [(np.arange(s) + (0.0 if s == n + 1 else 0.5)) / n for s in shape]  # z, y, x
+        z, y, x = np.meshgrid(*ax, indexing="ij")
+        env = np.exp(-((x - ctr[0]) ** 2 + (y - ctr[1]) ** 2 + (z - ctr[2]) ** 2) / (2 * sig * sig))
+        fields.append((rng.standard_normal(shape) * env).astype(np.float32))
+    return sim.to_faces(fields)
+
+
+def harvest(sim, seed, iters=HARVEST_ITERS, tol=1e-10, mode=0, rough=False):
     """Pairs (r_k, e_k) from one seeded volume on a context with that volume's
     mask: mode 0 from Jacobi-PCG iterates, mode 1 from the iterates of the
-    flexible CG with the network's current weights."""
-    u = pre_projection_field(sim, seed)
+    flexible CG with the network's current weights; rough: the right-hand
+    side comes from rough_field instead of a physical step."""
+    u = rough_field(sim, seed) if rough else pre_projection_field(sim, seed)
     return sim.harvest_pairs(u, list(iters), tol=tol, mode=mode)
 
 
@@ -66,7 +86,7 @@ def usable_pairs(R, E, rel_floor=1e-7):
 
 def train(n=128, seeds=range(1000, 1400), lr=1e-3, lr_final=1e-4, init_seed=0, out=None,
           device="cuda", log_every=25, max_seconds=None, weights=None,
-          plain_iters=(0, 12, 48), policy_iters=(1, 3, 8, 16, 32, 64)):
+          plain_iters=(0, 12, 48), policy_iters=(1, 3, 8, 16, 32, 64), rough_every=0):
     """On-policy training: every volume contributes pairs from Jacobi-PCG
     iterates and from the flexible CG driven by the current network, whose
     residuals are the ones the network meets when it preconditions."""
@@ -83,8 +103,11 @@ def train(n=128, seeds=range(1000, 1400), lr=1e-3, lr_final=1e-4, init_seed=0, o
         cell = inputs.gen_mask(n, seed)
         sim = Sim(cell, precond="learned", tol=1e-6, max_iter=40000, device=dev)
         sim.net_set_weights(master)
-        R0, E0, st = harvest(sim, seed, plain_iters, mode=0)
-        R1, E1, st1 = harvest(sim, seed, policy_iters, mode=1)
+        rough = rough_every > 0 and step % rough_every == 0
+        if rough:
+            sim.set_params(nu=1e-3, dt=DT, s=1.0)
+        R0, E0, st = harvest(sim, seed, plain_iters, mode=0, rough=rough)
+        R1, E1, st1 = harvest(sim, seed, policy_iters, mode=1, rough=rough)
         if st1["fallback_used"]:  # the flexible CG broke down: keep the plain pairs only
             R, E = R0, E0
         else:
