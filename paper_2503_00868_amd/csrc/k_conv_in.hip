@@ -87,7 +87,8 @@ __global__ void __launch_bounds__(kBlock)
       pv_ok[k] = ok;
     }
   };
-  auto store_plane = [&](int zi) {
+  auto store_plane = [&](int zi) -> int {
+    uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < PFI; ++k) {
       const int hv = threadIdx.x + k * kBlock;
@@ -95,27 +96,34 @@ __global__ void __launch_bounds__(kBlock)
         __bf16 pair[2];
         pair[0] = (__bf16)(pv_ok[k] ? pr[k] * inv : 0.f);
         pair[1] = (__bf16)(pv_ok[k] && pm[k] ? 1.f : 0.f);
-        ring[(zi + 4) & 3][hv] = *reinterpret_cast<const uint32_t*>(pair);
+        const uint32_t bits = *reinterpret_cast<const uint32_t*>(pair);
+        ring[(zi + 4) & 3][hv] = bits;
+        any |= bits;
       }
     }
+    return any != 0u;
   };
 
+  // all-zero neighbourhoods (air far from liquid) skip the MFMAs, as in
+  // k_conv_zm
   load_plane(z0 - 1);
-  store_plane(z0 - 1);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1));
   load_plane(z0);
-  store_plane(z0);
+  int nz_0 = __syncthreads_or(store_plane(z0));
   load_plane(z0 + 1);
 
   for (int z = z0; z < z1; ++z) {
-    store_plane(z + 1);
-    __syncthreads();
+    const int nz_p = __syncthreads_or(store_plane(z + 1));
     if (z + 2 <= z1) load_plane(z + 2);
+    const bool work = (nz_m | nz_0 | nz_p) != 0;
+    nz_m = nz_0;
+    nz_0 = nz_p;
 
     f32x4i acc[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) acc[a] = f32x4i{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < (work ? 2 : 0); ++s) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         bf16x8i af;

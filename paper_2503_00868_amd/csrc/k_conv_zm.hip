@@ -144,16 +144,21 @@ __global__ void __launch_bounds__(kBlock)
       pf[k] = val;
     }
   };
-  auto store_plane = [&](int zi) {
+  // stores the prefetched plane; returns whether this thread's part of it
+  // holds any non-zero bit
+  auto store_plane = [&](int zi) -> int {
     __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
+    uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * kBlock;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
         *reinterpret_cast<uint4*>(slot + ((p >> 1) * ZRV + hv) * 16 + (p & 1) * 8) = pf[k];
+        any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
       }
     }
+    return any != 0u;
   };
 
   // output layer: rms once per block; each lane owns one voxel of its wave's
@@ -162,19 +167,24 @@ __global__ void __launch_bounds__(kBlock)
   const int oy = y0 + 4 * wv + (lane >> 4), ox = x0 + (lane & 15);
   const bool own = ox < n && oy < n;
 
+  // A bias-free network maps an all-zero input neighbourhood to zero, so the
+  // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
+  // halo) are all zero; the flags come with the barrier after each store.
   load_plane(z0 - 1);
-  store_plane(z0 - 1);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1));
   load_plane(z0);
-  store_plane(z0);
+  int nz_0 = __syncthreads_or(store_plane(z0));
   load_plane(z0 + 1);
   float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
 #pragma unroll
   for (int e = 0; e < 8; ++e) pacc[e] = 0.f;
 
   for (int z = z0; z < z1; ++z) {
-    store_plane(z + 1);
-    __syncthreads();
+    const int nz_p = __syncthreads_or(store_plane(z + 1));
     if (z + 2 <= z1) load_plane(z + 2);
+    const bool work = (nz_m | nz_0 | nz_p) != 0;
+    nz_m = nz_0;
+    nz_0 = nz_p;
 
     // issued before the MFMAs, consumed in the epilogue
     uint8_t own_mask = 0;
@@ -192,7 +202,7 @@ __global__ void __launch_bounds__(kBlock)
     const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
     const int half = (g & 1) * 8;
 #pragma unroll
-    for (int q = 0; q < NCH; ++q) {
+    for (int q = 0; q < (work ? NCH : 0); ++q) {
       // groups 0-2: dx = 0..2, taps dz 0 | dz 1
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
