@@ -107,12 +107,13 @@ def copy_probe(mib):
     log(f"copy probe: 20 copies of {mib} MiB")
 
 
-def load_traffic(kind, n):
-    """HBM bytes per launch of `kind` at n^3 from the committed counter
-    summary, or None when there is none or the kernel source changed since
-    the counters were taken (the summary stores the source's SHA-256)."""
+def load_traffic(kind, n, precond):
+    """HBM bytes per launch of `kind` at n^3 with this pressure
+    preconditioner, from the committed counter summary; None when there is
+    none or a kernel source changed since the counters were taken (the
+    summary stores each source's SHA-256)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kind}_{n}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{precond}_{n}_traffic.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -122,10 +123,10 @@ def load_traffic(kind, n):
                 rec = json.loads(line.split(":", 1)[1])
     if not rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    for src, sha in rec["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
     return rec["bytes_per_launch"]
 
 
@@ -166,7 +167,7 @@ def rooflines(prof, n, precond):
         achieved = per_launch / avg_s / 1e9
         return {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(kind, n), "avg_us": round(avg_s * 1e6, 2),
+                "traffic": load_traffic(kind, n, precond), "avg_us": round(avg_s * 1e6, 2),
                 "launches": launches, "bytes_per_launch": per_launch}
 
     kinds = {k: v for k, v in prof.items() if k in BYTES_PER_UNIT and v[1] > 0}
@@ -178,7 +179,7 @@ def rooflines(prof, n, precond):
         achieved = flop / avg_s / 1e12
         return ({"bound": "mfma", "kernel": "net", "achieved": round(achieved, 1),
                  "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                 "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": load_traffic("net", n, precond),
                  "avg_us": round(avg_s * 1e6, 1), "launches": net_launches,
                  "flop_per_launch": flop}, r_hbm)
     return r_hbm, None
