@@ -87,6 +87,10 @@ typedef struct {
                                   step's pressure, each adjoint solve of sim_backward from the
                                   previous adjoint solve's (the stopping test, relative to the
                                   right-hand side, is unchanged); 0: every solve starts at 0 */
+    int32_t store_pressures;   /* 1 (needs max_steps > 0): a recorded rollout also keeps each
+                                  step's FP64 pressure (max_steps x n^3 doubles of workspace),
+                                  and sim_backward's recompute starts every projection from it,
+                                  so those solves stop at their first check with no iteration */
 } sim_desc;
 
 /* Dynamic parameters (sim_set_params).  Density is 1: the solver works with

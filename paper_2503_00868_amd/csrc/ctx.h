@@ -116,6 +116,7 @@ struct sim_ctx {
   // rollout recording
   float* ckpt = nullptr;  // (ckpt_slots) x 3F
   double* ckpt_x = nullptr;  // warm start: (ckpt_slots) x C pressures at the checkpoints
+  double* xhist = nullptr;   // store_pressures: max_steps x C pressures of the recorded steps
   int ckpt_slots = 0;
   float* seg = nullptr;  // (2 * checkpoint_every) x 3F: state and diffusion operand per step
   int rec_steps = 0;

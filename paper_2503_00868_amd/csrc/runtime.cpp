@@ -136,11 +136,13 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt_slots = (d.max_steps + d.checkpoint_every - 1) / d.checkpoint_every;
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
     t->ckpt_x = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
+    t->xhist = d.store_pressures ? cv.take<double>((size_t)d.max_steps * C) : nullptr;
     t->seg = cv.take<float>((size_t)2 * d.checkpoint_every * F3n);
   } else {
     t->ckpt_slots = 0;
     t->ckpt = nullptr;
     t->ckpt_x = nullptr;
+    t->xhist = nullptr;
     t->seg = nullptr;
   }
   if (d.precond == SIM_PRECOND_LEARNED) {
@@ -172,6 +174,8 @@ const char* validate_desc(const sim_desc* d) {
   if (!(d->tol > 0.0 && d->tol < 1.0)) return "tol must be in (0, 1)";
   if (!(d->diff_tol > 0.0 && d->diff_tol < 1.0)) return "diff_tol must be in (0, 1)";
   if (d->warm_start != 0 && d->warm_start != 1) return "warm_start must be 0 or 1";
+  if (d->store_pressures != 0 && d->store_pressures != 1) return "store_pressures must be 0 or 1";
+  if (d->store_pressures && d->max_steps == 0) return "store_pressures needs max_steps > 0";
   return nullptr;
 }
 
@@ -352,11 +356,12 @@ double relres_of(const LoopResult& r) { return r.bb > 0 ? std::sqrt(r.rr / r.bb)
 enum Start { START_ZERO, START_GUESS, START_CURRENT };
 
 // x = x0 (FP64 copy) after the zero-start setup, then r = b - A x through the
-// FP64 check (tolerance 0: it only stops when r is exactly zero).  With b = 0
-// the setup has already raised the done flag and x stays 0.
+// FP64 check with the solve's tolerance: a guess that already meets it ends
+// the solve with no iteration.  With b = 0 the setup has already raised the
+// done flag and x stays 0.
 void start_from_guess(sim_ctx* c, int prec_kind, const double* x0) {
   launch_x_to_double(c, x0, c->x, c->flags);
-  launch_pcg_check(c, prec_kind, 0.0);
+  launch_pcg_check(c, prec_kind, c->desc.tol);
 }
 
 // PCG on the Poisson matrix with rhs c->b, result in c->x.  Jacobi is fused
@@ -779,6 +784,7 @@ int sim_step(sim_ctx* c, float* u, float* v, float* w, int32_t nsteps, int32_t r
     if (stats) stats[s] = st;
     worst = combine(worst, rc);
     if (rc < 0) return rc;
+    if (record && c->xhist) launch_x_to_double(c, c->x, c->xhist + (int64_t)s * c->C);
   }
   if (record) c->recorded = 1;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -878,7 +884,8 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
           launch_copy_faces(c, cstacked(c, c->tmp), op);
         else
           launch_copy_faces(c, cf3(nxt.c[0], nxt.c[1], nxt.c[2]), op);
-        rc = project_inplace(c, nxt, nullptr, c->xw);
+        // the forward's own pressure (stored) or its warm start
+        rc = project_inplace(c, nxt, nullptr, c->xhist ? c->xhist + (int64_t)s * c->C : c->xw);
         worst = combine(worst, rc);
         if (rc < 0) return rc;
       } else {

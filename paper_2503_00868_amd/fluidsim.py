@@ -39,7 +39,7 @@ class sim_desc(ctypes.Structure):
     _fields_ = [("n", c_int32), ("precond", c_int32), ("diffusion", c_int32),
                 ("max_iter", c_int32), ("check_every", c_int32), ("checkpoint_every", c_int32),
                 ("max_steps", c_int32), ("learned_max_iter", c_int32), ("tol", c_double),
-                ("diff_tol", c_double), ("warm_start", c_int32)]
+                ("diff_tol", c_double), ("warm_start", c_int32), ("store_pressures", c_int32)]
 
 
 class sim_params(ctypes.Structure):
@@ -149,12 +149,13 @@ def sim_create(desc: sim_desc, cell_host: np.ndarray, workspace, stream_handle: 
 
 def make_desc(n, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6, max_iter=20000,
               check_every=8, checkpoint_every=8, max_steps=0, learned_max_iter=200,
-              warm_start=False):
+              warm_start=False, store_pressures=False):
     return sim_desc(n=n, precond=PRECONDS[precond] if isinstance(precond, str) else precond,
                     diffusion=DIFFUSIONS[diffusion] if isinstance(diffusion, str) else diffusion,
                     max_iter=max_iter, check_every=check_every, checkpoint_every=checkpoint_every,
                     max_steps=max_steps, learned_max_iter=learned_max_iter, tol=tol,
-                    diff_tol=diff_tol, warm_start=int(bool(warm_start)))
+                    diff_tol=diff_tol, warm_start=int(bool(warm_start)),
+                    store_pressures=int(bool(store_pressures)))
 
 
 def face_shapes(n):
@@ -167,14 +168,15 @@ class Sim:
 
     def __init__(self, cell, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6,
                  max_iter=20000, check_every=8, checkpoint_every=8, max_steps=0,
-                 learned_max_iter=200, warm_start=False, device="cuda"):
+                 learned_max_iter=200, warm_start=False, store_pressures=False, device="cuda"):
         import torch
         self.torch = torch
         cell = np.ascontiguousarray(cell, dtype=np.uint8)
         self.n = n = cell.shape[0]
         self.device = torch.device(device)
         self.desc = make_desc(n, precond, diffusion, tol, diff_tol, max_iter, check_every,
-                              checkpoint_every, max_steps, learned_max_iter, warm_start)
+                              checkpoint_every, max_steps, learned_max_iter, warm_start,
+                              store_pressures)
         size = sim_workspace_size(self.desc)
         self.ws = torch.empty(size, dtype=torch.uint8, device=self.device)
         assert self.ws.data_ptr() % 256 == 0

@@ -56,6 +56,18 @@ def test_workspace_size_rejects_bad_warm_start():
     d = _desc()
     d.warm_start = 2
     assert _ws_size(d)[0] == fsb.SIM_ERR_INVALID_ARG
+    d = _desc()
+    d.store_pressures = 2
+    assert _ws_size(d)[0] == fsb.SIM_ERR_INVALID_ARG
+    # the pressure history belongs to a recorded rollout
+    assert _ws_size(_desc(max_steps=0, store_pressures=True))[0] == fsb.SIM_ERR_INVALID_ARG
+
+
+def test_workspace_size_pressure_history():
+    n = 16
+    _, rec = _ws_size(_desc(max_steps=8))
+    _, hist = _ws_size(_desc(max_steps=8, store_pressures=True))
+    assert hist - rec >= 8 * 8 * n ** 3
 
 
 def test_workspace_size_grows_with_recording_and_precond():
