@@ -72,10 +72,11 @@ typedef struct {
     int32_t n;                 /* cells per axis, 4 <= n <= 1024; n % 4 == 0 for LEARNED */
     int32_t precond;           /* SIM_PRECOND_* for the pressure solve */
     int32_t diffusion;         /* SIM_DIFFUSION_*; AUTO = explicit iff nu*dt*n^2 <= 1/12 */
-    int32_t max_iter;          /* per solve, >= 1 (Jacobi: rounded up to a multiple of 4) */
-    int32_t check_every;       /* FP64 true-residual check period m, 1..1024 (Jacobi: rounded
-                                  up to a multiple of 4; it updates the FP64 iterate every 4
-                                  iterations) */
+    int32_t max_iter;          /* per solve, >= 1 (Jacobi and learned: rounded up to a
+                                  multiple of 4) */
+    int32_t check_every;       /* FP64 true-residual check period m, 1..1024 (Jacobi and
+                                  learned: rounded up to a multiple of 4; they update the FP64
+                                  iterate every 4 iterations) */
     int32_t checkpoint_every;  /* K: rollout checkpoint spacing for sim_backward, >= 1 */
     int32_t max_steps;         /* longest recordable rollout (0 = no recording) */
     int32_t learned_max_iter;  /* flexible-CG iterations before the Jacobi-PCG restart (it also

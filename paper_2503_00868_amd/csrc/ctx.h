@@ -167,6 +167,8 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
 // iteration % 4; dirs[0..3] are the directions of iterations phase-3..phase
 // of the current group (only dirs[3] is read before phase 3).
 void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
+// the same four-step iterate update for the flexible CG (alpha = d.r / d.q)
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);

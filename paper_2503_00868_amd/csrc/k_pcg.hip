@@ -659,7 +659,8 @@ __global__ void __launch_bounds__(kBlock)
 // three iterations of a group of four are kept in scal, and on the fourth
 // x += a0 d0 + a1 d1 + a2 d2 + a3 d3 in FP64 (one read-modify-write of x per
 // four iterations).
-template <int V, bool WITH_X>
+// FLEX: the flexible CG's step alpha = d.r / d.q, and no r.z partials.
+template <int V, bool WITH_X, bool FLEX>
 __global__ void __launch_bounds__(kBlock)
     k_update4(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
               float* __restrict__ r, const float* __restrict__ d0, const float* __restrict__ d1,
@@ -668,7 +669,7 @@ __global__ void __launch_bounds__(kBlock)
               const int* __restrict__ flags, double* partials) {
   if (flags[F_DONE]) return;
   const int64_t G = cells(n) / V;
-  const double alpha = scal[S_RZ] / scal[S_DQ];
+  const double alpha = (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
   const float alpha_f = (float)alpha;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const Run run = group_run(G, gridDim.x, lb);
@@ -703,11 +704,11 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       rv[e] -= alpha_f * qv[e];
-      v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+      if (!FLEX) v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
     }
     stf<V>(r + idx, rv);
   }
-  store_partials<1>(v, partials, lb);
+  if (!FLEX) store_partials<1>(v, partials, lb);
   if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_Q0 + phase] = alpha;
 }
 
@@ -994,12 +995,21 @@ void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
              phase, c->flags, c->partials
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   if (phase == 3)
-    FS_CELL_LAUNCH(k_update4, true);
+    FS_CELL_LAUNCH(k_update4, true, false);
   else
-    FS_CELL_LAUNCH(k_update4, false);
+    FS_CELL_LAUNCH(k_update4, false, false);
+  prof_mark(c, SIM_KERN_PCG_UPDATE, false);
+  launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
+}
+
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
+  prof_mark(c, SIM_KERN_PCG_UPDATE, true);
+  if (phase == 3)
+    FS_CELL_LAUNCH(k_update4, true, true);
+  else
+    FS_CELL_LAUNCH(k_update4, false, true);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
 #undef ARGS
-  launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }
 
 void launch_pcg_rz_first(sim_ctx* c, int first) {

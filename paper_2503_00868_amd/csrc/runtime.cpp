@@ -109,8 +109,9 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->z = cv.take<float>(C);
   t->dA = cv.take<float>(C);
   t->dB = cv.take<float>(C);
-  t->dC = d.precond == SIM_PRECOND_JACOBI ? cv.take<float>(C) : nullptr;
-  t->dD = d.precond == SIM_PRECOND_JACOBI ? cv.take<float>(C) : nullptr;
+  const bool four = d.precond == SIM_PRECOND_JACOBI || d.precond == SIM_PRECOND_LEARNED;
+  t->dC = four ? cv.take<float>(C) : nullptr;
+  t->dD = four ? cv.take<float>(C) : nullptr;
   t->q = cv.take<float>(C);
   t->b = cv.take<float>(C);
   const bool mic = d.precond == SIM_PRECOND_MIC0;
@@ -449,24 +450,28 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   int rc = net_apply(c, c->r, c->z, c->flags);
   if (rc) return rc;
   launch_fcg_beta_first(c, 1);
-  float* din = c->dA;
-  float* dout = c->dB;
+  // the FP64 iterate is updated every fourth iteration from four rotating
+  // direction buffers (as in Jacobi-PCG), so blocks hold multiples of 4
   const double tol = c->desc.tol;
   int inner_rc = SIM_OK;
+  float* const dbuf[4] = {c->dA, c->dB, c->dC, c->dD};
+  int it = 0;
   auto block = [&](int todo) {
-    for (int t = 0; t < todo; ++t) {
-      launch_fcg_dir_spmv(c, din, dout);
-      launch_fcg_update(c, dout);
+    for (int t = 0; t < todo; ++t, ++it) {
+      const int ph = it & 3;
+      launch_fcg_dir_spmv(c, dbuf[ph], dbuf[(ph + 1) & 3]);
+      const float* dirs[4] = {dbuf[(ph + 2) & 3], dbuf[(ph + 3) & 3], dbuf[ph], dbuf[(ph + 1) & 3]};
+      launch_fcg_update4(c, dirs, ph);
       if (t == todo - 1) launch_fcg_check(c, tol);
       int r2 = net_apply(c, c->r, c->z, c->flags);
       if (r2) inner_rc = r2;
       launch_fcg_beta(c);
-      std::swap(din, dout);
     }
   };
+  const int m = (c->desc.check_every + 3) / 4 * 4;
+  const int max_it = (std::min(c->desc.learned_max_iter, c->desc.max_iter) + 3) / 4 * 4;
   LoopResult lr{};
-  rc = run_blocks(c, c->desc.check_every, std::min(c->desc.learned_max_iter, c->desc.max_iter),
-                  block, lr, kFcgMinRate);
+  rc = run_blocks(c, m, max_it, block, lr, kFcgMinRate);
   if (rc) return rc;
   if (inner_rc) return inner_rc;
   if (st) {
