@@ -166,7 +166,7 @@ def rooflines(prof, n, precond):
         ms_tot, launches = prof[kind]
         units = F3 if kind in FACE_KINDS else C
         per_unit = BYTES_PER_UNIT[kind]
-        if kind == "pcg_update" and precond != "jacobi":
+        if kind == "pcg_update" and precond == "mic0":
             per_unit = 33.0
         per_launch = per_unit * units
         avg_s = ms_tot / launches / 1e3
