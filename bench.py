@@ -40,10 +40,10 @@ BF16_PEAK_TFLOPS = 2500.0
 # timed kernel kind: every array the operation must read or write once.
 BYTES_PER_UNIT = {
     "pcg_dir_spmv": 17.0,   # r 4 + diag 1 + d 4 in; d 4 + q 4 out
-    # Jacobi PCG updates the FP64 iterate every fourth iteration: three of
-    # four iterations move r 4+4, q 4, diag 1 (13 B), the fourth also x 8+8
-    # and four directions 4x4 (45 B); the average is 21 B.  (33 B for
-    # MIC(0)/learned, which update x every iteration.)
+    # Jacobi PCG and the flexible CG update the FP64 iterate every fourth
+    # iteration: three of four iterations move r 4+4, q 4, diag 1 (13 B), the
+    # fourth also x 8+8 and four directions 4x4 (45 B); the average is 21 B.
+    # (MIC(0)-PCG updates x every iteration: 33 B.)
     "pcg_update": 21.0,
     "pcg_check": 17.0,      # x 8, b 4, diag 1 in; r 4 out
     "advect": 9.0,          # own component 4 + face code 1 in; 4 out (per face)
