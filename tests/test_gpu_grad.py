@@ -55,16 +55,17 @@ def test_gradient_matches_oracle(torch_gpu, orc, mode, nu_t, nu_e, K, warm):
 @pytest.mark.parametrize("mode", ["explicit", "implicit"])
 def test_pressure_history_gives_the_same_gradient(torch_gpu, mode):
     """With store_pressures the backward's recompute starts each projection
-    from the forward's own pressure (no iteration); the recomputed states,
-    hence the gradient, are bitwise those of the recompute that repeats the
-    warm-started solves."""
+    from the forward's own pressure (no iteration).  The recomputed states
+    are those of the recompute that repeats the warm-started solves, so the
+    gradients agree to the run-to-run noise of the advection adjoint's FP32
+    atomic scatter (1e-6 relative here; two identical runs differ likewise)."""
     from paper_2503_00868_amd.fluidsim import Sim
     banner(f"pressure history, {mode}")
     n, steps, K = 20, 5, 2
     nu = 4e-3 if mode == "explicit" else 8e-2
     cell, ug = case(n, 100, 2.0)
     out = []
-    for store in (False, True):
+    for store in (False, True, False):
         sim = Sim(cell, precond="jacobi", diffusion=mode, tol=1e-8, max_steps=steps,
                   checkpoint_every=K, warm_start=True, store_pressures=store)
         sim.set_params(nu=nu, dt=DT, s=0.9)
@@ -75,9 +76,11 @@ def test_pressure_history_gives_the_same_gradient(torch_gpu, mode):
         J, gT = sim.loss_mse(u, sim.faces())
         g0, dnu, ds, _ = sim.backward(gT, ugen=ugen)
         out.append((dnu, ds, to_np(g0)))
-    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
-    for a, b in zip(out[0][2], out[1][2]):
-        assert np.array_equal(a, b)
+    for other in (out[1], out[2]):
+        assert abs(out[0][0] - other[0]) <= 1e-6 * abs(out[0][0])
+        assert abs(out[0][1] - other[1]) <= 1e-6 * abs(out[0][1])
+        l2, _ = rel_err(other[2], out[0][2])
+        assert l2 <= 1e-6, l2
 
 
 def test_gradient_fd_sanity_on_gpu(torch_gpu, orc):
