@@ -89,9 +89,12 @@ typedef struct {
                                   previous adjoint solve's (the stopping test, relative to the
                                   right-hand side, is unchanged); 0: every solve starts at 0 */
     int32_t store_pressures;   /* 1 (needs max_steps > 0): a recorded rollout also keeps each
-                                  step's FP64 pressure (max_steps x n^3 doubles of workspace),
-                                  and sim_backward's recompute starts every projection from it,
-                                  so those solves stop at their first check with no iteration */
+                                  step's FP64 pressure (max_steps x n^3 doubles of workspace)
+                                  and, unless diffusion is EXPLICIT, its implicit viscosity
+                                  output (max_steps x 3 x (n+1) n^2 floats).  sim_backward's
+                                  recompute then starts every projection from the stored
+                                  pressure (the solve stops at its first check with no
+                                  iteration) and takes the viscosity output as stored */
 } sim_desc;
 
 /* Dynamic parameters (sim_set_params).  Density is 1: the solver works with

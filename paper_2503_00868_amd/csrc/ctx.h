@@ -117,6 +117,7 @@ struct sim_ctx {
   float* ckpt = nullptr;  // (ckpt_slots) x 3F
   double* ckpt_x = nullptr;  // warm start: (ckpt_slots) x C pressures at the checkpoints
   double* xhist = nullptr;   // store_pressures: max_steps x C pressures of the recorded steps
+  float* vhist = nullptr;    // store_pressures: max_steps x 3F implicit viscosity outputs
   int ckpt_slots = 0;
   float* seg = nullptr;  // (2 * checkpoint_every) x 3F: state and diffusion operand per step
   int rec_steps = 0;

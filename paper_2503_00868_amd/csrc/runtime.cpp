@@ -138,12 +138,16 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
     t->ckpt_x = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
     t->xhist = d.store_pressures ? cv.take<double>((size_t)d.max_steps * C) : nullptr;
+    t->vhist = d.store_pressures && d.diffusion != SIM_DIFFUSION_EXPLICIT
+                   ? cv.take<float>((size_t)d.max_steps * F3n)
+                   : nullptr;
     t->seg = cv.take<float>((size_t)2 * d.checkpoint_every * F3n);
   } else {
     t->ckpt_slots = 0;
     t->ckpt = nullptr;
     t->ckpt_x = nullptr;
     t->xhist = nullptr;
+    t->vhist = nullptr;
     t->seg = nullptr;
   }
   if (d.precond == SIM_PRECOND_LEARNED) {
@@ -570,10 +574,15 @@ void advect_force(sim_ctx* c, CF3 in, F3 out) {
 }
 
 // One step in place: advect (+force) -> viscosity -> projection.
-int step_once(sim_ctx* c, F3 u, sim_stats* st) {
+// rec_step >= 0: a recorded step whose implicit viscosity output is kept in
+// the history (store_pressures).
+int step_once(sim_ctx* c, F3 u, sim_stats* st, int rec_step = -1) {
   advect_force(c, cf3(u.c[0], u.c[1], u.c[2]), stacked(c, c->tmp));
   int rc = diffuse_into(c, u, st);
   if (rc) return rc;
+  if (rec_step >= 0 && c->vhist && !diffusion_explicit(c))
+    launch_copy_faces(c, cf3(u.c[0], u.c[1], u.c[2]),
+                      stacked(c, c->vhist + (int64_t)rec_step * 3 * c->F));
   return project_inplace(c, u, st, c->xw);
 }
 
@@ -784,7 +793,7 @@ int sim_step(sim_ctx* c, float* u, float* v, float* w, int32_t nsteps, int32_t r
       if (c->ckpt_x) launch_x_to_double(c, c->xw, c->ckpt_x + (int64_t)(s / K) * c->C);
     }
     sim_stats st{};
-    int rc = step_once(c, U, &st);
+    int rc = step_once(c, U, &st, record ? s : -1);
     st.status = rc;
     if (stats) stats[s] = st;
     worst = combine(worst, rc);
@@ -876,26 +885,36 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
     launch_copy_faces(c, cstacked(c, c->ckpt + (int64_t)(s0 / K) * F3n), stacked(c, state0));
     // the recompute repeats the forward solves from the same starting iterates
     if (c->ckpt_x) launch_x_to_double(c, c->ckpt_x + (int64_t)(s0 / K) * c->C, c->xw);
+    // with the history, the implicit viscosity outputs are the forward's own
+    // (copied: no advection, no viscosity solve)
+    const bool have_visc = c->vhist && !explicit_d;
     for (int s = s0; s < s1; ++s) {
       const int q = s - s0;
       F3 us = stacked(c, c->seg + (int64_t)q * F3n);
       F3 op = stacked(c, c->seg + (int64_t)(K + q) * F3n);
-      advect_force(c, cf3(us.c[0], us.c[1], us.c[2]), stacked(c, c->tmp));
+      const float* vs = have_visc ? c->vhist + (int64_t)s * F3n : nullptr;
+      if (!have_visc) advect_force(c, cf3(us.c[0], us.c[1], us.c[2]), stacked(c, c->tmp));
       if (s + 1 < s1) {
         F3 nxt = stacked(c, c->seg + (int64_t)(q + 1) * F3n);
-        int rc = diffuse_into(c, nxt, nullptr);
-        if (rc) return rc;
+        if (have_visc) {
+          launch_copy_faces(c, cstacked(c, vs), nxt);
+        } else {
+          int rc = diffuse_into(c, nxt, nullptr);
+          if (rc) return rc;
+        }
         if (explicit_d)
           launch_copy_faces(c, cstacked(c, c->tmp), op);
         else
           launch_copy_faces(c, cf3(nxt.c[0], nxt.c[1], nxt.c[2]), op);
         // the forward's own pressure (stored) or its warm start
-        rc = project_inplace(c, nxt, nullptr, c->xhist ? c->xhist + (int64_t)s * c->C : c->xw);
+        const int rc = project_inplace(c, nxt, nullptr, c->xhist ? c->xhist + (int64_t)s * c->C : c->xw);
         worst = combine(worst, rc);
         if (rc < 0) return rc;
       } else {
         if (explicit_d) {
           launch_copy_faces(c, cstacked(c, c->tmp), op);
+        } else if (have_visc) {
+          launch_copy_faces(c, cstacked(c, vs), op);
         } else {
           int rc = diffuse_into(c, op, nullptr);
           if (rc) return rc;

@@ -55,7 +55,8 @@ def test_gradient_matches_oracle(torch_gpu, orc, mode, nu_t, nu_e, K, warm):
 @pytest.mark.parametrize("mode", ["explicit", "implicit"])
 def test_pressure_history_gives_the_same_gradient(torch_gpu, mode):
     """With store_pressures the backward's recompute starts each projection
-    from the forward's own pressure (no iteration).  The recomputed states
+    from the forward's own pressure (no iteration) and, for implicit
+    viscosity, copies the forward's viscosity output.  The recomputed states
     are those of the recompute that repeats the warm-started solves, so the
     gradients agree to the run-to-run noise of the advection adjoint's FP32
     atomic scatter (1e-6 relative here; two identical runs differ likewise)."""
