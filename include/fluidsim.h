@@ -177,6 +177,18 @@ int sim_net_param_count(int64_t* count);
 int sim_net_set_weights(sim_ctx* ctx, const float* d_weights, int64_t count);
 int sim_net_forward(sim_ctx* ctx, const float* d_r, float* d_z);
 
+/* Zero-tile skipping of the network's inference pass (default on).  The
+ * network is bias-free and its input vanishes off liquid, so each activation
+ * is zero beyond a fixed distance of the liquid (at most 23 fine cells; the
+ * receptive-field count is in the implementation).  At creation the library
+ * marks, per level, the 16 x 16 tiles of each plane that come within 24 fine
+ * cells of liquid; with skipping on, the inference kernels neither load nor
+ * store the other tiles, which hold zeros.  Results are bitwise those of the
+ * dense pass (on = 0); the switch exists to check exactly that.  d_r passed
+ * to sim_net_forward (or met in the solver) is read on liquid cells only.
+ * Returns SIM_ERR_STATE for a context without the learned preconditioner. */
+int sim_net_set_tile_skip(sim_ctx* ctx, int32_t on);
+
 /* Loss and weight gradient of the U-Net with its current weights on a batch
  * of (r, e) pairs, e = A^-1 r (cell arrays, batch-major, zero off liquid):
  * loss = mean over the batch of 1 - (r.z)^2 / ((r.e)(z.Az)), the squared sine

@@ -20,6 +20,7 @@ typedef float f32x4i __attribute__((ext_vector_type(4)));
 constexpr int IT = 16;          // output tile edge in x and y
 constexpr int IR = IT + 2;      // ring plane edge with halo
 constexpr int IRV = IR * IR;    // 324 voxels per ring plane
+constexpr int IMAXC = 128;      // planes per block at most
 
 struct InGrid {
   int zc, blocks;
@@ -27,10 +28,13 @@ struct InGrid {
 
 static InGrid in_grid(int n) {
   const int tiles = ((n + IT - 1) / IT) * ((n + IT - 1) / IT);
-  int chunks = (1024 + tiles - 1) / tiles;
+  // shorter z-runs on large grids, as in k_conv_zm
+  const int target = tiles >= 256 ? 4096 : 1024;
+  int chunks = (target + tiles - 1) / tiles;
   if (chunks > n) chunks = n;
   int zc = (n + chunks - 1) / chunks;
   if (zc < 2) zc = 2;
+  if (zc > IMAXC) zc = IMAXC;
   return InGrid{zc, tiles * ((n + zc - 1) / zc)};
 }
 
@@ -38,7 +42,8 @@ static InGrid in_grid(int n) {
 __global__ void __launch_bounds__(kBlock)
     k_conv_in(int n, int zc, const float* __restrict__ r, const uint8_t* __restrict__ cdiag,
               const double* __restrict__ sumsq, double n_liquid, double* __restrict__ rms_out,
-              const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags) {
+              const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags,
+              const uint8_t* __restrict__ act) {
   if (flags && flags[F_DONE]) return;
   __shared__ uint32_t ring[4][IRV];  // (r / rms, mask) as two bf16; four slots as in k_conv_zm
   __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * IT * 16];
@@ -55,6 +60,19 @@ __global__ void __launch_bounds__(kBlock)
   const int z1 = min(z0 + zc, n);
   if (z0 >= n) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  // tile-plane activity (block-uniform) of planes z0-1 .. z1+1, as in
+  // k_conv_zm
+  __shared__ uint8_t live_s[IMAXC + 3];
+  if (act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
+      const int zi = z0 - 1 + t;
+      live_s[t] = (unsigned)zi < (unsigned)n ? act[(int64_t)zi * tiles + tile] : 0;
+      any |= t >= 1 && t <= z1 - z0 && live_s[t];
+    }
+    if (!__syncthreads_or(any)) return;  // no live output plane
+  }
+  auto live = [&](int zi) -> bool { return !act || live_s[zi - z0 + 1] != 0; };
 
   // B fragments: step s, k = 8g + i -> tap 16s + 4g + i/2, channel i % 2
   bf16x8i bw[2];
@@ -70,32 +88,37 @@ __global__ void __launch_bounds__(kBlock)
   // stay in registers while the MFMAs of the current plane run; they are
   // converted only when stored into the ring.
   constexpr int PFI = (IRV + kBlock - 1) / kBlock;
-  float pr[PFI];
-  uint8_t pm[PFI];
-  bool pv_ok[PFI];
-  auto load_plane = [&](int zi) {
+  struct Raw {
+    float r[PFI];
+    uint8_t m[PFI];
+    bool ok[PFI];
+  };
+  Raw ra;
+  auto load_plane = [&](int zi, Raw& o) {
+    const bool on = live(zi);
 #pragma unroll
     for (int k = 0; k < PFI; ++k) {
       const int hv = threadIdx.x + k * kBlock;
       const int gx = x0 - 1 + hv % IR, gy = y0 - 1 + hv / IR;
-      const bool ok = hv < IRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n &&
+      const bool ok = on && hv < IRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n &&
                       (unsigned)zi < (unsigned)n;
       // clamped address: always a valid load, the value is dropped when !ok
       const int64_t v = ok ? (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi) : 0;
-      pr[k] = r[v];
-      pm[k] = cdiag[v];
-      pv_ok[k] = ok;
+      o.r[k] = r[v];
+      o.m[k] = cdiag[v];
+      o.ok[k] = ok;
     }
   };
-  auto store_plane = [&](int zi) -> int {
+  auto store_plane = [&](int zi, const Raw& o) -> int {
     uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < PFI; ++k) {
       const int hv = threadIdx.x + k * kBlock;
       if (hv < IRV) {
         __bf16 pair[2];
-        pair[0] = (__bf16)(pv_ok[k] ? pr[k] * inv : 0.f);
-        pair[1] = (__bf16)(pv_ok[k] && pm[k] ? 1.f : 0.f);
+        // r is read on liquid cells only
+        pair[0] = (__bf16)(o.ok[k] && o.m[k] ? o.r[k] * inv : 0.f);
+        pair[1] = (__bf16)(o.ok[k] && o.m[k] ? 1.f : 0.f);
         const uint32_t bits = *reinterpret_cast<const uint32_t*>(pair);
         ring[(zi + 4) & 3][hv] = bits;
         any |= bits;
@@ -106,18 +129,21 @@ __global__ void __launch_bounds__(kBlock)
 
   // all-zero neighbourhoods (air far from liquid) skip the MFMAs, as in
   // k_conv_zm
-  load_plane(z0 - 1);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1));
-  load_plane(z0);
-  int nz_0 = __syncthreads_or(store_plane(z0));
-  load_plane(z0 + 1);
+  load_plane(z0 - 1, ra);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1, ra));
+  load_plane(z0, ra);
+  int nz_0 = __syncthreads_or(store_plane(z0, ra));
+  load_plane(z0 + 1, ra);
 
-  for (int z = z0; z < z1; ++z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1));
-    if (z + 2 <= z1) load_plane(z + 2);
+  // one output plane: plane z+1 goes to the ring, plane z+2 is loaded while
+  // the MFMAs of plane z run
+  auto plane_step = [&](int z) {
+    const int nz_p = __syncthreads_or(store_plane(z + 1, ra));
+    if (z + 2 <= z1) load_plane(z + 2, ra);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
     nz_0 = nz_p;
+    if (!live(z)) return;  // zero output plane: nothing to store
 
     f32x4i acc[4];
 #pragma unroll
@@ -164,14 +190,15 @@ __global__ void __launch_bounds__(kBlock)
       *reinterpret_cast<uint4*>(out + v * 16 + part * 8) =
           *reinterpret_cast<const uint4*>(st + lv * 16 + part * 8);
     }
-  }
+  };
+  for (int z = z0; z < z1; ++z) plane_step(z);
 }
 
 void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
-                 const __bf16* w, __bf16* out, const int* flags) {
+                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act) {
   const InGrid g = in_grid(c->n);
   hipLaunchKernelGGL(k_conv_in, dim3(g.blocks), dim3(kBlock), 0, c->stream, c->n, g.zc, r,
-                     c->cdiag, sumsq, (double)c->n_liquid, rms_out, w, out, flags);
+                     c->cdiag, sumsq, (double)c->n_liquid, rms_out, w, out, flags, act);
 }
 
 }  // namespace fs

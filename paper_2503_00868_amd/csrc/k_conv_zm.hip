@@ -8,7 +8,9 @@
 // plane z, the global loads of plane z+2 are already in flight, and they land
 // in the ring slot that plane z-1 frees.  Each input voxel is thus read from
 // memory about once per layer (1.27x for the xy halo), instead of once per
-// overlapping 3-D tile.
+// overlapping 3-D tile.  A ring slot stores its plane as 8-channel
+// sub-planes [part][voxel][8]: the lanes that read one fragment row then
+// take consecutive 16-byte words, free of LDS bank conflicts.
 //
 // MFMA mapping (lane layout checked on the device): M = 16 output voxels
 // along x, N = 16 output channels, K = 32.  A K-step pairs two taps of one
@@ -34,6 +36,7 @@ constexpr int ZR = ZT + 2;          // ring plane edge with halo
 constexpr int ZRV = ZR * ZR;        // 324 voxels per ring plane
 constexpr int ZSTEPS = 15;          // K-steps per 16-channel chunk
 constexpr int ZTAPS = 28;           // packed taps per weight row (27 + zero)
+constexpr int ZMAXC = 128;          // planes per block at most
 
 __device__ inline int zm_tap0(int s) {
   if (s < 9) return (s % 3) + 3 * (s / 3);              // dz 0
@@ -55,10 +58,14 @@ static ZmGrid zm_grid(int n) {
   g.tx = (n + ZT - 1) / ZT;
   g.ty = g.tx;
   const int tiles = g.tx * g.ty;
-  int chunks = (1024 + tiles - 1) / tiles;
+  // large levels take shorter z-runs: blocks whose tiles are mostly zero
+  // (skipped) then balance against the busy ones
+  const int target = tiles >= 256 ? 4096 : 1024;
+  int chunks = (target + tiles - 1) / tiles;
   if (chunks > n) chunks = n;
   g.zc = (n + chunks - 1) / chunks;
   g.zc += g.zc & 1;  // even: a block owns whole plane pairs (fused 2x2x2 pooling)
+  if (g.zc > ZMAXC) g.zc = ZMAXC;
   g.nchunks = (n + g.zc - 1) / g.zc;
   g.blocks = tiles * g.nchunks;
   return g;
@@ -98,6 +105,23 @@ __global__ void __launch_bounds__(kBlock)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   const int nc = n >> 1;
 
+  // tile-plane activity (block-uniform): a plane marked 0 is zero in this
+  // tile and its halo, in the input and the output of the layer.  The flags
+  // of planes z0-1 .. z1+1 are read once, so that no plane's loads wait on
+  // a flag; a block with no live output plane ends here (the output layer
+  // still stores its zeros).
+  __shared__ uint8_t live_s[ZMAXC + 3];
+  if (out.act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
+      const int zi = z0 - 1 + t;
+      live_s[t] = (unsigned)zi < (unsigned)n ? out.act[(int64_t)zi * tiles + tile] : 0;
+      any |= t >= 1 && t <= z1 - z0 && live_s[t];
+    }
+    if (!__syncthreads_or(any) && EPI != NET_EPI_OUT) return;
+  }
+  auto live = [&](int zi) -> bool { return !out.act || live_s[zi - z0 + 1] != 0; };
+
   // weight fragments: bw[q][s][t] for chunk q, step s, output group t
   bf16x8z bw[NCH][ZSTEPS][NT];
 #pragma unroll
@@ -119,14 +143,16 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
 
-  // global -> registers for input plane zi (zero outside the volume)
+  // global -> registers for input plane zi (zero outside the volume and on
+  // planes known to be zero)
   uint4 pf[PF];
-  auto load_plane = [&](int zi) {
+  auto load_plane = [&](int zi, uint4 (&pf)[PF]) {
+    const bool on = live(zi);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * kBlock;
       uint4 val = make_uint4(0u, 0u, 0u, 0u);
-      if (it < ITEMS) {
+      if (on && it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
         const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
         const int c = p * 8;
@@ -146,7 +172,7 @@ __global__ void __launch_bounds__(kBlock)
   };
   // stores the prefetched plane; returns whether this thread's part of it
   // holds any non-zero bit
-  auto store_plane = [&](int zi) -> int {
+  auto store_plane = [&](int zi, const uint4 (&pf)[PF]) -> int {
     __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
     uint32_t any = 0u;
 #pragma unroll
@@ -154,7 +180,7 @@ __global__ void __launch_bounds__(kBlock)
       const int it = threadIdx.x + k * kBlock;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
-        *reinterpret_cast<uint4*>(slot + ((p >> 1) * ZRV + hv) * 16 + (p & 1) * 8) = pf[k];
+        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = pf[k];
         any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
       }
     }
@@ -170,21 +196,30 @@ __global__ void __launch_bounds__(kBlock)
   // A bias-free network maps an all-zero input neighbourhood to zero, so the
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
-  load_plane(z0 - 1);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1));
-  load_plane(z0);
-  int nz_0 = __syncthreads_or(store_plane(z0));
-  load_plane(z0 + 1);
+  load_plane(z0 - 1, pf);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1, pf));
+  load_plane(z0, pf);
+  int nz_0 = __syncthreads_or(store_plane(z0, pf));
+  load_plane(z0 + 1, pf);
   float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
 #pragma unroll
   for (int e = 0; e < 8; ++e) pacc[e] = 0.f;
 
-  for (int z = z0; z < z1; ++z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1));
-    if (z + 2 <= z1) load_plane(z + 2);
+  // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
+  // is loaded while the MFMAs of plane z run
+  auto plane_step = [&](int z) {
+    const int nz_p = __syncthreads_or(store_plane(z + 1, pf));
+    if (z + 2 <= z1) load_plane(z + 2, pf);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
     nz_0 = nz_p;
+
+    // an output plane known to be zero is neither computed nor stored (a
+    // pooled pair is live if either plane is); the output layer stores zeros
+    if (!live(z) && !(EPI == NET_EPI_RELU_POOL && live(z ^ 1))) {
+      if (EPI == NET_EPI_OUT && own) out.f32[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)] = 0.f;
+      return;
+    }
 
     // issued before the MFMAs, consumed in the epilogue
     uint8_t own_mask = 0;
@@ -200,17 +235,17 @@ __global__ void __launch_bounds__(kBlock)
     const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
     const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
     const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
-    const int half = (g & 1) * 8;
+    const int sub = g & 1;  // 8-channel half of the chunk
 #pragma unroll
     for (int q = 0; q < (work ? NCH : 0); ++q) {
       // groups 0-2: dx = 0..2, taps dz 0 | dz 1
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)q * ZRV * 16;
+        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)(2 * q + sub) * ZRV * 8;
         bf16x8z f[6];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 16 + half);
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 8);
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -224,11 +259,11 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int xo = h == 0 ? (g < 2 ? 0 : 1) : 2;
-        const __bf16* base = sp + (int64_t)q * ZRV * 16;
+        const __bf16* base = sp + (int64_t)(2 * q + sub) * ZRV * 8;
         bf16x8z f[6];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 16 + half);
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -255,7 +290,7 @@ __global__ void __launch_bounds__(kBlock)
       if (own)
         out.f32[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)] =
             own_mask ? rms_f * so[lane] : 0.f;
-      continue;
+      return;
     }
     if (EPI == NET_EPI_RELU_ADD) {
       // raw fp32 sums through LDS; each store adds the fp16 partial sums of
@@ -289,7 +324,7 @@ __global__ void __launch_bounds__(kBlock)
         }
         *reinterpret_cast<uint4*>(out.bf + v * COUT + part * 8) = *reinterpret_cast<const uint4*>(o8);
       }
-      continue;
+      return;
     }
     __bf16* st = stage + wv * (4 * ZT * COUT);
 #pragma unroll
@@ -363,7 +398,8 @@ __global__ void __launch_bounds__(kBlock)
       }
       *reinterpret_cast<uint4*>(out.bf + v * COUT + part * 8) = val;
     }
-  }
+  };
+  for (int z = z0; z < z1; ++z) plane_step(z);
 }
 
 template <int CIN, int WS, int COUT, int EPI>

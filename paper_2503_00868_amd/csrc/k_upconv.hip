@@ -28,6 +28,7 @@ typedef float f32x4u __attribute__((ext_vector_type(4)));
 constexpr int UX = 16;   // coarse voxels per wave row (MFMA M)
 constexpr int UR = 4;    // coarse rows per wave
 constexpr int UY = 16;   // coarse rows per block (4 waves)
+constexpr int UMAXZ = 128;  // coarse planes per block at most
 
 // Coarse offset of fine tap d (-1, 0, 1) for parity q (0, 1).
 __host__ __device__ constexpr int up_off(int q, int d) { return (q + d + 2) / 2 - 1; }
@@ -40,19 +41,21 @@ static UpGrid up_grid(int nc) {
   const int tiles = ((nc + UX - 1) / UX) * ((nc + UY - 1) / UY);
   int runs = (1024 + tiles - 1) / tiles;
   if (runs > nc) runs = nc;
-  const int zr = (nc + runs - 1) / runs;
+  int zr = (nc + runs - 1) / runs;
+  if (zr > UMAXZ) zr = UMAXZ;
   return UpGrid{zr, tiles * ((nc + zr - 1) / zr)};
 }
 
 // A block owns a 16 x 16 coarse tile and a run of zr coarse planes.  For each
 // 16-channel output group the group's per-parity weights are staged in LDS
-// once (8 x 8 x 16 x CC bf16), then every plane of the run is computed: per
+// once (8 x 8 x CC x 16 bf16), then every plane of the run is computed: per
 // (ox, oz, K-step) a wave loads the 6 coarse rows its 4 output rows need and
 // reuses them for the three oy offsets and every parity class using them.
 template <int CC, int COUT>
 __global__ void __launch_bounds__(kBlock)
     k_upconv(int n, int zr, const __bf16* __restrict__ coarse, const __bf16* __restrict__ weff,
-             _Float16* __restrict__ out, const int* __restrict__ flags) {
+             _Float16* __restrict__ out, const int* __restrict__ flags,
+             const uint8_t* __restrict__ act) {
   if (flags && flags[F_DONE]) return;
   static_assert(CC % 32 == 0 && COUT % 16 == 0, "channel counts");
   constexpr int KS = CC / 32;
@@ -69,20 +72,35 @@ __global__ void __launch_bounds__(kBlock)
   if (Z0 >= nc) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   const int Yw = Y0 + UR * wv;
+  // coarse tile-plane activity of the run, read once; a run with no live
+  // plane ends here
+  __shared__ uint8_t live_s[UMAXZ];
+  if (act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < Z1 - Z0; t += kBlock) {
+      live_s[t] = act[(int64_t)(Z0 + t) * (tx * ty) + tile];
+      any |= live_s[t];
+    }
+    if (!__syncthreads_or(any)) return;
+  }
 
 #pragma unroll 1
   for (int t = 0; t < NT; ++t) {
     __syncthreads();  // the previous group's weights are no longer read
+    // LDS layout [p*8 + tap][c / 8][col][8]: the 16 lanes of one weight
+    // fragment read consecutive 16-byte words (no bank conflicts)
     for (int q = threadIdx.x; q < WL / 8; q += kBlock) {
-      const int e = q * 8;  // [p*8 + tap][col][c] -> global [p*8 + tap][t*16 + col][c]
-      const int c = e % CC, cl = (e / CC) % 16, pt = e / (CC * 16);
-      *reinterpret_cast<uint4*>(wl + e) = *reinterpret_cast<const uint4*>(
-          weff + ((int64_t)pt * COUT + t * 16 + cl) * CC + c);
+      const int cl = q % 16, kc = (q / 16) % (CC / 8), pt = q / (16 * (CC / 8));
+      *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) = *reinterpret_cast<const uint4*>(
+          weff + ((int64_t)pt * COUT + t * 16 + cl) * CC + kc * 8);
     }
     __syncthreads();
 
 #pragma unroll 1
     for (int Z = Z0; Z < Z1; ++Z) {
+      // coarse tile-plane known to be zero (with its halo): its fine outputs
+      // are zero and stay as cleared (block-uniform)
+      if (act && !live_s[Z - Z0]) continue;
       f32x4u acc[8][UR];
 #pragma unroll
       for (int p = 0; p < 8; ++p)
@@ -125,7 +143,7 @@ __global__ void __launch_bounds__(kBlock)
                     const int tap =
                         (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
                     const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
-                        wl + ((p * 8 + tap) * 16 + col) * CC + ks * 32 + 8 * g);
+                        wl + (((p * 8 + tap) * (CC / 8) + ks * 4 + g) * 16 + col) * 8);
 #pragma unroll
                     for (int r = 0; r < UR; ++r)
                       acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[r + oy + 1], bw,
@@ -209,16 +227,16 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
-                _Float16* out, const int* flags) {
+                _Float16* out, const int* flags, const uint8_t* act) {
   const UpGrid ug = up_grid(n / 2);
   if (cc == 32 && cout == 16) {
     hipLaunchKernelGGL((k_upconv<32, 16>), dim3(ug.blocks), dim3(kBlock), 0, c->stream, n, ug.zr,
-                       coarse, weff, out, flags);
+                       coarse, weff, out, flags, act);
     return true;
   }
   if (cc == 64 && cout == 32) {
     hipLaunchKernelGGL((k_upconv<64, 32>), dim3(ug.blocks), dim3(kBlock), 0, c->stream, n, ug.zr,
-                       coarse, weff, out, flags);
+                       coarse, weff, out, flags, act);
     return true;
   }
   return false;

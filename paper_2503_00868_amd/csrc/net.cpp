@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -60,6 +61,10 @@ struct UNetState {
   // and the fp16 partial sums of the upsampled half (fine layout)
   __bf16 *weff7, *wskip7, *weff9, *wskip9;
   _Float16 *T2, *T1;
+  // tile-plane activity maps of levels 1-3 (device), and whether the
+  // inference pass uses them
+  uint8_t* act[3];
+  bool skip_tiles = true;
   float* dW;
   float* zbuf;
   float* Az;
@@ -124,6 +129,10 @@ size_t carve_net(int n, char* base, UNetState* s) {
   t->wskip9 = cv.take<__bf16>((size_t)16 * 28 * 16);
   t->T2 = cv.take<_Float16>(V2 * 32);
   t->T1 = cv.take<_Float16>(V1 * 16);
+  for (int l = 0; l < 3; ++l) {
+    const int64_t m = n >> l, tpr = (m + 15) / 16;
+    t->act[l] = cv.take<uint8_t>(tpr * tpr * m);
+  }
   t->dW = cv.take<float>(param_total());
   t->zbuf = cv.take<float>(V1);
   t->Az = cv.take<float>(V1);
@@ -134,9 +143,11 @@ NetSrc src1(const __bf16* a, int ca) { return NetSrc{a, nullptr, ca, 0, 0}; }
 NetSrc srcup(const __bf16* coarse, int cc, const __bf16* skip, int cs) {
   return NetSrc{coarse, skip, cc, cs, 1};
 }
-NetOut out_bf(__bf16* p) { return NetOut{p, nullptr, nullptr, nullptr, nullptr}; }
-NetOut out_pool(__bf16* p, __bf16* pooled) {
-  return NetOut{p, nullptr, nullptr, nullptr, nullptr, nullptr, pooled};
+NetOut out_bf(__bf16* p, const uint8_t* act = nullptr) {
+  return NetOut{p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, act};
+}
+NetOut out_pool(__bf16* p, __bf16* pooled, const uint8_t* act) {
+  return NetOut{p, nullptr, nullptr, nullptr, nullptr, nullptr, pooled, act};
 }
 NetOut out_mask(__bf16* p, const __bf16* relu_of) { return NetOut{p, nullptr, nullptr, nullptr, relu_of}; }
 
@@ -160,11 +171,13 @@ int dgrad(sim_ctx* c, int n, int l, int epi, const __bf16* G, NetOut out) {
 
 // Concatenating layer: fp16 partial sums of the upsampled channels from the
 // coarse grid, then the skip channels' convolution adds them before the ReLU.
+// act_c, act_f (nullable): activity maps of the coarse and the fine level.
 int split_conv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
-               _Float16* T, NetSrc skip, const __bf16* wskip, __bf16* out, const int* flags) {
-  if (!net_upconv(c, n, cc, cout, coarse, weff, T, flags) ||
+               _Float16* T, NetSrc skip, const __bf16* wskip, __bf16* out, const int* flags,
+               const uint8_t* act_c, const uint8_t* act_f) {
+  if (!net_upconv(c, n, cc, cout, coarse, weff, T, flags, act_c) ||
       !net_conv(c, n, skip.ca, cout, NET_EPI_RELU_ADD, skip, wskip,
-                NetOut{out, nullptr, nullptr, nullptr, nullptr, T}, flags)) {
+                NetOut{out, nullptr, nullptr, nullptr, nullptr, T, nullptr, act_f}, flags)) {
     c->err = "no split convolution kernel for this channel configuration";
     return SIM_ERR_INVALID_ARG;
   }
@@ -177,31 +190,39 @@ void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, 
 }
 
 // U-Net forward pass into z (fp32, n^3); activations stay in the workspace.
-// keep_input: store the 2-channel input tensor (the weight gradient of c1
-// reads it); otherwise c1 reads r and the mask directly.
+// keep_input (training): store the 2-channel input tensor (the weight
+// gradient of c1 reads it) and compute every tile; otherwise c1 reads r and
+// the mask directly, and the tiles the activity maps mark as zero are
+// skipped.
 int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_input) {
   UNetState* s = c->net;
   const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
+  const bool skip = !keep_input && s->skip_tiles;
+  const uint8_t* a1 = skip ? s->act[0] : nullptr;
+  const uint8_t* a2 = skip ? s->act[1] : nullptr;
+  const uint8_t* a3 = skip ? s->act[2] : nullptr;
   launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
   int rc = SIM_OK;
   if (keep_input) {
     net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
     rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
   } else {
-    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags);
+    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags, a1);
   }
   // c2 and c4 also write the 2x2x2 average pool of their output
-  rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1), flags);
-  rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2), flags);
-  rc |= conv(c, n2, 3, NET_EPI_RELU_POOL, src1(s->A2, 32), out_pool(s->E2, s->P2), flags);
+  rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1, a1), flags);
+  rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2, a2), flags);
+  rc |= conv(c, n2, 3, NET_EPI_RELU_POOL, src1(s->A2, 32), out_pool(s->E2, s->P2, a2), flags);
   rc |= conv(c, n3, 4, NET_EPI_RELU, src1(s->P2, 32), out_bf(s->A3), flags);
   rc |= conv(c, n3, 5, NET_EPI_RELU, src1(s->A3, 64), out_bf(s->E3), flags);
   // c7 = ReLU(upsampled half, on the coarse grid + skip half), likewise c9
-  rc |= split_conv(c, n2, 64, 32, s->E3, s->weff7, s->T2, src1(s->E2, 32), s->wskip7, s->B2, flags);
-  rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32), out_bf(s->D2), flags);
-  rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16), s->wskip9, s->B1, flags);
-  rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1), flags);
-  NetOut o{nullptr, z, c->cdiag, c->scal + S_NET_RMS, nullptr};
+  rc |= split_conv(c, n2, 64, 32, s->E3, s->weff7, s->T2, src1(s->E2, 32), s->wskip7, s->B2, flags,
+                   a3, a2);
+  rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32), out_bf(s->D2, a2), flags);
+  rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16), s->wskip9, s->B1, flags,
+                   a2, a1);
+  rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1, a1), flags);
+  NetOut o{nullptr, z, c->cdiag, c->scal + S_NET_RMS, nullptr, nullptr, nullptr, a1};
   rc |= conv(c, n1, 10, NET_EPI_OUT, src1(s->D1, 16), o, flags);
   return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
 }
@@ -251,15 +272,84 @@ void pack_all(sim_ctx* c, const float* master) {
   net_pack_split(c, master + param_offset(8), 48, 16, 32, 16, c->net->weff9, c->net->wskip9);
 }
 
+// Where the forward activations can be non-zero.  The convolutions are
+// bias-free, every activation but the output is a ReLU or a pooling of one,
+// and the input (r / rms, mask) vanishes off liquid, so an activation is
+// zero wherever its receptive field holds no liquid cell.  In fine voxels of
+// Chebyshev distance d to the nearest liquid cell: a 3x3x3 convolution at
+// level l reaches 2^(l-1) voxels further, a 2x2x2 pooling adds 1 (level 2)
+// or 2 (level 3) for the alignment to its block, and the nearest upsampling
+// adds nothing.  Through the network that gives d <= 2 (c2), 7 (c4), 17
+// (c6), 21 (c8) and 23 (c10): every activation voxel that is non-zero has
+// its whole fine block within kSupport = 24 of liquid.
+constexpr int kSupport = 24;
+
+// dilation of a 0/1 volume by a cube of half-width r along one axis
+void dilate_axis(std::vector<uint8_t>& a, int n, int axis, int r) {
+  const int64_t s1 = axis == 0 ? n : 1, s2 = axis == 2 ? n : (int64_t)n * n;
+  const int64_t st = axis == 0 ? 1 : axis == 1 ? n : (int64_t)n * n;
+  std::vector<int> pre(n + 1);
+  for (int64_t b = 0; b < n; ++b)
+    for (int64_t a1 = 0; a1 < n; ++a1) {
+      const int64_t base = a1 * s1 + b * s2;
+      pre[0] = 0;
+      for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + (a[base + i * st] != 0);
+      for (int i = 0; i < n; ++i)
+        a[base + i * st] = pre[std::min(n, i + r + 1)] - pre[std::max(0, i - r)] > 0;
+    }
+}
+
+// Activity maps of levels 1-3: map[(z * tpr + ty) * tpr + tx] = 1 when a
+// voxel of the 16 x 16 tile (tx, ty) of plane z, or of its one-voxel halo,
+// has a fine block within kSupport of liquid.
+void activity_maps(int n, const uint8_t* cell, std::vector<uint8_t> maps[3]) {
+  const int64_t C = (int64_t)n * n * n;
+  std::vector<uint8_t> near(C);
+  for (int64_t q = 0; q < C; ++q) near[q] = cell[q] == 1;
+  for (int axis = 0; axis < 3; ++axis) dilate_axis(near, n, axis, kSupport);
+  for (int l = 0; l < 3; ++l) {
+    const int m = n >> l, b = 1 << l, tpr = (m + 15) / 16;
+    // level voxel live when any voxel of its fine block is
+    std::vector<uint8_t> lv((size_t)m * m * m, 0);
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x)
+          if (near[x + (int64_t)n * (y + (int64_t)n * z)])
+            lv[x / b + (int64_t)m * (y / b + (int64_t)m * (z / b))] = 1;
+    maps[l].assign((size_t)tpr * tpr * m, 0);
+    for (int z = 0; z < m; ++z)
+      for (int y = 0; y < m; ++y)
+        for (int x = 0; x < m; ++x) {
+          if (!lv[x + (int64_t)m * (y + (int64_t)m * z)]) continue;
+          // every tile whose halo-extended square holds (x, y)
+          for (int ty = std::max(0, (y - 16) / 16); ty <= std::min(tpr - 1, (y + 1) / 16); ++ty)
+            for (int tx = std::max(0, (x - 16) / 16); tx <= std::min(tpr - 1, (x + 1) / 16); ++tx)
+              if (x >= 16 * tx - 1 && x <= 16 * tx + 16 && y >= 16 * ty - 1 && y <= 16 * ty + 16)
+                maps[l][((size_t)z * tpr + ty) * tpr + tx] = 1;
+        }
+  }
+}
+
 }  // namespace
 
 size_t net_workspace_bytes(int n) { return carve_net(n, nullptr, nullptr); }
 
-int net_init(sim_ctx* c) {
+int net_init(sim_ctx* c, const uint8_t* h_cell) {
   UNetState* s = new (std::nothrow) UNetState();
   if (!s) return SIM_ERR_INVALID_ARG;
   carve_net(c->n, reinterpret_cast<char*>(c->net_ws), s);
   c->net = s;
+  // the inference pass never writes the tiles it skips: clear the whole
+  // network workspace once, so they read as zero
+  std::vector<uint8_t> maps[3];
+  activity_maps(c->n, h_cell, maps);
+  if (hipMemsetAsync(c->net_ws, 0, c->net_ws_bytes, c->stream) != hipSuccess) return SIM_ERR_HIP;
+  for (int l = 0; l < 3; ++l)
+    if (hipMemcpyAsync(s->act[l], maps[l].data(), maps[l].size(), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess)
+      return SIM_ERR_HIP;
+  // the host vectors must outlive the copies
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SIM_ERR_HIP;
   return SIM_OK;
 }
 
@@ -305,6 +395,20 @@ int sim_net_set_weights(sim_ctx* c, const float* w, int64_t count) {
     return SIM_ERR_HIP;
   }
   c->net->ready = true;
+  return SIM_OK;
+}
+
+int sim_net_set_tile_skip(sim_ctx* c, int32_t on) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  if (!c->net) {
+    c->err = "context was not created with the learned preconditioner";
+    return SIM_ERR_STATE;
+  }
+  if (on != 0 && on != 1) {
+    c->err = "on must be 0 or 1";
+    return SIM_ERR_INVALID_ARG;
+  }
+  c->net->skip_tiles = on != 0;
   return SIM_OK;
 }
 

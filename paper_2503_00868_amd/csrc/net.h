@@ -33,10 +33,18 @@ struct NetOut {
   const __bf16* relu_of;    // MASKGRAD: post-activation whose ReLU the gradient passes
   const _Float16* add;      // RELU_ADD: fp16 partial sums [voxel][c_out] added before ReLU
   __bf16* pool;             // RELU_POOL: pooled output at half resolution [voxel][c_out]
+  // Tile-plane activity map of the output level (nullable: every tile is
+  // live), index (z * tiles_per_row + ty) * tiles_per_row + tx over the
+  // 16 x 16 xy-tiles.  Where it holds 0, the tile of that plane, with its
+  // one-voxel halo, is known to be zero in every forward activation of the
+  // level: the z-marching kernels neither load it nor store it (the
+  // buffers hold zeros there); the output layer stores zeros.
+  const uint8_t* act;
 };
 
 size_t net_workspace_bytes(int n);
-int net_init(sim_ctx* c);
+// h_cell: host copy of the cell types (the activity maps derive from it)
+int net_init(sim_ctx* c, const uint8_t* h_cell);
 void net_destroy(sim_ctx* c);
 bool net_ready(const sim_ctx* c);
 // z = mask * rms(r) * U(r / rms(r), mask); returns at once when flags (nullable)
@@ -58,8 +66,10 @@ void net_pool(sim_ctx* c, int n, int C, const __bf16* in, __bf16* out, const int
 // the fine level n, out[v][co] (fp16) = sum over taps and coarse channels of
 // the 3x3x3 convolution of up(coarse) (nearest x2), through the per-parity
 // 2x2x2 weights weff [8 parities][8 taps][cout][cc] (k_pack_subpixel).
+// act (nullable): activity map of the coarse level; the fine outputs of a
+// coarse tile-plane marked 0 are not computed (they stay zero).
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
-                _Float16* out, const int* flags);
+                _Float16* out, const int* flags, const uint8_t* act);
 // Packs weff from the fp32 master weights W [cout][cin][27] of a layer whose
 // first cc input channels are the upsampled ones; and the skip channels
 // [cc, cin) into the forward layout [cout_p][28][cin - cc].
@@ -68,9 +78,10 @@ void net_pack_split(sim_ctx* c, const float* W, int cin, int cout, int cc, int c
 void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out, __bf16* x0,
                const int* flags);
 // c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
-// rms written to rms_out; the 2-channel input is never stored
+// rms written to rms_out; the 2-channel input is never stored.  r is read on
+// liquid cells only.  act (nullable): activity map of the level.
 void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
-                 const __bf16* w, __bf16* out, const int* flags);
+                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act);
 void net_loss_grad(sim_ctx* c, const float* r, const float* Az, const double* dots,
                    const double* rms, __bf16* g11);
 void net_upsum_mask(sim_ctx* c, int n_fine, int Cc, int Ct, const __bf16* T, const __bf16* P,

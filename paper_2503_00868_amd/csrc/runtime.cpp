@@ -650,7 +650,7 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
       return fail(SIM_ERR_HIP);
     launch_mic0_setup(c);
   }
-  if (desc->precond == SIM_PRECOND_LEARNED && net_init(c) != SIM_OK) return fail(SIM_ERR_HIP);
+  if (desc->precond == SIM_PRECOND_LEARNED && net_init(c, h_cell_type) != SIM_OK) return fail(SIM_ERR_HIP);
   if (hipGetLastError() != hipSuccess) return fail(SIM_ERR_HIP);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
   *out = c;

@@ -76,6 +76,7 @@ SIGNATURES = {
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
     "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
     "sim_net_forward": (c_int32, [_P, _P, _P]),
+    "sim_net_set_tile_skip": (c_int32, [_P, c_int32]),
     "sim_harvest_pairs": (c_int32, [_P, _P, _P, _P, POINTER(c_int32), c_int32, c_int32, c_double,
                                     _P, _P, POINTER(sim_stats)]),
     "sim_net_grad": (c_int32, [_P, _P, _P, c_int32, _P, POINTER(c_double)]),
@@ -322,6 +323,9 @@ class Sim:
         z = z if z is not None else self.cells_tensor()
         self._chk(lib().sim_net_forward(self.ctx, _ptr(r), _ptr(z)))
         return z
+
+    def net_set_tile_skip(self, on):
+        self._chk(lib().sim_net_set_tile_skip(self.ctx, int(bool(on))))
 
     def net_grad(self, r, e, batch, grad):
         loss = c_double()

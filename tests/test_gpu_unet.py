@@ -69,6 +69,51 @@ def test_net_zero_input(torch_gpu):
     assert float(z.abs().max()) == 0.0
 
 
+def _ball_mask(n, centre, radius):
+    """Air everywhere but one liquid ball: most tiles lie far from liquid."""
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    d2 = (xx - centre[0]) ** 2 + (yy - centre[1]) ** 2 + (zz - centre[2]) ** 2
+    return np.where(d2 <= radius * radius, inputs.LIQUID, inputs.AIR).astype(np.uint8)
+
+
+@pytest.mark.parametrize("n,which", [(128, "ball"), (128, "seed4"), (96, "ball"), (64, "seed4")])
+def test_tile_skip_is_bitwise_dense(torch_gpu, n, which):
+    """The inference pass skips the tiles farther than 24 fine cells from
+    liquid (every activation is zero there); its output must be bitwise the
+    dense pass's, for random and for the trained weights, and for an FCG
+    projection the iteration count and the pressure must agree bitwise."""
+    torch = torch_gpu
+    from paper_2503_00868_amd.train import DEFAULT_WEIGHTS
+    banner(f"tile skipping vs dense, n={n} {which}")
+    cell = _ball_mask(n, (n // 5, n // 4, n // 3), n // 10) if which == "ball" else inputs.gen_mask(n, 4)
+    mask = cell == inputs.LIQUID
+    rng = np.random.default_rng(n)
+    r = np.where(mask, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    sim = _sim(cell)
+    for w in (torch.as_tensor(net_weights.init_weights(3), device="cuda"),
+              net_weights.load_weights(DEFAULT_WEIGHTS, device="cuda")):
+        sim.net_set_weights(w)
+        out = []
+        for on in (True, False, True):
+            sim.net_set_tile_skip(on)
+            out.append(sim.net_forward(sim.cells_tensor(r)).cpu().numpy())
+        assert np.abs(out[0]).max() > 0
+        assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    if which == "seed4" and n == 64:
+        _, ug = inputs.gen_case(n, 4)
+        res = []
+        for on in (True, False):
+            sim.net_set_tile_skip(on)
+            U = sim.to_faces(ug)
+            st, p = sim.project(U, want_p=True)
+            res.append((st["iters"], p.cpu().numpy(), to_np(U)))
+        assert res[0][0] == res[1][0]
+        assert np.array_equal(res[0][1], res[1][1])
+        for a, b in zip(res[0][2], res[1][2]):
+            assert np.array_equal(a, b)
+    sim.net_set_tile_skip(True)
+
+
 @pytest.mark.parametrize("n,batch", [(16, 1), (16, 2)])
 def test_net_grad_parity(torch_gpu, orc, n, batch):
     torch = torch_gpu

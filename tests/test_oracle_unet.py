@@ -119,3 +119,34 @@ def test_loss_gradient_matches_fd(orc):
         h = 1e-7  # small: larger steps cross ReLU kinks of the piecewise-linear net
         fd = (loss_exact(w + h * d) - loss_exact(w - h * d)) / (2 * h)
         assert abs(fd - g @ d) < 1e-5 * max(1.0, abs(fd)), (fd, g @ d)
+
+
+@pytest.mark.parametrize("p", [(32, 32, 32), (33, 34, 31)])
+def test_activation_support_radius(p):
+    """Support of every activation for a single liquid cell, with positive
+    weights (so every voxel the receptive field reaches is strictly
+    positive): the Chebyshev distance in fine cells from the liquid cell to
+    the farthest fine cell under a non-zero voxel.  The library's inference
+    pass skips tiles farther than 24 fine cells from liquid, which is exact
+    only if no activation reaches beyond 23; the counts are 2^(l-1) per
+    convolution at level l, plus the block alignment of each pooling."""
+    n = 64
+    W = unet.split_weights(np.full(unet.param_count(), 0.01, np.float32))
+    r = np.zeros((n, n, n))
+    r[p[2], p[1], p[0]] = 1.0
+    _, acts = unet.forward(W, r, r > 0, emulate_bf16=False, return_all=True)
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    d = np.maximum(np.maximum(abs(xx - p[0]), abs(yy - p[1])), abs(zz - p[2]))
+    reach = {}
+    for k in ("a1", "e1", "p1", "a2", "e2", "p2", "a3", "e3", "b2", "d2", "b1", "d1"):
+        a = acts[k][0].abs().sum(0).numpy() > 0
+        f = n // a.shape[0]
+        reach[k] = int(d[np.kron(a, np.ones((f, f, f), bool))].max())
+    odd = p[0] % 2 == 1 or p[1] % 2 == 1 or p[2] % 2 == 1
+    bound = {"a1": 1, "e1": 2, "p1": 3, "a2": 5, "e2": 7, "p2": 9, "a3": 13, "e3": 17, "b2": 19,
+             "d2": 21, "b1": 22, "d1": 23}
+    for k, b in bound.items():
+        assert reach[k] <= b, (k, reach[k])
+    if odd:  # an alignment that reaches the bound exactly
+        assert reach == bound, reach
+    assert max(reach.values()) < 24
