@@ -80,6 +80,375 @@ __global__ void __launch_bounds__(kBlock)
               const int* __restrict__ flags) {
   if (flags && flags[F_DONE]) return;
   static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts");
+  static_assert(EPI != NET_EPI_RELU_ADD && EPI != NET_EPI_RELU_POOL, "k_conv_zm_pa");
+  constexpr int NCH = CIN / 16;          // 16-channel chunks
+  constexpr int NT = COUT / 16;          // 16-channel output groups
+  constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
+  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
+  constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
+  constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
+  // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
+  // compute of plane z-2) needs no barrier of its own
+  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
+  // Epilogue: layers with 32 or more channels on either side take the
+  // weights as the MFMA's A operand (D = [output channel][voxel]) and store
+  // straight from registers; 16 -> 16 layers take the input as A (D =
+  // [voxel][output channel]) and store through an LDS stage, which measured
+  // faster for them.
+  constexpr bool DIRECT = NT > 1 || NCH > 1;
+  constexpr int STAGE_BYTES = DIRECT ? 16 : 4 * 4 * ZT * COUT * 2;
+  __shared__ __attribute__((aligned(16))) char stage_raw[STAGE_BYTES];
+  __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
+
+  const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % tiles, chunk = lb / tiles;
+  const int tpr = (n + ZT - 1) / ZT;
+  const int x0 = (tile % tpr) * ZT, y0 = (tile / tpr) * ZT;
+  const int z0 = chunk * zc;
+  const int z1 = min(z0 + zc, n);
+  if (z0 >= n) return;
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int nc = n >> 1;
+
+  // tile-plane activity (block-uniform): a plane marked 0 is zero in this
+  // tile and its halo, in the input and the output of the layer.  The flags
+  // of planes z0-1 .. z1+1 are read once, so that no plane's loads wait on
+  // a flag; a block with no live output plane ends here (the output layer
+  // still stores its zeros).
+  __shared__ uint8_t live_s[ZMAXC + 3];
+  if (out.act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
+      const int zi = z0 - 1 + t;
+      live_s[t] = (unsigned)zi < (unsigned)n ? out.act[(int64_t)zi * tiles + tile] : 0;
+      any |= t >= 1 && t <= z1 - z0 && live_s[t];
+    }
+    if (!__syncthreads_or(any) && EPI != NET_EPI_OUT) return;
+  }
+  auto live = [&](int zi) -> bool { return !out.act || live_s[zi - z0 + 1] != 0; };
+
+  // weight fragments: bw[q][s][t] for chunk q, step s, output group t
+  bf16x8z bw[NCH][ZSTEPS][NT];
+#pragma unroll
+  for (int q = 0; q < NCH; ++q)
+#pragma unroll
+    for (int s = 0; s < ZSTEPS; ++s) {
+      const int tap = g < 2 ? zm_tap0(s) : zm_tap1(s);
+      const int ci = q * 16 + (g & 1) * 8;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        bf16x8z v;
+        if (ci < WS) {
+          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)(t * 16 + col) * ZTAPS + tap) * WS + ci);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+        }
+        bw[q][s][t] = v;
+      }
+    }
+
+  // Load items of this thread: item it = threadIdx.x + k * kBlock holds 8
+  // channels (part p) of halo voxel hv.  Its byte offset within one plane of
+  // its source is fixed for the block; only the (uniform) plane offset moves
+  // with z.  src: 0 none (outside the volume or channel padding), 1 a, 2 b.
+  uint32_t ioff[PF];
+  uint8_t isrc[PF];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int it = threadIdx.x + k * kBlock;
+    const int hv = it / P8, p = it - hv * P8;
+    const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
+    const int c = p * 8;
+    ioff[k] = 0u;
+    isrc[k] = 0;
+    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+      if (c < src.ca) {
+        const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
+        ioff[k] = (uint32_t)((v * src.ca + c) * 2);
+        isrc[k] = 1;
+      } else if (c < src.ca + src.cb) {
+        ioff[k] = (uint32_t)((((int64_t)gx + (int64_t)n * gy) * src.cb + (c - src.ca)) * 2);
+        isrc[k] = 2;
+      }
+    }
+  }
+  const int64_t plane_a = (int64_t)(src.up ? nc : n) * (src.up ? nc : n) * src.ca * 2;
+  const int64_t plane_b = (int64_t)n * n * src.cb * 2;
+
+  // global -> registers for input plane zi (zero outside the volume and on
+  // planes known to be zero)
+  uint4 pf[PF];
+  auto load_plane = [&](int zi) {
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+    if (!live(zi) || (unsigned)zi >= (unsigned)n) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pf[k] = zero;
+      return;
+    }
+    const char* pa = reinterpret_cast<const char*>(src.a) + (int64_t)(src.up ? zi >> 1 : zi) * plane_a;
+    if (!src.b) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const uint4 raw = *reinterpret_cast<const uint4*>(pa + ioff[k]);
+        pf[k] = isrc[k] ? raw : zero;
+      }
+    } else {
+      const char* pb = reinterpret_cast<const char*>(src.b) + (int64_t)zi * plane_b;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const uint4 raw = *reinterpret_cast<const uint4*>((isrc[k] == 2 ? pb : pa) + ioff[k]);
+        pf[k] = isrc[k] ? raw : zero;
+      }
+    }
+  };
+  // stores the prefetched plane; returns whether this thread's part of it
+  // holds any non-zero bit
+  auto store_plane = [&](int zi) -> int {
+    __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
+    uint32_t any = 0u;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int it = threadIdx.x + k * kBlock;
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
+        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = pf[k];
+        any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
+      }
+    }
+    return any != 0u;
+  };
+
+  // Output mapping (the MFMA takes the weights as A and the input as B, so
+  // D is [output channel][voxel]): lane (g, col) holds channels 4g .. 4g+3
+  // of output group t for voxel x0 + col of row y0 + 4 wv + a, and stores
+  // them as one 8-byte word; a wave's store of one row is 512 contiguous
+  // bytes.  No staging through LDS.
+  const int ox = x0 + col;
+  const bool ox_ok = ox < n;
+  // staged epilogue: lane l owns voxel (x0 + l % 16, row l / 16) of its
+  // wave's rows for the output layer's mask and store
+  const int oy = y0 + 4 * wv + (lane >> 4);
+  const bool own = ox < n && oy < n;
+  const int64_t nn = (int64_t)n * n;
+  const float rms_f = EPI == NET_EPI_OUT ? (float)*out.rms : 0.f;
+  auto vox = [&](int a, int z) -> int64_t { return (int64_t)ox + (int64_t)n * (y0 + 4 * wv + a) + nn * z; };
+  auto row_ok = [&](int a) -> bool { return ox_ok && y0 + 4 * wv + a < n; };
+  auto pack4 = [](float f0, float f1, float f2, float f3) -> uint2 {
+    __bf16 h[4] = {(__bf16)f0, (__bf16)f1, (__bf16)f2, (__bf16)f3};
+    return *reinterpret_cast<const uint2*>(h);
+  };
+
+  // A bias-free network maps an all-zero input neighbourhood to zero, so the
+  // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
+  // halo) are all zero; the flags come with the barrier after each store.
+  load_plane(z0 - 1);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1));
+  load_plane(z0);
+  int nz_0 = __syncthreads_or(store_plane(z0));
+  load_plane(z0 + 1);
+
+  // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
+  // is loaded while the MFMAs of plane z run
+  auto plane_step = [&](int z) {
+    const int nz_p = __syncthreads_or(store_plane(z + 1));
+    if (z + 2 <= z1) load_plane(z + 2);
+    const bool work = (nz_m | nz_0 | nz_p) != 0;
+    nz_m = nz_0;
+    nz_0 = nz_p;
+
+    // an output plane known to be zero is neither computed nor stored; the
+    // output layer stores zeros
+    if (!live(z)) {
+      if (EPI == NET_EPI_OUT && DIRECT && g == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (row_ok(a)) out.f32[vox(a, z)] = 0.f;
+      }
+      if (EPI == NET_EPI_OUT && !DIRECT && own) out.f32[(int64_t)ox + (int64_t)n * oy + nn * z] = 0.f;
+      return;
+    }
+
+    // issued before the MFMAs, consumed in the epilogue
+    uint8_t mk[4] = {0, 0, 0, 0};
+    uint8_t own_mask = 0;
+    if (EPI == NET_EPI_OUT && DIRECT && g == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (row_ok(a)) mk[a] = out.mask[vox(a, z)];
+    }
+    if (EPI == NET_EPI_OUT && !DIRECT && own)
+      own_mask = out.mask[(int64_t)ox + (int64_t)n * oy + nn * z];
+
+    f32x4z acc[4][NT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
+
+    const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
+    const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
+    const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
+    const int sub = g & 1;  // 8-channel half of the chunk
+#pragma unroll
+    for (int q = 0; q < (work ? NCH : 0); ++q) {
+      // groups 0-2: dx = 0..2, taps dz 0 | dz 1
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)(2 * q + sub) * ZRV * 8;
+        bf16x8z f[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 8);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[q][dx + 3 * dy][t],
+                                                                           f[a + dy], acc[a][t], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][dx + 3 * dy][t],
+                                                                           acc[a][t], 0, 0, 0);
+      }
+      // groups 3-4: dz 2 with (dx 0 | dx 1) and (dx 2 | zero)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int xo = h == 0 ? (g < 2 ? 0 : 1) : 2;
+        const __bf16* base = sp + (int64_t)(2 * q + sub) * ZRV * 8;
+        bf16x8z f[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                       bw[q][9 + 3 * h + dy][t], f[a + dy], acc[a][t], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                       f[a + dy], bw[q][9 + 3 * h + dy][t], acc[a][t], 0, 0, 0);
+      }
+    }
+
+    if constexpr (DIRECT) {
+      if (EPI == NET_EPI_OUT) {
+        // channel 0 is row 0 of D: lanes g = 0, element 0
+        if (g == 0) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (row_ok(a)) out.f32[vox(a, z)] = mk[a] ? rms_f * acc[a][0][0] : 0.f;
+        }
+        return;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const bool ok = row_ok(a);
+        const int64_t v = vox(a, z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int64_t e = v * COUT + t * 16 + 4 * g;  // element of channel 4g
+          float f[4] = {acc[a][t][0], acc[a][t][1], acc[a][t][2], acc[a][t][3]};
+          if (EPI == NET_EPI_RELU) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[i] = f[i] > 0.f ? f[i] : 0.f;
+          }
+          uint2 o = pack4(f[0], f[1], f[2], f[3]);
+          if (EPI == NET_EPI_MASKGRAD) {
+            // the gradient passes where the post-activation is positive
+            uint2 pm = make_uint2(0u, 0u);
+            if (ok) pm = *reinterpret_cast<const uint2*>(out.relu_of + e);
+            const uint32_t* pw = reinterpret_cast<const uint32_t*>(&pm);
+            uint32_t* ow = reinterpret_cast<uint32_t*>(&o);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const uint32_t lo = pw[j] & 0xffffu, hi = pw[j] >> 16;
+              const uint32_t keep_lo = (lo != 0u && !(lo & 0x8000u)) ? 0xffffu : 0u;
+              const uint32_t keep_hi = (hi != 0u && !(hi & 0x8000u)) ? 0xffff0000u : 0u;
+              ow[j] &= (keep_lo | keep_hi);
+            }
+          }
+          if (ok) *reinterpret_cast<uint2*>(out.bf + e) = o;
+        }
+      }
+    } else {
+      // epilogue: rows y0 + 4 wv + a, voxels x0 + 4 g + i, channel t*16 + col
+      if (EPI == NET_EPI_OUT) {
+        // channel 0 (lanes with col 0) through LDS: lane l then stores voxel
+        // (row l / 16, x l % 16) of the wave's rows, coalesced
+        float* so = reinterpret_cast<float*>(stage) + wv * 64;
+        if (col == 0) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) so[a * 16 + 4 * g + i] = acc[a][0][i];
+        }
+        wave_sync();  // per-wave staging
+        if (own)
+          out.f32[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)] =
+              own_mask ? rms_f * so[lane] : 0.f;
+        return;
+      }
+      __bf16* st = stage + wv * (4 * ZT * COUT);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = acc[a][t][i];
+            if (EPI == NET_EPI_RELU) v = v > 0.f ? v : 0.f;
+            st[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = (__bf16)v;
+          }
+      wave_sync();  // per-wave staging
+      constexpr int PV = COUT / 8;
+#pragma unroll
+      for (int k = 0; k < (4 * ZT * PV + 63) / 64; ++k) {
+        const int it = lane + 64 * k;
+        if (it >= 4 * ZT * PV) break;
+        const int lv = it / PV, part = it - lv * PV;
+        const int a = lv / ZT, xl = lv % ZT;
+        const int x = x0 + xl, y = y0 + 4 * wv + a;
+        if (x >= n || y >= n) continue;
+        const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+        uint4 val = *reinterpret_cast<const uint4*>(st + lv * COUT + part * 8);
+        if (EPI == NET_EPI_MASKGRAD) {
+          const uint4 pm = *reinterpret_cast<const uint4*>(out.relu_of + v * COUT + part * 8);
+          const uint32_t* pw = reinterpret_cast<const uint32_t*>(&pm);
+          uint32_t* vw = reinterpret_cast<uint32_t*>(&val);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = pw[e] & 0xffffu, hi = pw[e] >> 16;
+            const uint32_t keep_lo = (lo != 0u && !(lo & 0x8000u)) ? 0xffffu : 0u;
+            const uint32_t keep_hi = (hi != 0u && !(hi & 0x8000u)) ? 0xffff0000u : 0u;
+            vw[e] &= (keep_lo | keep_hi);
+          }
+        }
+        *reinterpret_cast<uint4*>(out.bf + v * COUT + part * 8) = val;
+      }
+    }
+  };
+  for (int z = z0; z < z1; ++z) plane_step(z);
+}
+
+// Variant for the layers with the add and pool epilogues: the plane loads
+// do their address arithmetic per item and plane, and the epilogue stages
+// through LDS.  The same source compiled into the kernel below (whose
+// streamlined loads suit the other epilogues) measured 10-35% slower for
+// these two epilogues, so they keep this form.
+// CIN: channels held per ring voxel (multiple of 16; the source may have
+// fewer, the rest is zero).  WS: channel stride of the packed weights.
+// COUT: output channels (16 or 48).
+template <int CIN, int WS, int COUT, int EPI>
+__global__ void __launch_bounds__(kBlock)
+    k_conv_zm_pa(int n, int zc, NetSrc src, const __bf16* __restrict__ w, NetOut out,
+              const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts");
   constexpr int NCH = CIN / 16;          // 16-channel chunks
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
@@ -406,8 +775,12 @@ template <int CIN, int WS, int COUT, int EPI>
 static void zm_launch(sim_ctx* c, int n, NetSrc src, const __bf16* w, NetOut out,
                       const int* flags) {
   const ZmGrid g = zm_grid(n);
-  hipLaunchKernelGGL((k_conv_zm<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream, n,
-                     g.zc, src, w, out, flags);
+  if constexpr (EPI == NET_EPI_RELU_ADD || EPI == NET_EPI_RELU_POOL)
+    hipLaunchKernelGGL((k_conv_zm_pa<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream,
+                       n, g.zc, src, w, out, flags);
+  else
+    hipLaunchKernelGGL((k_conv_zm<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream, n,
+                       g.zc, src, w, out, flags);
 }
 
 template <int CIN, int WS, int COUT>
