@@ -222,8 +222,7 @@ int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_in
   rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16), s->wskip9, s->B1, flags,
                    a2, a1);
   rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1, a1), flags);
-  NetOut o{nullptr, z, c->cdiag, c->scal + S_NET_RMS, nullptr, nullptr, nullptr, a1};
-  rc |= conv(c, n1, 10, NET_EPI_OUT, src1(s->D1, 16), o, flags);
+  net_conv_out(c, n1, s->D1, s->wf[10], z, c->scal + S_NET_RMS, flags, a1);
   return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
 }
 

@@ -77,6 +77,11 @@ void net_pack_split(sim_ctx* c, const float* W, int cin, int cout, int cc, int c
                     __bf16* weff, __bf16* wskip);
 void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out, __bf16* x0,
                const int* flags);
+// c11 (16 -> 1) fused with the output map: z = mask * rms * conv(D), on the
+// vector ALU (bf16 dot products); w is the layer's packed forward weights.
+// act (nullable): activity map of the level.
+void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z, const double* rms,
+                  const int* flags, const uint8_t* act);
 // c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
 // rms written to rms_out; the 2-channel input is never stored.  r is read on
 // liquid cells only.  act (nullable): activity map of the level.
