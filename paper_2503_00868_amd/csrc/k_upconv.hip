@@ -29,6 +29,10 @@ constexpr int UX = 16;   // coarse voxels per wave row (MFMA M)
 constexpr int UR = 4;    // coarse rows per wave
 constexpr int UY = 16;   // coarse rows per block (4 waves)
 constexpr int UMAXZ = 128;  // coarse planes per block at most
+// Launch sizes (measured at 256^3): the 64-channel layer stages 128 KB of
+// weights per output group, so its blocks take runs of 4 coarse planes.
+constexpr int UP_TARGET32 = 512;  // blocks for the 32-channel layer
+constexpr int UP_TARGET64 = 256;  // blocks for the 64-channel layer
 
 // Coarse offset of fine tap d (-1, 0, 1) for parity q (0, 1).
 __host__ __device__ constexpr int up_off(int q, int d) { return (q + d + 2) / 2 - 1; }
@@ -37,9 +41,12 @@ struct UpGrid {
   int zr, blocks;
 };
 
-static UpGrid up_grid(int nc) {
+// target: blocks to aim for.  A block stages its weights (8 x 8 x CC x 16
+// bf16 per output group) once for its whole run, so wide layers, whose
+// staging fills most of the LDS, take fewer blocks with longer runs.
+static UpGrid up_grid(int nc, int target) {
   const int tiles = ((nc + UX - 1) / UX) * ((nc + UY - 1) / UY);
-  int runs = (1024 + tiles - 1) / tiles;
+  int runs = (target + tiles - 1) / tiles;
   if (runs > nc) runs = nc;
   int zr = (nc + runs - 1) / runs;
   if (zr > UMAXZ) zr = UMAXZ;
@@ -228,7 +235,7 @@ __global__ void __launch_bounds__(kBlock)
 
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
                 _Float16* out, const int* flags, const uint8_t* act) {
-  const UpGrid ug = up_grid(n / 2);
+  const UpGrid ug = up_grid(n / 2, cc == 64 ? UP_TARGET64 : UP_TARGET32);
   if (cc == 32 && cout == 16) {
     hipLaunchKernelGGL((k_upconv<32, 16>), dim3(ug.blocks), dim3(kBlock), 0, c->stream, n, ug.zr,
                        coarse, weff, out, flags, act);
