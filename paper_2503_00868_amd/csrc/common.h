@@ -8,6 +8,9 @@
 namespace fs {
 
 constexpr int kBlock = 256;  // threads per block for streaming/stencil kernels
+constexpr int kMaxGrid = 2048;  // blocks per cell-domain launch (and per face component)
+// the block partial sums hold kMaxGrid * 3 * 4 doubles
+constexpr int kPartialDoubles = kMaxGrid * 3 * 4;
 constexpr int kWave = 64;
 
 enum : uint8_t { AIR = 0, LIQUID = 1, SOLID = 2 };

@@ -1232,6 +1232,169 @@ __global__ void __launch_bounds__(kBlock)
   store_partials<1>(v, partials, comp * gridDim.x + lb);
 }
 
+// The same step organised as a z-march (as k_dir_spmv_zm for the cells): a
+// block owns a 64 x 16 tile of one face component's (x, y) plane and walks a
+// run of z planes.  Each face's direction is formed once per plane; planes
+// z-1, z, z+1 stay in registers for the z neighbours, plane z (with a
+// one-face halo) goes through LDS for the x and y neighbours.  Thread (tx,
+// tg) owns the faces of column x0 + tx in rows y0 + tg + 4k, k = 0..3.
+constexpr int DZ_TX = 64, DZ_TY = 16, DZ_K = DZ_TY / (kBlock / DZ_TX);
+
+struct DcgZmShape {
+  int tiles_x, tiles, chunks, zc;
+};
+
+__host__ __device__ inline DcgZmShape dcg_zm_shape(int n) {
+  // the largest face grid, (n + 1) x (n + 1) x (n + 1), bounds all three
+  DcgZmShape s;
+  s.tiles_x = (n + 1 + DZ_TX - 1) / DZ_TX;
+  s.tiles = s.tiles_x * ((n + 1 + DZ_TY - 1) / DZ_TY);
+  int chunks = (1024 + s.tiles - 1) / s.tiles;
+  if (chunks > n + 1) chunks = n + 1;
+  s.zc = (n + 1 + chunks - 1) / chunks;
+  s.chunks = (n + 1 + s.zc - 1) / s.zc;
+  return s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_dcg_dir_spmv_zm(int n, const uint8_t* __restrict__ fcode, float alpha,
+                      const float* __restrict__ r, const float* __restrict__ d_in,
+                      float* __restrict__ d_out, float* __restrict__ q, int64_t F,
+                      const double* __restrict__ scal, const int* __restrict__ flags,
+                      double* partials) {
+  if (flags[F_DONE]) return;
+  __shared__ float sd[DZ_TY + 2][DZ_TX + 2];
+  const int comp = blockIdx.y;
+  const Dims dm3 = face_dims(n, comp);
+  const int64_t sy = dm3.nx, sz = (int64_t)dm3.nx * dm3.ny;
+  const float beta = (float)scal[S_BETA];
+  const uint8_t* __restrict__ code = fcode + comp * F;
+  const float* __restrict__ rc = r + comp * F;
+  const float* __restrict__ di = d_in + comp * F;
+  float* __restrict__ dout = d_out + comp * F;
+  float* __restrict__ qc = q + comp * F;
+  const DcgZmShape sh = dcg_zm_shape(n);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % sh.tiles, chunk = lb / sh.tiles;
+  const int x0 = (tile % sh.tiles_x) * DZ_TX, y0 = (tile / sh.tiles_x) * DZ_TY;
+  const int z0 = chunk * sh.zc;
+  const int z1 = min(z0 + sh.zc, dm3.nz);
+  double v[1] = {0.0};
+  if (x0 < dm3.nx && y0 < dm3.ny && z0 < dm3.nz) {
+    const int tx = threadIdx.x % DZ_TX, tg = threadIdx.x / DZ_TX;
+    const int x = x0 + tx;
+    auto in_grid = [&](int xx, int yy, int zz) {
+      return xx >= 0 && xx < dm3.nx && yy >= 0 && yy < dm3.ny && zz >= 0 && zz < dm3.nz;
+    };
+    auto dir_of = [&](float rv, float dv, uint8_t cd) { return rv * mrow_diag_inv(cd, alpha) + beta * dv; };
+    // raw (r, d, code) of this thread's faces of one plane, and of its halo face
+    struct Raw {
+      float r[DZ_K], d[DZ_K];
+      uint8_t c[DZ_K];
+    };
+    auto load_own = [&](int zz, Raw& o) {
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) {
+        const int y = y0 + tg + 4 * k;
+        if (in_grid(x, y, zz)) {
+          const int64_t m = x + sy * y + sz * zz;
+          o.r[k] = rc[m];
+          o.d[k] = di[m];
+          o.c[k] = code[m];
+        } else {
+          o.r[k] = 0.f, o.d[k] = 0.f, o.c[k] = 0;
+        }
+      }
+    };
+    // halo face h (threads 0..159): x-halo for h < 32, y-halo otherwise
+    const int h = threadIdx.x;
+    int hx = -1, hy = -1, hrow = 0, hcol = 0;
+    if (h < 2 * DZ_TY) {
+      hrow = 1 + (h % DZ_TY);
+      hcol = h < DZ_TY ? 0 : DZ_TX + 1;
+      hx = h < DZ_TY ? x0 - 1 : x0 + DZ_TX;
+      hy = y0 + h % DZ_TY;
+    } else if (h < 2 * DZ_TY + 2 * DZ_TX) {
+      const int j = h - 2 * DZ_TY;
+      hcol = 1 + (j % DZ_TX);
+      hrow = j < DZ_TX ? 0 : DZ_TY + 1;
+      hx = x0 + j % DZ_TX;
+      hy = j < DZ_TX ? y0 - 1 : y0 + DZ_TY;
+    }
+    float hr = 0.f, hd = 0.f;
+    uint8_t hc = 0;
+    auto load_halo = [&](int zz) {
+      if (hx != -1 && in_grid(hx, hy, zz)) {
+        const int64_t m = hx + sy * hy + sz * zz;
+        hr = rc[m], hd = di[m], hc = code[m];
+      } else {
+        hr = 0.f, hd = 0.f, hc = 0;
+      }
+    };
+
+    float dmv[DZ_K], dcv[DZ_K], dpv[DZ_K];
+    uint8_t cc[DZ_K];
+    Raw c1, c2;
+    {
+      Raw c0;
+      load_own(z0 - 1, c0);
+      load_own(z0, c1);
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) {
+        dmv[k] = dir_of(c0.r[k], c0.d[k], c0.c[k]);
+        dcv[k] = dir_of(c1.r[k], c1.d[k], c1.c[k]);
+        cc[k] = c1.c[k];
+      }
+    }
+    load_own(z0 + 1, c1);
+    load_halo(z0);
+    for (int zz = z0; zz < z1; ++zz) {
+      const float hv = dir_of(hr, hd, hc);
+      uint8_t cn[DZ_K];
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) {
+        dpv[k] = dir_of(c1.r[k], c1.d[k], c1.c[k]);
+        cn[k] = c1.c[k];
+      }
+      // next loads before the barrier
+      load_own(zz + 2, c2);
+      load_halo(zz + 1);
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) sd[1 + tg + 4 * k][1 + tx] = dcv[k];
+      if (hx != -1) sd[hrow][hcol] = hv;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) {
+        const int y = y0 + tg + 4 * k;
+        if (x < dm3.nx && y < dm3.ny) {
+          const int row = 1 + tg + 4 * k, col = 1 + tx;
+          const uint8_t cd = cc[k];
+          const float dcur = dcv[k];
+          float acc = 0.f;
+          if (cd & 1) acc += sd[row][col - 1] - dcur;
+          if (cd & 2) acc += sd[row][col + 1] - dcur;
+          if (cd & 4) acc += sd[row - 1][col] - dcur;
+          if (cd & 8) acc += sd[row + 1][col] - dcur;
+          if (cd & 16) acc += dmv[k] - dcur;
+          if (cd & 32) acc += dpv[k] - dcur;
+          const bool act = (cd & FC_ACTIVE) != 0;
+          const float qv = act ? dcur - alpha * acc : 0.f;
+          const float dv = act ? dcur : 0.f;
+          const int64_t m = x + sy * y + sz * zz;
+          dout[m] = dv;
+          qc[m] = qv;
+          v[0] += (double)dv * (double)qv;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < DZ_K; ++k) dmv[k] = dcv[k], dcv[k] = dpv[k], cc[k] = cn[k];
+      c1 = c2;
+    }
+  }
+  store_partials<1>(v, partials, comp * gridDim.x + lb);
+}
+
 __global__ void __launch_bounds__(kBlock)
     k_dcg_update(const uint8_t* __restrict__ fcode, float alpha, double* __restrict__ x,
                  float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
@@ -1307,6 +1470,15 @@ void launch_dcg_init(sim_ctx* c, float alpha) {
 
 void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_out) {
   prof_mark(c, SIM_KERN_DCG_DIR_SPMV, true);
+  const DcgZmShape sh = dcg_zm_shape(c->n);
+  const int nb = sh.tiles * sh.chunks;
+  if (3 * nb <= kPartialDoubles) {
+    hipLaunchKernelGGL(k_dcg_dir_spmv_zm, dim3(nb, 3), dim3(kBlock), 0, c->stream, c->n, c->fcode,
+                       alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags, c->partials);
+    prof_mark(c, SIM_KERN_DCG_DIR_SPMV, false);
+    launch_finalize(c, 3 * nb, 1, FIN_DQ, 0.0, 0, 0, 0.0, 0);
+    return;
+  }
   hipLaunchKernelGGL(k_dcg_dir_spmv, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
                      c->fcode, alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags,
                      c->partials);

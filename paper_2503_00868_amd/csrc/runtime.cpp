@@ -68,7 +68,6 @@ void fs::prof_mark(sim_ctx* c, int kind, bool begin) {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = 2048;  // blocks per cell-domain launch (and per face component)
 constexpr int kCtrlBytes = S_COUNT * sizeof(double) + F_COUNT * sizeof(int);
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -128,7 +127,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->fq = cv.take<float>(F3n);
   t->lam = cv.take<float>(F3n);
   t->lam2 = cv.take<float>(F3n);
-  t->partials = cv.take<double>((size_t)kMaxGrid * 3 * 4);
+  t->partials = cv.take<double>((size_t)kPartialDoubles);
   // control block: scalars then flags, copied to the host in one transfer
   char* ctrl = cv.take<char>(kCtrlBytes);
   t->scal = reinterpret_cast<double*>(ctrl);
