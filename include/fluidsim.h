@@ -177,16 +177,18 @@ int sim_net_param_count(int64_t* count);
 int sim_net_set_weights(sim_ctx* ctx, const float* d_weights, int64_t count);
 int sim_net_forward(sim_ctx* ctx, const float* d_r, float* d_z);
 
-/* Zero-tile skipping of the network's inference pass (default on).  The
- * network is bias-free and its input vanishes off liquid, so each activation
- * is zero beyond a fixed distance of the liquid (at most 23 fine cells; the
- * receptive-field count is in the implementation).  At creation the library
- * marks, per level, the 16 x 16 tiles of each plane that come within 24 fine
- * cells of liquid; with skipping on, the inference kernels neither load nor
- * store the other tiles, which hold zeros.  Results are bitwise those of the
- * dense pass (on = 0); the switch exists to check exactly that.  d_r passed
- * to sim_net_forward (or met in the solver) is read on liquid cells only.
- * Returns SIM_ERR_STATE for a context without the learned preconditioner. */
+/* Tile skipping of the network's inference pass (default on).  The network
+ * is bias-free and its input vanishes off liquid, so each activation is zero
+ * beyond a fixed distance of the liquid; and z is masked to liquid, so the
+ * late decoder layers matter only near it (c10's output within 1 cell, c9's
+ * within 2, and so on; the counts are in the implementation).  At creation
+ * the library marks, per layer, the 16 x 16 tiles of each plane that come
+ * within the smaller of the two distances; with skipping on, the inference
+ * kernels neither compute nor store the other tiles.  z is bitwise that of
+ * the dense pass (on = 0); the switch exists to check exactly that.  d_r
+ * passed to sim_net_forward (or met in the solver) is read on liquid cells
+ * only.  Returns SIM_ERR_STATE for a context without the learned
+ * preconditioner. */
 int sim_net_set_tile_skip(sim_ctx* ctx, int32_t on);
 
 /* Loss and weight gradient of the U-Net with its current weights on a batch

@@ -44,17 +44,18 @@ static OutGrid out_grid(int n) {
 // D: c10's output [voxel][16] bf16.  w: the packed layer weights in the
 // forward layout [16][28][16] bf16 (only output channel 0 is real), read as
 // bf16 pairs: w2[tap * 8 + j] holds input channels 2j, 2j + 1 of tap
-// dx + 3 dy + 9 dz.  act (nullable): activity map of the level.
+// dx + 3 dy + 9 dz.  act_in, act (nullable, both or neither): activity maps
+// of D and of z.
 __global__ void __launch_bounds__(kBlock)
     k_conv_out(int n, int zc, const __bf16* __restrict__ D, const uint32_t* __restrict__ w2,
                float* __restrict__ z, const uint8_t* __restrict__ mask,
                const double* __restrict__ rms_p, const int* __restrict__ flags,
-               const uint8_t* __restrict__ act) {
+               const uint8_t* __restrict__ act_in, const uint8_t* __restrict__ act) {
   if (flags && flags[F_DONE]) return;
   // two staged planes, each as two 8-channel halves [half][voxel] (16 B per
   // voxel and half: the 16 lanes of a row read consecutive words)
   __shared__ uint4 ring[2][2][ORV];
-  __shared__ uint8_t live_s[OMAXC + 3];
+  __shared__ uint8_t live_s[OMAXC + 3], live_in_s[OMAXC + 3];
 
   const int tpr = (n + OT - 1) / OT;
   const int tiles = tpr * tpr;
@@ -69,14 +70,18 @@ __global__ void __launch_bounds__(kBlock)
   const bool own = x < n && y < n;
   const int64_t nn = (int64_t)n * n;
 
-  // tile-plane activity of planes z0-1 .. z1 (block-uniform)
+  // tile-plane activity of planes z0-1 .. z1 (block-uniform): output planes
+  // marked 0 in act store zeros, input planes marked 0 in act_in read as zero
   if (act)
     for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
       const int zi = z0 - 1 + t;
-      live_s[t] = (unsigned)zi < (unsigned)n ? act[(int64_t)zi * tiles + tile] : 0;
+      const bool in = (unsigned)zi < (unsigned)n;
+      live_s[t] = in ? act[(int64_t)zi * tiles + tile] : 0;
+      live_in_s[t] = in ? act_in[(int64_t)zi * tiles + tile] : 0;
     }
   __syncthreads();
   auto live = [&](int zi) -> bool { return !act || live_s[zi - z0 + 1] != 0; };
+  auto live_in = [&](int zi) -> bool { return !act || live_in_s[zi - z0 + 1] != 0; };
 
   // load items: it = threadIdx.x + k * kBlock is half (it & 1) of halo voxel
   // it >> 1; its byte offset within a plane of D is fixed for the block
@@ -93,7 +98,7 @@ __global__ void __launch_bounds__(kBlock)
   uint4 pf[OPF];
   auto load_plane = [&](int zi) {
     const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-    if (!live(zi) || (unsigned)zi >= (unsigned)n) {
+    if (!live_in(zi) || (unsigned)zi >= (unsigned)n) {
 #pragma unroll
       for (int k = 0; k < OPF; ++k) pf[k] = zero;
       return;
@@ -165,10 +170,10 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z, const double* rms,
-                  const int* flags, const uint8_t* act) {
+                  const int* flags, const uint8_t* act_in, const uint8_t* act) {
   const OutGrid g = out_grid(n);
   hipLaunchKernelGGL(k_conv_out, dim3(g.blocks), dim3(kBlock), 0, c->stream, n, g.zc, D,
-                     reinterpret_cast<const uint32_t*>(w), z, c->cdiag, rms, flags, act);
+                     reinterpret_cast<const uint32_t*>(w), z, c->cdiag, rms, flags, act_in, act);
 }
 
 }  // namespace fs

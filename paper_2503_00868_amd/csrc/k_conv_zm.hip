@@ -112,22 +112,27 @@ __global__ void __launch_bounds__(kBlock)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   const int nc = n >> 1;
 
-  // tile-plane activity (block-uniform): a plane marked 0 is zero in this
-  // tile and its halo, in the input and the output of the layer.  The flags
-  // of planes z0-1 .. z1+1 are read once, so that no plane's loads wait on
-  // a flag; a block with no live output plane ends here (the output layer
-  // still stores its zeros).
-  __shared__ uint8_t live_s[ZMAXC + 3];
+  // tile-plane activity (block-uniform): an output plane marked 0 in
+  // out.act is neither computed nor stored, an input plane marked 0 in
+  // src.act (else out.act) is read as zero.  The flags of planes z0-1 ..
+  // z1+1 are read once, so that no plane's loads wait on a flag; a block
+  // with no live output plane ends here (the output layer still stores its
+  // zeros).
+  __shared__ uint8_t live_s[ZMAXC + 3], live_in_s[ZMAXC + 3];
   if (out.act) {
+    const uint8_t* act_in = src.act ? src.act : out.act;
     int any = 0;
     for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
       const int zi = z0 - 1 + t;
-      live_s[t] = (unsigned)zi < (unsigned)n ? out.act[(int64_t)zi * tiles + tile] : 0;
+      const bool in = (unsigned)zi < (unsigned)n;
+      live_s[t] = in ? out.act[(int64_t)zi * tiles + tile] : 0;
+      live_in_s[t] = in ? act_in[(int64_t)zi * tiles + tile] : 0;
       any |= t >= 1 && t <= z1 - z0 && live_s[t];
     }
     if (!__syncthreads_or(any) && EPI != NET_EPI_OUT) return;
   }
   auto live = [&](int zi) -> bool { return !out.act || live_s[zi - z0 + 1] != 0; };
+  auto live_in = [&](int zi) -> bool { return !out.act || live_in_s[zi - z0 + 1] != 0; };
 
   // weight fragments: bw[q][s][t] for chunk q, step s, output group t
   bf16x8z bw[NCH][ZSTEPS][NT];
@@ -183,7 +188,7 @@ __global__ void __launch_bounds__(kBlock)
   uint4 pf[PF];
   auto load_plane = [&](int zi) {
     const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-    if (!live(zi) || (unsigned)zi >= (unsigned)n) {
+    if (!live_in(zi) || (unsigned)zi >= (unsigned)n) {
 #pragma unroll
       for (int k = 0; k < PF; ++k) pf[k] = zero;
       return;
@@ -474,22 +479,27 @@ __global__ void __launch_bounds__(kBlock)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   const int nc = n >> 1;
 
-  // tile-plane activity (block-uniform): a plane marked 0 is zero in this
-  // tile and its halo, in the input and the output of the layer.  The flags
-  // of planes z0-1 .. z1+1 are read once, so that no plane's loads wait on
-  // a flag; a block with no live output plane ends here (the output layer
-  // still stores its zeros).
-  __shared__ uint8_t live_s[ZMAXC + 3];
+  // tile-plane activity (block-uniform): an output plane marked 0 in
+  // out.act is neither computed nor stored, an input plane marked 0 in
+  // src.act (else out.act) is read as zero.  The flags of planes z0-1 ..
+  // z1+1 are read once, so that no plane's loads wait on a flag; a block
+  // with no live output plane ends here (the output layer still stores its
+  // zeros).
+  __shared__ uint8_t live_s[ZMAXC + 3], live_in_s[ZMAXC + 3];
   if (out.act) {
+    const uint8_t* act_in = src.act ? src.act : out.act;
     int any = 0;
     for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
       const int zi = z0 - 1 + t;
-      live_s[t] = (unsigned)zi < (unsigned)n ? out.act[(int64_t)zi * tiles + tile] : 0;
+      const bool in = (unsigned)zi < (unsigned)n;
+      live_s[t] = in ? out.act[(int64_t)zi * tiles + tile] : 0;
+      live_in_s[t] = in ? act_in[(int64_t)zi * tiles + tile] : 0;
       any |= t >= 1 && t <= z1 - z0 && live_s[t];
     }
     if (!__syncthreads_or(any) && EPI != NET_EPI_OUT) return;
   }
   auto live = [&](int zi) -> bool { return !out.act || live_s[zi - z0 + 1] != 0; };
+  auto live_in = [&](int zi) -> bool { return !out.act || live_in_s[zi - z0 + 1] != 0; };
 
   // weight fragments: bw[q][s][t] for chunk q, step s, output group t
   bf16x8z bw[NCH][ZSTEPS][NT];
@@ -516,7 +526,7 @@ __global__ void __launch_bounds__(kBlock)
   // planes known to be zero)
   uint4 pf[PF];
   auto load_plane = [&](int zi, uint4 (&pf)[PF]) {
-    const bool on = live(zi);
+    const bool on = live_in(zi);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * kBlock;

@@ -45,6 +45,14 @@ static int64_t param_offset(int l) {
 
 static int64_t param_total() { return param_offset(11); }
 
+// Activity maps of the inference pass: map Mi_r covers the level with i
+// halvings (0: full resolution) and radius r in fine voxels (see
+// activity_maps for what the radii are).
+enum MapId { M0_0, M0_1, M0_2, M1_2, M1_3, M1_5, M1_7, M2_5, kNetMaps };
+constexpr int kMaps = kNetMaps;
+constexpr int kMapLevel[kMaps] = {0, 0, 0, 1, 1, 1, 1, 2};
+constexpr int kMapRadius[kMaps] = {0, 1, 2, 2, 3, 5, 7, 5};
+
 }  // namespace fs
 
 struct UNetState {
@@ -61,9 +69,9 @@ struct UNetState {
   // and the fp16 partial sums of the upsampled half (fine layout)
   __bf16 *weff7, *wskip7, *weff9, *wskip9;
   _Float16 *T2, *T1;
-  // tile-plane activity maps of levels 1-3 (device), and whether the
-  // inference pass uses them
-  uint8_t* act[3];
+  // tile-plane activity maps (device), and whether the inference pass uses
+  // them
+  uint8_t* act[fs::kNetMaps];
   bool skip_tiles = true;
   float* dW;
   float* zbuf;
@@ -129,9 +137,10 @@ size_t carve_net(int n, char* base, UNetState* s) {
   t->wskip9 = cv.take<__bf16>((size_t)16 * 28 * 16);
   t->T2 = cv.take<_Float16>(V2 * 32);
   t->T1 = cv.take<_Float16>(V1 * 16);
-  for (int l = 0; l < 3; ++l) {
-    const int64_t m = n >> l, tpr = (m + 15) / 16;
-    t->act[l] = cv.take<uint8_t>(tpr * tpr * m);
+  // each sized for the full-resolution level (n^3 / 256 bytes)
+  for (int k = 0; k < kNetMaps; ++k) {
+    const int64_t m = n, tpr = (m + 15) / 16;
+    t->act[k] = cv.take<uint8_t>(tpr * tpr * m);
   }
   t->dW = cv.take<float>(param_total());
   t->zbuf = cv.take<float>(V1);
@@ -139,7 +148,9 @@ size_t carve_net(int n, char* base, UNetState* s) {
   return cv.off;
 }
 
-NetSrc src1(const __bf16* a, int ca) { return NetSrc{a, nullptr, ca, 0, 0}; }
+NetSrc src1(const __bf16* a, int ca, const uint8_t* act = nullptr) {
+  return NetSrc{a, nullptr, ca, 0, 0, act};
+}
 NetSrc srcup(const __bf16* coarse, int cc, const __bf16* skip, int cs) {
   return NetSrc{coarse, skip, cc, cs, 1};
 }
@@ -198,31 +209,29 @@ int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_in
   UNetState* s = c->net;
   const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
   const bool skip = !keep_input && s->skip_tiles;
-  const uint8_t* a1 = skip ? s->act[0] : nullptr;
-  const uint8_t* a2 = skip ? s->act[1] : nullptr;
-  const uint8_t* a3 = skip ? s->act[2] : nullptr;
+  auto A = [&](int id) -> const uint8_t* { return skip ? s->act[id] : nullptr; };
   launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
   int rc = SIM_OK;
   if (keep_input) {
     net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
     rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
   } else {
-    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags, a1);
+    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags, A(M0_1));
   }
   // c2 and c4 also write the 2x2x2 average pool of their output
-  rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1, a1), flags);
-  rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2, a2), flags);
-  rc |= conv(c, n2, 3, NET_EPI_RELU_POOL, src1(s->A2, 32), out_pool(s->E2, s->P2, a2), flags);
+  rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1, A(M0_2)), flags);
+  rc |= conv(c, n2, 2, NET_EPI_RELU, src1(s->P1, 16), out_bf(s->A2, A(M1_5)), flags);
+  rc |= conv(c, n2, 3, NET_EPI_RELU_POOL, src1(s->A2, 32), out_pool(s->E2, s->P2, A(M1_7)), flags);
   rc |= conv(c, n3, 4, NET_EPI_RELU, src1(s->P2, 32), out_bf(s->A3), flags);
   rc |= conv(c, n3, 5, NET_EPI_RELU, src1(s->A3, 64), out_bf(s->E3), flags);
   // c7 = ReLU(upsampled half, on the coarse grid + skip half), likewise c9
-  rc |= split_conv(c, n2, 64, 32, s->E3, s->weff7, s->T2, src1(s->E2, 32), s->wskip7, s->B2, flags,
-                   a3, a2);
-  rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32), out_bf(s->D2, a2), flags);
-  rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16), s->wskip9, s->B1, flags,
-                   a2, a1);
-  rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16), out_bf(s->D1, a1), flags);
-  net_conv_out(c, n1, s->D1, s->wf[10], z, c->scal + S_NET_RMS, flags, a1);
+  rc |= split_conv(c, n2, 64, 32, s->E3, s->weff7, s->T2, src1(s->E2, 32, A(M1_7)), s->wskip7, s->B2,
+                   flags, A(M2_5), A(M1_5));
+  rc |= conv(c, n2, 7, NET_EPI_RELU, src1(s->B2, 32, A(M1_5)), out_bf(s->D2, A(M1_3)), flags);
+  rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16, A(M0_2)), s->wskip9, s->B1,
+                   flags, A(M1_2), A(M0_2));
+  rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16, A(M0_2)), out_bf(s->D1, A(M0_1)), flags);
+  net_conv_out(c, n1, s->D1, s->wf[10], z, c->scal + S_NET_RMS, flags, A(M0_1), A(M0_0));
   return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
 }
 
@@ -271,17 +280,29 @@ void pack_all(sim_ctx* c, const float* master) {
   net_pack_split(c, master + param_offset(8), 48, 16, 32, 16, c->net->weff9, c->net->wskip9);
 }
 
-// Where the forward activations can be non-zero.  The convolutions are
-// bias-free, every activation but the output is a ReLU or a pooling of one,
-// and the input (r / rms, mask) vanishes off liquid, so an activation is
-// zero wherever its receptive field holds no liquid cell.  In fine voxels of
-// Chebyshev distance d to the nearest liquid cell: a 3x3x3 convolution at
-// level l reaches 2^(l-1) voxels further, a 2x2x2 pooling adds 1 (level 2)
-// or 2 (level 3) for the alignment to its block, and the nearest upsampling
-// adds nothing.  Through the network that gives d <= 2 (c2), 7 (c4), 17
-// (c6), 21 (c8) and 23 (c10): every activation voxel that is non-zero has
-// its whole fine block within kSupport = 24 of liquid.
-constexpr int kSupport = 24;
+// Which tiles the inference pass computes.  Distances are Chebyshev
+// distances d, in fine voxels, to the nearest liquid cell; a voxel of a
+// coarser level stands for its fine block.
+//
+// Non-zero bound: the convolutions are bias-free, every activation but the
+// output is a ReLU or a pooling of one, and the input (r / rms, mask)
+// vanishes off liquid, so an activation is zero wherever its receptive field
+// holds no liquid cell.  A 3x3x3 convolution at level l reaches 2^(l-1)
+// fine voxels further, a 2x2x2 pooling adds 1 (level 2) or 2 (level 3) for
+// the alignment to its block, nearest upsampling adds nothing: c1 <= 1,
+// c2 <= 2, c3 <= 5, c4 <= 7, c6 <= 17, c8 <= 21, c10 <= 23.
+//
+// Needed bound: z is masked to liquid, so c11 needs c10's output only within
+// d <= 1, which needs c9's within 2, whose upsampled half needs c8's within
+// 3 (of a fine voxel of its block), which needs c7's within 3 + 2 = 5, which
+// needs c4's within 7.  Values outside these sets never reach z.
+//
+// Each layer computes the tiles that hold a voxel within the smaller of its
+// two bounds.  Skipped tiles of layers limited by the non-zero bound hold
+// zeros (the workspace is cleared once and no pass writes anything else
+// there); skipped tiles of layers limited by the needed bound may hold stale
+// values, which only ever feed other unneeded values.
+// (the maps, MapId, are listed with the network's constants above)
 
 // dilation of a 0/1 volume by a cube of half-width r along one axis
 void dilate_axis(std::vector<uint8_t>& a, int n, int axis, int r) {
@@ -298,34 +319,40 @@ void dilate_axis(std::vector<uint8_t>& a, int n, int axis, int r) {
     }
 }
 
-// Activity maps of levels 1-3: map[(z * tpr + ty) * tpr + tx] = 1 when a
-// voxel of the 16 x 16 tile (tx, ty) of plane z, or of its one-voxel halo,
-// has a fine block within kSupport of liquid.
-void activity_maps(int n, const uint8_t* cell, std::vector<uint8_t> maps[3]) {
+// Activity maps: maps[k][(z * tpr + ty) * tpr + tx] = 1 when a voxel of the
+// 16 x 16 tile (tx, ty) of plane z of level kMapLevel[k], or of its
+// one-voxel halo, has a fine block voxel within kMapRadius[k] of liquid.
+void activity_maps(int n, const uint8_t* cell, std::vector<uint8_t> maps[kMaps]) {
   const int64_t C = (int64_t)n * n * n;
   std::vector<uint8_t> near(C);
   for (int64_t q = 0; q < C; ++q) near[q] = cell[q] == 1;
-  for (int axis = 0; axis < 3; ++axis) dilate_axis(near, n, axis, kSupport);
-  for (int l = 0; l < 3; ++l) {
-    const int m = n >> l, b = 1 << l, tpr = (m + 15) / 16;
-    // level voxel live when any voxel of its fine block is
-    std::vector<uint8_t> lv((size_t)m * m * m, 0);
-    for (int z = 0; z < n; ++z)
-      for (int y = 0; y < n; ++y)
-        for (int x = 0; x < n; ++x)
-          if (near[x + (int64_t)n * (y + (int64_t)n * z)])
-            lv[x / b + (int64_t)m * (y / b + (int64_t)m * (z / b))] = 1;
-    maps[l].assign((size_t)tpr * tpr * m, 0);
-    for (int z = 0; z < m; ++z)
-      for (int y = 0; y < m; ++y)
-        for (int x = 0; x < m; ++x) {
-          if (!lv[x + (int64_t)m * (y + (int64_t)m * z)]) continue;
-          // every tile whose halo-extended square holds (x, y)
-          for (int ty = std::max(0, (y - 16) / 16); ty <= std::min(tpr - 1, (y + 1) / 16); ++ty)
-            for (int tx = std::max(0, (x - 16) / 16); tx <= std::min(tpr - 1, (x + 1) / 16); ++tx)
-              if (x >= 16 * tx - 1 && x <= 16 * tx + 16 && y >= 16 * ty - 1 && y <= 16 * ty + 16)
-                maps[l][((size_t)z * tpr + ty) * tpr + tx] = 1;
-        }
+  int radius = 0;
+  for (int r : {0, 1, 2, 3, 5, 7}) {
+    // near: within r of liquid (dilations by a cube compose)
+    for (int axis = 0; axis < 3 && r > radius; ++axis) dilate_axis(near, n, axis, r - radius);
+    radius = r;
+    for (int k = 0; k < kMaps; ++k) {
+      if (kMapRadius[k] != r) continue;
+      const int l = kMapLevel[k], m = n >> l, b = 1 << l, tpr = (m + 15) / 16;
+      // level voxel live when any voxel of its fine block is
+      std::vector<uint8_t> lv((size_t)m * m * m, 0);
+      for (int z = 0; z < m * b; ++z)
+        for (int y = 0; y < m * b; ++y)
+          for (int x = 0; x < m * b; ++x)
+            if (near[x + (int64_t)n * (y + (int64_t)n * z)])
+              lv[x / b + (int64_t)m * (y / b + (int64_t)m * (z / b))] = 1;
+      maps[k].assign((size_t)tpr * tpr * m, 0);
+      for (int z = 0; z < m; ++z)
+        for (int y = 0; y < m; ++y)
+          for (int x = 0; x < m; ++x) {
+            if (!lv[x + (int64_t)m * (y + (int64_t)m * z)]) continue;
+            // every tile whose halo-extended square holds (x, y)
+            for (int ty = std::max(0, (y - 16) / 16); ty <= std::min(tpr - 1, (y + 1) / 16); ++ty)
+              for (int tx = std::max(0, (x - 16) / 16); tx <= std::min(tpr - 1, (x + 1) / 16); ++tx)
+                if (x >= 16 * tx - 1 && x <= 16 * tx + 16 && y >= 16 * ty - 1 && y <= 16 * ty + 16)
+                  maps[k][((size_t)z * tpr + ty) * tpr + tx] = 1;
+          }
+    }
   }
 }
 
@@ -340,11 +367,11 @@ int net_init(sim_ctx* c, const uint8_t* h_cell) {
   c->net = s;
   // the inference pass never writes the tiles it skips: clear the whole
   // network workspace once, so they read as zero
-  std::vector<uint8_t> maps[3];
+  std::vector<uint8_t> maps[kMaps];
   activity_maps(c->n, h_cell, maps);
   if (hipMemsetAsync(c->net_ws, 0, c->net_ws_bytes, c->stream) != hipSuccess) return SIM_ERR_HIP;
-  for (int l = 0; l < 3; ++l)
-    if (hipMemcpyAsync(s->act[l], maps[l].data(), maps[l].size(), hipMemcpyHostToDevice,
+  for (int k = 0; k < kMaps; ++k)
+    if (hipMemcpyAsync(s->act[k], maps[k].data(), maps[k].size(), hipMemcpyHostToDevice,
                        c->stream) != hipSuccess)
       return SIM_ERR_HIP;
   // the host vectors must outlive the copies

@@ -14,6 +14,9 @@ struct NetSrc {
   const __bf16* a;
   const __bf16* b;
   int ca, cb, up;
+  // activity map of the input (nullable: the output's, NetOut::act): input
+  // planes of a tile marked 0 are read as zero
+  const uint8_t* act;
 };
 
 enum NetEpi {
@@ -33,12 +36,12 @@ struct NetOut {
   const __bf16* relu_of;    // MASKGRAD: post-activation whose ReLU the gradient passes
   const _Float16* add;      // RELU_ADD: fp16 partial sums [voxel][c_out] added before ReLU
   __bf16* pool;             // RELU_POOL: pooled output at half resolution [voxel][c_out]
-  // Tile-plane activity map of the output level (nullable: every tile is
-  // live), index (z * tiles_per_row + ty) * tiles_per_row + tx over the
-  // 16 x 16 xy-tiles.  Where it holds 0, the tile of that plane, with its
-  // one-voxel halo, is known to be zero in every forward activation of the
-  // level: the z-marching kernels neither load it nor store it (the
-  // buffers hold zeros there); the output layer stores zeros.
+  // Tile-plane activity map of the output (nullable: every tile is live),
+  // index (z * tiles_per_row + ty) * tiles_per_row + tx over the 16 x 16
+  // xy-tiles.  Where it holds 0, no voxel of that tile and plane (with its
+  // one-voxel halo) is needed: its values are zero, or nothing downstream
+  // that reaches the network's output reads them.  The z-marching kernels
+  // neither compute nor store such a tile; the output layer stores zeros.
   const uint8_t* act;
 };
 
@@ -79,9 +82,9 @@ void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
                const int* flags);
 // c11 (16 -> 1) fused with the output map: z = mask * rms * conv(D), on the
 // vector ALU (bf16 dot products); w is the layer's packed forward weights.
-// act (nullable): activity map of the level.
+// act_in, act (nullable, both or neither): activity maps of D and of z.
 void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z, const double* rms,
-                  const int* flags, const uint8_t* act);
+                  const int* flags, const uint8_t* act_in, const uint8_t* act);
 // c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
 // rms written to rms_out; the 2-channel input is never stored.  r is read on
 // liquid cells only.  act (nullable): activity map of the level.
