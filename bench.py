@@ -39,7 +39,7 @@ BF16_PEAK_TFLOPS = 2500.0
 # Algorithmic bytes per unit (cell, or face for the viscosity CG) of each
 # timed kernel kind: every array the operation must read or write once.
 BYTES_PER_UNIT = {
-    "pcg_dir_spmv": 17.0,   # r 4 + diag 1 + d 4 in; d 4 + q 4 out
+    "pcg_dir_spmv": 17.0,   # r 4 + diag 1 + d 4 in; d 4 + q 4 out (Jacobi; 21 flexible CG)
     # Jacobi PCG and the flexible CG update the FP64 iterate every fourth
     # iteration: three of four iterations move r 4+4, q 4, diag 1 (13 B), the
     # fourth also x 8+8 and four directions 4x4 (45 B); the average is 21 B.
@@ -168,6 +168,8 @@ def rooflines(prof, n, precond):
         per_unit = BYTES_PER_UNIT[kind]
         if kind == "pcg_update" and precond == "mic0":
             per_unit = 33.0
+        if kind == "pcg_dir_spmv" and precond == "learned":
+            per_unit = 21.0  # z 4 + d 4 + r 4 (the flexible-CG dot) + diag 1 in; d 4 + q 4 out
         per_launch = per_unit * units
         avg_s = ms_tot / launches / 1e3
         achieved = per_launch / avg_s / 1e9

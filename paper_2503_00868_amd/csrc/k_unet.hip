@@ -94,6 +94,12 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int OUT_E = TX * TY * TZ * COUT;
   constexpr int LDS_E = HALO_E > OUT_E ? HALO_E : OUT_E;
   __shared__ __attribute__((aligned(16))) __bf16 lds[LDS_E];
+  // 64-output-channel layers (the coarsest level) stage each chunk's weights
+  // in LDS as [tap][half][c_out][8]: the 16 lanes of a fragment read
+  // consecutive 16-byte words, and no step waits on an L2 load
+  constexpr bool WL = CK == 16 && COUT == 64;
+  constexpr int WL_E = WL ? TAPS * 2 * COUT * 8 : 8;
+  __shared__ __attribute__((aligned(16))) __bf16 wl[WL_E];
   const TileXYZ t = tile_of(n, blockIdx.x);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   f32x4 acc[4][NT];
@@ -105,6 +111,13 @@ __global__ void __launch_bounds__(kBlock)
   for (int c0 = 0; c0 < CIN; c0 += CK) {
     __syncthreads();
     load_halo<CK>(lds, src, n, t, c0);
+    if (WL) {
+      for (int q = threadIdx.x; q < TAPS * 2 * COUT; q += kBlock) {
+        const int co = q % COUT, half = (q / COUT) & 1, tap = q / (2 * COUT);
+        *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) = *reinterpret_cast<const uint4*>(
+            w + ((int64_t)co * TAPS + tap) * CIN + c0 + half * 8);
+      }
+    }
     __syncthreads();
 #pragma unroll 2
     for (int s = 0; s < STEPS; ++s) {
@@ -115,8 +128,9 @@ __global__ void __launch_bounds__(kBlock)
       bf16x8 bfr[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b)
-        bfr[b] = *reinterpret_cast<const bf16x8*>(
-            w + ((int64_t)(b * 16 + col) * TAPS + tap) * CIN + c0 + coff);
+        bfr[b] = WL ? *reinterpret_cast<const bf16x8*>(wl + ((tap * 2 + (g & 1)) * COUT + b * 16 + col) * 8)
+                    : *reinterpret_cast<const bf16x8*>(
+                          w + ((int64_t)(b * 16 + col) * TAPS + tap) * CIN + c0 + coff);
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int hv = (col + dx) + HX * ((a + dy) + HY * (wv + dz));
