@@ -245,7 +245,10 @@ int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, cons
  * the kernels below (the finalize reductions are not included); durations
  * accumulate per kind until read.  sim_profile_read synchronises the
  * stream, writes SIM_KERN_COUNT totals in milliseconds and launch counts,
- * and resets them.  Every 1<<15 timed launches the library waits for the
+ * and resets them.  For the CG kinds and the network, whose kernels return
+ * at once when the solve has already converged (the library enqueues a
+ * block of iterations ahead of its convergence test), the count is of the
+ * launches that did work; the time includes the others.  Every 1<<15 timed launches the library waits for the
  * stream once to fold the recorded events into the totals. */
 enum {
     SIM_KERN_PCG_DIR_SPMV = 0,  /* d = M^-1 r + beta d ; q = A d ; d.q            */

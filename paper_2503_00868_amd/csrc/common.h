@@ -110,6 +110,12 @@ __device__ inline void block_sum(double (&v)[NV]) {
 // grid) and turns them into solver scalars.  A kernel boundary, not a
 // device-scope fence per block, makes the partials visible: on this chip a
 // release fence per block costs ~20 ns each, serialised.
+// Counts a launch that did work (passed its done check) for the timing
+// hooks: block (0, 0) adds one to *work (nullable).
+__device__ inline void count_work(int* work) {
+  if (work && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(work, 1);
+}
+
 template <int NV>
 __device__ inline void store_partials(double (&v)[NV], double* partials, int block_id) {
   block_sum<NV>(v);

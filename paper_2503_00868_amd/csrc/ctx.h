@@ -112,6 +112,7 @@ struct sim_ctx {
   double* partials = nullptr;
   double* scal = nullptr;
   int* flags = nullptr;
+  int* work = nullptr;  // SIM_KERN_COUNT counters: launches that did work (timing hooks)
 
   // rollout recording
   float* ckpt = nullptr;  // (ckpt_slots) x 3F

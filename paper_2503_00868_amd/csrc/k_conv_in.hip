@@ -43,8 +43,9 @@ __global__ void __launch_bounds__(kBlock)
     k_conv_in(int n, int zc, const float* __restrict__ r, const uint8_t* __restrict__ cdiag,
               const double* __restrict__ sumsq, double n_liquid, double* __restrict__ rms_out,
               const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags,
-              const uint8_t* __restrict__ act) {
+              const uint8_t* __restrict__ act, int* __restrict__ work) {
   if (flags && flags[F_DONE]) return;
+  count_work(work);
   __shared__ uint32_t ring[4][IRV];  // (r / rms, mask) as two bf16; four slots as in k_conv_zm
   __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * IT * 16];
   const double rms = n_liquid > 0.0 ? sqrt(*sumsq / n_liquid) : 0.0;
@@ -195,10 +196,11 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
-                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act) {
+                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act,
+                 int* work) {
   const InGrid g = in_grid(c->n);
   hipLaunchKernelGGL(k_conv_in, dim3(g.blocks), dim3(kBlock), 0, c->stream, c->n, g.zc, r,
-                     c->cdiag, sumsq, (double)c->n_liquid, rms_out, w, out, flags, act);
+                     c->cdiag, sumsq, (double)c->n_liquid, rms_out, w, out, flags, act, work);
 }
 
 }  // namespace fs

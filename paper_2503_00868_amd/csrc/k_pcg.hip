@@ -253,8 +253,9 @@ __global__ void __launch_bounds__(kBlock)
     k_dir_spmv(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
                const float* __restrict__ z, const float* __restrict__ d_in,
                float* __restrict__ d_out, float* __restrict__ q, const double* __restrict__ scal,
-               const int* __restrict__ flags, double* partials) {
+               const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int64_t G = cells(n) / V;
   const float beta = (float)scal[S_BETA];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -424,8 +425,9 @@ __global__ void __launch_bounds__(kBlock)
     k_dir_spmv_zm(int n, int zc, const uint8_t* __restrict__ cdiag, const float* __restrict__ r,
                   const float* __restrict__ z, const float* __restrict__ d_in,
                   float* __restrict__ d_out, float* __restrict__ q, const double* __restrict__ scal,
-                  const int* __restrict__ flags, double* partials) {
+                  const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   __shared__ float sd[ZM_TY + 2][ZM_W];
   const float beta = (float)scal[S_BETA];
   const ZTile t = ztile(n, zc);
@@ -528,8 +530,9 @@ template <int PREC>
 __global__ void __launch_bounds__(kBlock)
     k_check_zm(int n, int zc, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
                const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
-               double* partials) {
+               double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   __shared__ double sx[ZM_TY + 2][ZM_W];
   const ZTile t = ztile(n, zc);
   const int64_t sz = (int64_t)n * n;
@@ -618,8 +621,9 @@ __global__ void __launch_bounds__(kBlock)
     k_update2(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
               float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ d_prev,
               const float* __restrict__ q, double* __restrict__ scal,
-              const int* __restrict__ flags, double* partials) {
+              const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int64_t G = cells(n) / V;
   const double alpha = scal[S_RZ] / scal[S_DQ];
   const double alpha_prev = scal[S_ALPHA_PREV];
@@ -666,8 +670,9 @@ __global__ void __launch_bounds__(kBlock)
               float* __restrict__ r, const float* __restrict__ d0, const float* __restrict__ d1,
               const float* __restrict__ d2, const float* __restrict__ d3,
               const float* __restrict__ q, double* __restrict__ scal, int phase,
-              const int* __restrict__ flags, double* partials) {
+              const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int64_t G = cells(n) / V;
   const double alpha = (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
   const float alpha_f = (float)alpha;
@@ -718,8 +723,9 @@ template <int V, int PREC, bool FLEX>
 __global__ void __launch_bounds__(kBlock)
     k_update(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
              float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
-             const double* __restrict__ scal, const int* __restrict__ flags, double* partials) {
+             const double* __restrict__ scal, const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int64_t G = cells(n) / V;
   const double alpha = (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
   const float alpha_f = (float)alpha;
@@ -775,8 +781,9 @@ template <int V, int PREC>
 __global__ void __launch_bounds__(kBlock)
     k_check(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
             const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
-            double* partials) {
+            double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int64_t G = cells(n) / V;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const Run run = group_run(G, gridDim.x, lb);
@@ -939,14 +946,15 @@ static int dir_spmv_any(sim_ctx* c, int prec, const float* d_in, float* d_out) {
     if (prec == PK_JACOBI)
       hipLaunchKernelGGL((k_dir_spmv_zm<PK_JACOBI, FLEX>), dim3(zs.blocks), dim3(kBlock), 0,
                          c->stream, c->n, zs.zc, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal,
-                         c->flags, c->partials);
+                         c->flags, c->partials, c->work + SIM_KERN_PCG_DIR_SPMV);
     else
       hipLaunchKernelGGL((k_dir_spmv_zm<PK_ZARRAY, FLEX>), dim3(zs.blocks), dim3(kBlock), 0,
                          c->stream, c->n, zs.zc, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal,
-                         c->flags, c->partials);
+                         c->flags, c->partials, c->work + SIM_KERN_PCG_DIR_SPMV);
     return zs.blocks;
   }
-#define ARGS c->n, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal, c->flags, c->partials
+#define ARGS c->n, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal, c->flags, c->partials, \
+             c->work + SIM_KERN_PCG_DIR_SPMV
   if (prec == PK_JACOBI)
     hipLaunchKernelGGL((k_dir_spmv<1, PK_JACOBI, FLEX>), dim3(c->grid_cells), dim3(kBlock), 0,
                        c->stream, ARGS);
@@ -965,7 +973,8 @@ void launch_pcg_dir_spmv(sim_ctx* c, int prec, const float* d_in, float* d_out) 
 }
 
 void launch_pcg_update(sim_ctx* c, int prec, const float* d) {
-#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials
+#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials, \
+             c->work + SIM_KERN_PCG_UPDATE
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   if (prec == PK_JACOBI) {
     FS_CELL_LAUNCH(k_update, PK_JACOBI, false);
@@ -979,7 +988,8 @@ void launch_pcg_update(sim_ctx* c, int prec, const float* d) {
 }
 
 void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool with_x) {
-#define ARGS c->n, c->cdiag, c->x, c->r, d, d_prev, c->q, c->scal, c->flags, c->partials
+#define ARGS c->n, c->cdiag, c->x, c->r, d, d_prev, c->q, c->scal, c->flags, c->partials, \
+             c->work + SIM_KERN_PCG_UPDATE
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   if (with_x)
     FS_CELL_LAUNCH(k_update2, true);
@@ -992,7 +1002,7 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
 
 void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
 #define ARGS c->n, c->cdiag, c->x, c->r, dirs[0], dirs[1], dirs[2], dirs[3], c->q, c->scal, \
-             phase, c->flags, c->partials
+             phase, c->flags, c->partials, c->work + SIM_KERN_PCG_UPDATE
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   if (phase == 3)
     FS_CELL_LAUNCH(k_update4, true, false);
@@ -1037,12 +1047,14 @@ void launch_pcg_check(sim_ctx* c, int prec, double tol) {
     nb = zs.blocks;
     if (prec == PK_JACOBI)
       hipLaunchKernelGGL((k_check_zm<PK_JACOBI>), dim3(zs.blocks), dim3(kBlock), 0, c->stream,
-                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials);
+                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials,
+                         c->work + SIM_KERN_PCG_CHECK);
     else
       hipLaunchKernelGGL((k_check_zm<PK_ZARRAY>), dim3(zs.blocks), dim3(kBlock), 0, c->stream,
-                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials);
+                         c->n, zs.zc, c->cdiag, c->b, c->x, c->r, c->flags, c->partials,
+                         c->work + SIM_KERN_PCG_CHECK);
   } else {
-#define ARGS c->n, c->cdiag, c->b, c->x, c->r, c->flags, c->partials
+#define ARGS c->n, c->cdiag, c->b, c->x, c->r, c->flags, c->partials, c->work + SIM_KERN_PCG_CHECK
     if (prec == PK_JACOBI)
       hipLaunchKernelGGL((k_check<1, PK_JACOBI>), dim3(c->grid_cells), dim3(kBlock), 0, c->stream,
                          ARGS);
@@ -1091,7 +1103,8 @@ void launch_fcg_dir_spmv(sim_ctx* c, const float* d_in, float* d_out) {
 }
 
 void launch_fcg_update(sim_ctx* c, const float* d) {
-#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials
+#define ARGS c->n, c->cdiag, c->x, c->r, d, c->q, c->scal, c->flags, c->partials, \
+             c->work + SIM_KERN_PCG_UPDATE
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   FS_CELL_LAUNCH(k_update, PK_ZARRAY, true);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
@@ -1194,8 +1207,9 @@ __global__ void __launch_bounds__(kBlock)
                    const float* __restrict__ r, const float* __restrict__ d_in,
                    float* __restrict__ d_out, float* __restrict__ q, int64_t F,
                    const double* __restrict__ scal, const int* __restrict__ flags,
-                   double* partials) {
+                   double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
   const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
@@ -1261,8 +1275,9 @@ __global__ void __launch_bounds__(kBlock)
                       const float* __restrict__ r, const float* __restrict__ d_in,
                       float* __restrict__ d_out, float* __restrict__ q, int64_t F,
                       const double* __restrict__ scal, const int* __restrict__ flags,
-                      double* partials) {
+                      double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   __shared__ float sd[DZ_TY + 2][DZ_TX + 2];
   const int comp = blockIdx.y;
   const Dims dm3 = face_dims(n, comp);
@@ -1399,8 +1414,9 @@ __global__ void __launch_bounds__(kBlock)
     k_dcg_update(const uint8_t* __restrict__ fcode, float alpha, double* __restrict__ x,
                  float* __restrict__ r, const float* __restrict__ d, const float* __restrict__ q,
                  int64_t F, const double* __restrict__ scal, const int* __restrict__ flags,
-                 double* partials) {
+                 double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
+  count_work(work);
   const int comp = blockIdx.y;
   const double a = scal[S_RZ] / scal[S_DQ];
   const float af = (float)a;
@@ -1474,14 +1490,15 @@ void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_ou
   const int nb = sh.tiles * sh.chunks;
   if (3 * nb <= kPartialDoubles) {
     hipLaunchKernelGGL(k_dcg_dir_spmv_zm, dim3(nb, 3), dim3(kBlock), 0, c->stream, c->n, c->fcode,
-                       alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags, c->partials);
+                       alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags, c->partials,
+                       c->work + SIM_KERN_DCG_DIR_SPMV);
     prof_mark(c, SIM_KERN_DCG_DIR_SPMV, false);
     launch_finalize(c, 3 * nb, 1, FIN_DQ, 0.0, 0, 0, 0.0, 0);
     return;
   }
   hipLaunchKernelGGL(k_dcg_dir_spmv, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
                      c->fcode, alpha, c->fr, d_in, d_out, c->fq, c->F, c->scal, c->flags,
-                     c->partials);
+                     c->partials, c->work + SIM_KERN_DCG_DIR_SPMV);
   prof_mark(c, SIM_KERN_DCG_DIR_SPMV, false);
   launch_finalize(c, 3 * c->grid_faces, 1, FIN_DQ, 0.0, 0, 0, 0.0, 0);
 }
@@ -1489,7 +1506,8 @@ void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_ou
 void launch_dcg_update(sim_ctx* c, float alpha, const float* d) {
   prof_mark(c, SIM_KERN_DCG_UPDATE, true);
   hipLaunchKernelGGL(k_dcg_update, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->fcode,
-                     alpha, c->fx, c->fr, d, c->fq, c->F, c->scal, c->flags, c->partials);
+                     alpha, c->fx, c->fr, d, c->fq, c->F, c->scal, c->flags, c->partials,
+                     c->work + SIM_KERN_DCG_UPDATE);
   prof_mark(c, SIM_KERN_DCG_UPDATE, false);
   launch_finalize(c, 3 * c->grid_faces, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }

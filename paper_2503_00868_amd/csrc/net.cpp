@@ -216,7 +216,8 @@ int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_in
     net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
     rc |= conv(c, n1, 0, NET_EPI_RELU, src1(s->X0, 8), out_bf(s->A1), flags);
   } else {
-    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags, A(M0_1));
+    net_conv_in(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->wf[0], s->A1, flags, A(M0_1),
+                c->work + SIM_KERN_NET);
   }
   // c2 and c4 also write the 2x2x2 average pool of their output
   rc |= conv(c, n1, 1, NET_EPI_RELU_POOL, src1(s->A1, 16), out_pool(s->E1, s->P1, A(M0_2)), flags);

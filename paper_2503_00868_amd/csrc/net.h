@@ -87,9 +87,11 @@ void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z,
                   const int* flags, const uint8_t* act_in, const uint8_t* act);
 // c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
 // rms written to rms_out; the 2-channel input is never stored.  r is read on
-// liquid cells only.  act (nullable): activity map of the level.
+// liquid cells only.  act (nullable): activity map of the level.  work
+// (nullable): counter of applications that did work.
 void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
-                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act);
+                 const __bf16* w, __bf16* out, const int* flags, const uint8_t* act,
+                 int* work);
 void net_loss_grad(sim_ctx* c, const float* r, const float* Az, const double* dots,
                    const double* rms, __bf16* g11);
 void net_upsum_mask(sim_ctx* c, int n_fine, int Cc, int Ct, const __bf16* T, const __bf16* P,

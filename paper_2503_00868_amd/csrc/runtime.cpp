@@ -132,6 +132,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   char* ctrl = cv.take<char>(kCtrlBytes);
   t->scal = reinterpret_cast<double*>(ctrl);
   t->flags = ctrl ? reinterpret_cast<int*>(ctrl + S_COUNT * sizeof(double)) : nullptr;
+  t->work = cv.take<int>(SIM_KERN_COUNT);
   if (recording_enabled(d)) {
     t->ckpt_slots = (d.max_steps + d.checkpoint_every - 1) / d.checkpoint_every;
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
@@ -640,6 +641,8 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   if (hipMemcpyAsync(c->cell, h_cell_type, c->C, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return fail(SIM_ERR_HIP);
   if (hipMemsetAsync(c->scal, 0, kCtrlBytes, c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
+  if (hipMemsetAsync(c->work, 0, sizeof(int) * SIM_KERN_COUNT, c->stream) != hipSuccess)
+    return fail(SIM_ERR_HIP);
   for (double* wbuf : {c->xw, c->xwa})
     if (wbuf && hipMemsetAsync(wbuf, 0, sizeof(double) * c->C, c->stream) != hipSuccess)
       return fail(SIM_ERR_HIP);
@@ -676,6 +679,7 @@ int sim_profile_enable(sim_ctx* c, int32_t on) {
     c->prof->used = 0;
     c->prof->open = -1;
     for (int k = 0; k < SIM_KERN_COUNT; ++k) c->prof->ms[k] = 0.0, c->prof->launches[k] = 0;
+    HIPCHK(hipMemsetAsync(c->work, 0, sizeof(int) * SIM_KERN_COUNT, c->stream));
   }
   return SIM_OK;
 }
@@ -693,9 +697,17 @@ int sim_profile_read(sim_ctx* c, double* h_ms, int64_t* h_launches) {
   if (p->open >= 0) p->used = p->open;  // drop an unmatched begin
   HIPCHK(prof_drain(p));
   p->open = -1;
+  // kinds whose kernels return at once once the solve has converged (the
+  // launches of a block enqueued ahead): count the launches that did work
+  int work[SIM_KERN_COUNT];
+  HIPCHK(hipMemcpy(work, c->work, sizeof work, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemsetAsync(c->work, 0, sizeof work, c->stream));
   for (int k = 0; k < SIM_KERN_COUNT; ++k) {
+    const bool skips = k == SIM_KERN_PCG_DIR_SPMV || k == SIM_KERN_PCG_UPDATE ||
+                       k == SIM_KERN_PCG_CHECK || k == SIM_KERN_DCG_DIR_SPMV ||
+                       k == SIM_KERN_DCG_UPDATE || k == SIM_KERN_NET;
     h_ms[k] = p->ms[k];
-    h_launches[k] = p->launches[k];
+    h_launches[k] = skips ? std::min<int64_t>(work[k], p->launches[k]) : p->launches[k];
     p->ms[k] = 0.0;
     p->launches[k] = 0;
   }
