@@ -78,10 +78,12 @@ def _ball_mask(n, centre, radius):
 
 @pytest.mark.parametrize("n,which", [(128, "ball"), (128, "seed4"), (96, "ball"), (64, "seed4")])
 def test_tile_skip_is_bitwise_dense(torch_gpu, n, which):
-    """The inference pass skips the tiles farther than 24 fine cells from
-    liquid (every activation is zero there); its output must be bitwise the
-    dense pass's, for random and for the trained weights, and for an FCG
-    projection the iteration count and the pressure must agree bitwise."""
+    """The inference pass skips, per layer, the tiles beyond the smaller of
+    two distances to liquid: where the layer's activations must be zero, and
+    where they can still reach the liquid-masked output.  Its output must be
+    bitwise the dense pass's, for random and for the trained weights, and
+    for an FCG projection the iteration count and the pressure must agree
+    bitwise."""
     torch = torch_gpu
     from paper_2503_00868_amd.train import DEFAULT_WEIGHTS
     banner(f"tile skipping vs dense, n={n} {which}")

@@ -127,9 +127,9 @@ def test_activation_support_radius(p):
     weights (so every voxel the receptive field reaches is strictly
     positive): the Chebyshev distance in fine cells from the liquid cell to
     the farthest fine cell under a non-zero voxel.  The library's inference
-    pass skips tiles farther than 24 fine cells from liquid, which is exact
-    only if no activation reaches beyond 23; the counts are 2^(l-1) per
-    convolution at level l, plus the block alignment of each pooling."""
+    pass relies on these reaches (its maps for the encoder layers use them
+    as radii); the counts are 2^(l-1) per convolution at level l, plus the
+    block alignment of each pooling."""
     n = 64
     W = unet.split_weights(np.full(unet.param_count(), 0.01, np.float32))
     r = np.zeros((n, n, n))
