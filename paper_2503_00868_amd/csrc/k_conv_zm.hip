@@ -1,6 +1,6 @@
-// Full-resolution convolutions of the learned preconditioner (the 16-channel
-// level of the U-Net and the layers around it): a z-marching implicit GEMM on
-// the 16x16x32 bf16 MFMA of gfx950.
+// Convolutions of the learned preconditioner's two finer levels (and their
+// data gradients in training): a z-marching implicit GEMM on the 16x16x32
+// bf16 MFMA of gfx950.
 //
 // A block owns a 16 x 16 tile of the xy-plane and walks a run of z-planes.
 // The three input planes z-1, z, z+1 (with a one-voxel xy halo, 18 x 18
@@ -13,7 +13,10 @@
 // take consecutive 16-byte words, free of LDS bank conflicts.
 //
 // MFMA mapping (lane layout checked on the device): M = 16 output voxels
-// along x, N = 16 output channels, K = 32.  A K-step pairs two taps of one
+// along x, N = 16 output channels, K = 32 (the layers with 32 or more
+// channels swap the operands, see k_conv_zm's epilogue; the A and B register
+// layouts are the same, so only the output layout changes).  A K-step pairs
+// two taps of one
 // 16-channel chunk: lanes 0-31 carry tap T0, lanes 32-63 tap T1.  The 27
 // taps form 15 steps per chunk:
 //   steps 0-8    (dx, dy) = (s % 3, s / 3), T0 = dz 0, T1 = dz 1

@@ -56,8 +56,9 @@ int net_apply(sim_ctx* c, const float* r, float* z, const int* flags);
 
 // kernel launchers
 int conv_tiles(int n);
-// z-marching kernels for the configurations (c_in, c_out) = (8|16|48, 16) and
-// (16, 48); false for any other configuration
+// z-marching kernels for the configurations (c_in, c_out) = (8|16|48, 16),
+// (16, 32), (32, 32) and (16, 48); false for any other
+// configuration
 bool net_conv_zm(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const __bf16* w,
                  NetOut out, const int* flags);
 bool net_conv(sim_ctx* c, int n, int cin, int cout, int epi, NetSrc src, const __bf16* w,
