@@ -150,3 +150,55 @@ def test_activation_support_radius(p):
     if odd:  # an alignment that reaches the bound exactly
         assert reach == bound, reach
     assert max(reach.values()) < 24
+
+
+def test_pruned_network_keeps_the_output():
+    """The library's inference pass computes each layer only within a radius
+    of liquid (the smaller of where the layer can be non-zero and where it can
+    still reach the liquid-masked output): c1 1, c2 2, c3 5, c4 7, c7 5, c8 3,
+    c9 2, c10 1 fine cells (a coarse voxel counts when a fine cell of its
+    block does).  Zeroing every activation outside its radius, voxel by voxel,
+    must leave z on the liquid cells exactly as it is, in FP64."""
+    n = 48
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    mask = ((xx - 12) ** 2 + (yy - 14) ** 2 + (zz - 10) ** 2 <= 36) | ((xx > 36) & (yy < 4))
+    rng = np.random.default_rng(5)
+    r = np.where(mask, rng.standard_normal((n, n, n)), 0.0)
+    W = [torch.as_tensor(w) for w in unet.split_weights(unet.init_weights(7))]
+    # Chebyshev distance to liquid, in fine cells
+    d = np.full((n, n, n), 10 ** 6)
+    pts = np.argwhere(mask)
+    for z, y, x in pts:
+        np.minimum(d, np.maximum(np.maximum(abs(zz - z), abs(yy - y)), abs(xx - x)), out=d)
+
+    def keep(t, radius):
+        f = n // t.shape[-1]
+        near = torch.as_tensor(d <= radius)
+        near = near.reshape(n // f, f, n // f, f, n // f, f).any(dim=5).any(dim=3).any(dim=1)
+        return t * near.to(t.dtype)
+
+    rms = float(np.sqrt((r * r * mask).sum() / mask.sum()))
+    x0 = torch.stack([torch.as_tensor(r / rms), torch.as_tensor(mask, dtype=torch.float64)])[None]
+
+    def run(prune):
+        k = (lambda t, rad: keep(t, rad)) if prune else (lambda t, rad: t)
+        conv = lambda x, w, relu=True: F.relu(F.conv3d(x, w, padding=1)) if relu else F.conv3d(x, w, padding=1)
+        a1 = k(conv(x0, W[0]), 1)
+        e1 = k(conv(a1, W[1]), 2)
+        a2 = k(conv(F.avg_pool3d(e1, 2), W[2]), 5)
+        e2 = k(conv(a2, W[3]), 7)
+        e3 = conv(conv(F.avg_pool3d(e2, 2), W[4]), W[5])
+        b2 = k(conv(torch.cat([F.interpolate(e3, scale_factor=2, mode="nearest"), e2], 1), W[6]), 5)
+        d2 = k(conv(b2, W[7]), 3)
+        b1 = k(conv(torch.cat([F.interpolate(d2, scale_factor=2, mode="nearest"), e1], 1), W[8]), 2)
+        d1 = k(conv(b1, W[9]), 1)
+        return conv(d1, W[10], relu=False)[0, 0].numpy()
+
+    dense, pruned = run(False), run(True)
+    # the dense pass is the oracle's network
+    np.testing.assert_allclose(mask * rms * dense, unet.forward(W, r, mask, emulate_bf16=False),
+                               rtol=0, atol=1e-12 * np.abs(dense).max() * rms)
+    assert np.abs(dense[mask]).max() > 0
+    assert np.array_equal(dense[mask], pruned[mask])
+    # the radii are tight enough to matter: pruning changes the activations
+    assert not np.array_equal(dense, pruned)
