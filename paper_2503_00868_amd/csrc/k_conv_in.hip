@@ -39,7 +39,7 @@ static InGrid in_grid(int n) {
 }
 
 // w: packed c1 weights [16][28][8] (forward layout, channels 0 = r, 1 = mask).
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
     k_conv_in(int n, int zc, const float* __restrict__ r, const uint8_t* __restrict__ cdiag,
               const double* __restrict__ sumsq, double n_liquid, double* __restrict__ rms_out,
               const __bf16* __restrict__ w, __bf16* __restrict__ out, const int* __restrict__ flags,
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kBlock)
     uint8_t m[PFI];
     bool ok[PFI];
   };
-  Raw ra;
+  Raw ra, rb;  // two planes in flight
   auto load_plane = [&](int zi, Raw& o) {
     const bool on = live(zi);
 #pragma unroll
@@ -135,12 +135,15 @@ __global__ void __launch_bounds__(kBlock)
   load_plane(z0, ra);
   int nz_0 = __syncthreads_or(store_plane(z0, ra));
   load_plane(z0 + 1, ra);
+  if (z0 + 2 <= z1) load_plane(z0 + 2, rb);
 
-  // one output plane: plane z+1 goes to the ring, plane z+2 is loaded while
-  // the MFMAs of plane z run
-  auto plane_step = [&](int z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1, ra));
-    if (z + 2 <= z1) load_plane(z + 2, ra);
+  // one output plane: plane z+1 (held in cur) goes to the ring, and cur
+  // takes the loads of plane z+3, which stay in flight for two planes
+  // (the per-plane work of this layer is too small to hide one load
+  // latency)
+  auto plane_step = [&](int z, Raw& cur) {
+    const int nz_p = __syncthreads_or(store_plane(z + 1, cur));
+    if (z + 3 <= z1) load_plane(z + 3, cur);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
     nz_0 = nz_p;
@@ -192,7 +195,10 @@ __global__ void __launch_bounds__(kBlock)
           *reinterpret_cast<const uint4*>(st + lv * 16 + part * 8);
     }
   };
-  for (int z = z0; z < z1; ++z) plane_step(z);
+  for (int z = z0; z < z1; z += 2) {
+    plane_step(z, ra);
+    if (z + 1 < z1) plane_step(z + 1, rb);
+  }
 }
 
 void net_conv_in(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,

@@ -95,30 +95,29 @@ __global__ void __launch_bounds__(kBlock)
     iok[k] = it < OITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
     ioff[k] = iok[k] ? (uint32_t)((((int64_t)gx + (int64_t)n * gy) * 16 + h * 8) * 2) : 0u;
   }
+  // the raw loads stay unmasked in registers while the current plane is
+  // computed; items outside the grid (loaded from a valid clamped address)
+  // and planes that read as zero are masked only when stored into the ring
   uint4 pf[OPF];
+  bool pf_on = false;  // block-uniform
   auto load_plane = [&](int zi) {
-    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-    if (!live_in(zi) || (unsigned)zi >= (unsigned)n) {
-#pragma unroll
-      for (int k = 0; k < OPF; ++k) pf[k] = zero;
-      return;
-    }
+    pf_on = live_in(zi) && (unsigned)zi < (unsigned)n;
+    if (!pf_on) return;
     const char* pl = reinterpret_cast<const char*>(D) + zi * nn * 32;
 #pragma unroll
-    for (int k = 0; k < OPF; ++k) {
-      const uint4 raw = *reinterpret_cast<const uint4*>(pl + ioff[k]);
-      pf[k] = iok[k] ? raw : zero;
-    }
+    for (int k = 0; k < OPF; ++k) pf[k] = *reinterpret_cast<const uint4*>(pl + ioff[k]);
   };
   // returns whether this thread's part of the plane holds a non-zero bit
   auto store_plane = [&](int slot) -> int {
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
     uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < OPF; ++k) {
       const int it = threadIdx.x + k * kBlock;
       if (it < OITEMS) {
-        ring[slot][it & 1][it >> 1] = pf[k];
-        any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
+        const uint4 v = pf_on && iok[k] ? pf[k] : zero;
+        ring[slot][it & 1][it >> 1] = v;
+        any |= v.x | v.y | v.z | v.w;
       }
     }
     return any != 0u;
@@ -132,13 +131,14 @@ __global__ void __launch_bounds__(kBlock)
     const int slot = p & 1;
     // the slot was last read for plane p - 2, before the previous barrier
     const int nz = __syncthreads_or(store_plane(slot));
-    if (p + 1 <= z1) load_plane(p + 1);
     // the output plane p - 1 is complete after this plane; its mask byte is
-    // fetched before the arithmetic
+    // loaded (from a clamped address) ahead of the next plane's loads, so
+    // that waiting for it does not wait for them
     const int o = p - 1;
     const bool out_here = o >= z0 && own;
-    uint8_t m = 0;
-    if (out_here && live(o)) m = mask[(int64_t)x + (int64_t)n * y + nn * o];
+    const bool want_m = out_here && live(o);
+    const uint8_t m_raw = mask[want_m ? (int64_t)x + (int64_t)n * y + nn * o : 0];
+    if (p + 1 <= z1) load_plane(p + 1);
     if (nz) {
       float c0 = 0.f, c1 = 0.f, c2 = 0.f;  // z-slices 0, 1, 2
 #pragma unroll
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kBlock)
       s_mid += c1;
       s_lo += c2;
     }
-    if (out_here) z[(int64_t)x + (int64_t)n * y + nn * o] = m ? rms * s_lo : 0.f;
+    if (out_here) z[(int64_t)x + (int64_t)n * y + nn * o] = want_m && m_raw ? rms * s_lo : 0.f;
     s_lo = s_mid;
     s_mid = s_hi;
     s_hi = 0.f;

@@ -186,35 +186,33 @@ __global__ void __launch_bounds__(kBlock)
   const int64_t plane_a = (int64_t)(src.up ? nc : n) * (src.up ? nc : n) * src.ca * 2;
   const int64_t plane_b = (int64_t)n * n * src.cb * 2;
 
-  // global -> registers for input plane zi (zero outside the volume and on
-  // planes known to be zero)
+  // global -> registers for input plane zi.  The raw loads stay unmasked
+  // while the MFMAs of the current plane run: items with no source (outside
+  // the volume, channel padding; loaded from a valid clamped offset) and
+  // planes known to be zero are masked only when stored into the ring.  A
+  // select right after the load would make the wave wait for it there.
   uint4 pf[PF];
   auto load_plane = [&](int zi) {
-    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
     if (!live_in(zi) || (unsigned)zi >= (unsigned)n) {
 #pragma unroll
-      for (int k = 0; k < PF; ++k) pf[k] = zero;
+      for (int k = 0; k < PF; ++k) pf[k] = make_uint4(0u, 0u, 0u, 0u);
       return;
     }
     const char* pa = reinterpret_cast<const char*>(src.a) + (int64_t)(src.up ? zi >> 1 : zi) * plane_a;
     if (!src.b) {
 #pragma unroll
-      for (int k = 0; k < PF; ++k) {
-        const uint4 raw = *reinterpret_cast<const uint4*>(pa + ioff[k]);
-        pf[k] = isrc[k] ? raw : zero;
-      }
+      for (int k = 0; k < PF; ++k) pf[k] = *reinterpret_cast<const uint4*>(pa + ioff[k]);
     } else {
       const char* pb = reinterpret_cast<const char*>(src.b) + (int64_t)zi * plane_b;
 #pragma unroll
-      for (int k = 0; k < PF; ++k) {
-        const uint4 raw = *reinterpret_cast<const uint4*>((isrc[k] == 2 ? pb : pa) + ioff[k]);
-        pf[k] = isrc[k] ? raw : zero;
-      }
+      for (int k = 0; k < PF; ++k)
+        pf[k] = *reinterpret_cast<const uint4*>((isrc[k] == 2 ? pb : pa) + ioff[k]);
     }
   };
   // stores the prefetched plane; returns whether this thread's part of it
   // holds any non-zero bit
   auto store_plane = [&](int zi) -> int {
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
     __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
     uint32_t any = 0u;
 #pragma unroll
@@ -222,8 +220,9 @@ __global__ void __launch_bounds__(kBlock)
       const int it = threadIdx.x + k * kBlock;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
-        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = pf[k];
-        any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
+        const uint4 v = isrc[k] ? pf[k] : zero;
+        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        any |= v.x | v.y | v.z | v.w;
       }
     }
     return any != 0u;
@@ -525,36 +524,53 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
 
-  // global -> registers for input plane zi (zero outside the volume and on
-  // planes known to be zero)
-  uint4 pf[PF];
-  auto load_plane = [&](int zi, uint4 (&pf)[PF]) {
-    const bool on = live_in(zi);
+  // plane loads as in k_conv_zm: per-item offsets fixed for the block, raw
+  // loads from valid clamped offsets, masked when stored into the ring
+  uint32_t ioff[PF];
+  uint8_t isrc[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int it = threadIdx.x + k * kBlock;
-      uint4 val = make_uint4(0u, 0u, 0u, 0u);
-      if (on && it < ITEMS) {
-        const int hv = it / P8, p = it - hv * P8;
-        const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
-        const int c = p * 8;
-        if ((unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n && (unsigned)zi < (unsigned)n) {
-          if (c < src.ca) {
-            const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * ((gy >> 1) + (int64_t)nc * (zi >> 1))
-                                     : (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi);
-            val = *reinterpret_cast<const uint4*>(src.a + v * src.ca + c);
-          } else if (c < src.ca + src.cb) {
-            const int64_t v = (int64_t)gx + (int64_t)n * (gy + (int64_t)n * zi);
-            val = *reinterpret_cast<const uint4*>(src.b + v * src.cb + (c - src.ca));
-          }
-        }
+  for (int k = 0; k < PF; ++k) {
+    const int it = threadIdx.x + k * kBlock;
+    const int hv = it / P8, p = it - hv * P8;
+    const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
+    const int c = p * 8;
+    ioff[k] = 0u;
+    isrc[k] = 0;
+    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+      if (c < src.ca) {
+        const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
+        ioff[k] = (uint32_t)((v * src.ca + c) * 2);
+        isrc[k] = 1;
+      } else if (c < src.ca + src.cb) {
+        ioff[k] = (uint32_t)((((int64_t)gx + (int64_t)n * gy) * src.cb + (c - src.ca)) * 2);
+        isrc[k] = 2;
       }
-      pf[k] = val;
+    }
+  }
+  const int64_t plane_a = (int64_t)(src.up ? nc : n) * (src.up ? nc : n) * src.ca * 2;
+  const int64_t plane_b = (int64_t)n * n * src.cb * 2;
+  uint4 pf[PF];
+  auto load_plane = [&](int zi) {
+    if (!live_in(zi) || (unsigned)zi >= (unsigned)n) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pf[k] = make_uint4(0u, 0u, 0u, 0u);
+      return;
+    }
+    const char* pa = reinterpret_cast<const char*>(src.a) + (int64_t)(src.up ? zi >> 1 : zi) * plane_a;
+    if (!src.b) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pf[k] = *reinterpret_cast<const uint4*>(pa + ioff[k]);
+    } else {
+      const char* pb = reinterpret_cast<const char*>(src.b) + (int64_t)zi * plane_b;
+#pragma unroll
+      for (int k = 0; k < PF; ++k)
+        pf[k] = *reinterpret_cast<const uint4*>((isrc[k] == 2 ? pb : pa) + ioff[k]);
     }
   };
   // stores the prefetched plane; returns whether this thread's part of it
   // holds any non-zero bit
-  auto store_plane = [&](int zi, const uint4 (&pf)[PF]) -> int {
+  auto store_plane = [&](int zi) -> int {
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
     __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
     uint32_t any = 0u;
 #pragma unroll
@@ -562,8 +578,9 @@ __global__ void __launch_bounds__(kBlock)
       const int it = threadIdx.x + k * kBlock;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
-        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = pf[k];
-        any |= pf[k].x | pf[k].y | pf[k].z | pf[k].w;
+        const uint4 v = isrc[k] ? pf[k] : zero;
+        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        any |= v.x | v.y | v.z | v.w;
       }
     }
     return any != 0u;
@@ -578,11 +595,11 @@ __global__ void __launch_bounds__(kBlock)
   // A bias-free network maps an all-zero input neighbourhood to zero, so the
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
-  load_plane(z0 - 1, pf);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1, pf));
-  load_plane(z0, pf);
-  int nz_0 = __syncthreads_or(store_plane(z0, pf));
-  load_plane(z0 + 1, pf);
+  load_plane(z0 - 1);
+  int nz_m = __syncthreads_or(store_plane(z0 - 1));
+  load_plane(z0);
+  int nz_0 = __syncthreads_or(store_plane(z0));
+  load_plane(z0 + 1);
   float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
 #pragma unroll
   for (int e = 0; e < 8; ++e) pacc[e] = 0.f;
@@ -590,8 +607,8 @@ __global__ void __launch_bounds__(kBlock)
   // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
   // is loaded while the MFMAs of plane z run
   auto plane_step = [&](int z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1, pf));
-    if (z + 2 <= z1) load_plane(z + 2, pf);
+    const int nz_p = __syncthreads_or(store_plane(z + 1));
+    if (z + 2 <= z1) load_plane(z + 2);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
     nz_0 = nz_p;
@@ -607,6 +624,23 @@ __global__ void __launch_bounds__(kBlock)
     uint8_t own_mask = 0;
     if (EPI == NET_EPI_OUT && own)
       own_mask = out.mask[(int64_t)ox + (int64_t)n * (oy + (int64_t)n * z)];
+    // RELU_ADD: the fp16 partial sums of this plane's epilogue items (item
+    // it = lane + 64 k: voxel it / PV8 of the wave's rows, 8 channels part
+    // it % PV8), from a clamped address where the item is outside
+    constexpr int PV8 = COUT / 8;
+    constexpr int ADD_K = EPI == NET_EPI_RELU_ADD ? (4 * ZT * PV8 + 63) / 64 : 1;
+    uint4 hadd[ADD_K];
+    if (EPI == NET_EPI_RELU_ADD) {
+#pragma unroll
+      for (int k = 0; k < ADD_K; ++k) {
+        const int it = lane + 64 * k;
+        const int lv = it / PV8, part = it - lv * PV8;
+        const int x = x0 + lv % ZT, y = y0 + 4 * wv + lv / ZT;
+        const bool ok = it < 4 * ZT * PV8 && x < n && y < n;
+        const int64_t v = ok ? (int64_t)x + (int64_t)n * (y + (int64_t)n * z) : 0;
+        hadd[k] = *reinterpret_cast<const uint4*>(out.add + v * COUT + part * 8);
+      }
+    }
 
     f32x4z acc[4][NT];
 #pragma unroll
@@ -685,9 +719,8 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
           for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = acc[a][t][i];
       wave_sync();  // per-wave staging
-      constexpr int PV8 = COUT / 8;
 #pragma unroll
-      for (int k = 0; k < (4 * ZT * PV8 + 63) / 64; ++k) {
+      for (int k = 0; k < ADD_K; ++k) {
         const int it = lane + 64 * k;
         if (it >= 4 * ZT * PV8) break;
         const int lv = it / PV8, part = it - lv * PV8;
@@ -695,8 +728,7 @@ __global__ void __launch_bounds__(kBlock)
         const int x = x0 + xl, y = y0 + 4 * wv + a;
         if (x >= n || y >= n) continue;
         const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
-        const uint4 hv = *reinterpret_cast<const uint4*>(out.add + v * COUT + part * 8);
-        const _Float16* hp = reinterpret_cast<const _Float16*>(&hv);
+        const _Float16* hp = reinterpret_cast<const _Float16*>(&hadd[k]);
         const float* s8 = sf + lv * COUT + part * 8;
         __bf16 o8[8];
 #pragma unroll

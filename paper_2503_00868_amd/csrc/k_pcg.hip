@@ -386,15 +386,18 @@ __device__ inline ZTile ztile(int n, int zc) {
 }
 
 // Raw inputs of the direction at one 4-cell group (z = r/diag for Jacobi,
-// else the explicit z array).
+// else the explicit z array).  A group of the tile itself (CENTER) also
+// carries what its stencil row needs after the barrier: the diagonal codes
+// and, for the flexible variant's second dot, r.
 template <int PREC>
 struct DirRaw {
   float a[4];  // r (Jacobi) or z
   float d[4];
   uint32_t g;
+  float rr[4];  // r of a centre group in the flexible variant
 };
 
-template <int PREC>
+template <int PREC, bool CENTER, bool FLEX>
 __device__ inline void dir_raw_load(const float* __restrict__ r, const float* __restrict__ z,
                                     const uint8_t* __restrict__ cdiag,
                                     const float* __restrict__ d_in, int64_t idx, bool ok,
@@ -402,10 +405,11 @@ __device__ inline void dir_raw_load(const float* __restrict__ r, const float* __
   if (ok) {
     ldf<4>((PREC == PK_JACOBI ? r : z) + idx, o.a);
     ldf<4>(d_in + idx, o.d);
-    o.g = PREC == PK_JACOBI ? *reinterpret_cast<const uint32_t*>(cdiag + idx) : 0u;
+    o.g = PREC == PK_JACOBI || CENTER ? *reinterpret_cast<const uint32_t*>(cdiag + idx) : 0u;
+    if (CENTER && FLEX) ldf<4>(r + idx, o.rr);
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) o.a[e] = 0.f, o.d[e] = 0.f;
+    for (int e = 0; e < 4; ++e) o.a[e] = 0.f, o.d[e] = 0.f, o.rr[e] = 0.f;
     o.g = 0u;
   }
 }
@@ -428,7 +432,10 @@ __global__ void __launch_bounds__(kBlock)
                   const int* __restrict__ flags, double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
   count_work(work);
-  __shared__ float sd[ZM_TY + 2][ZM_W];
+  // two plane slots: plane zz is written to slot zz & 1, so the slot written
+  // for plane zz + 1 was last read for plane zz - 1, before this plane's
+  // barrier, and one barrier per plane suffices
+  __shared__ float sd2[2][ZM_TY + 2][ZM_W];
   const float beta = (float)scal[S_BETA];
   const ZTile t = ztile(n, zc);
   const int64_t sz = (int64_t)n * n;
@@ -445,10 +452,12 @@ __global__ void __launch_bounds__(kBlock)
   const bool has_hx = t.gx == 0 || t.gx == ZM_GX - 1;
 
   auto load_center = [&](int zz, DirRaw<PREC>& o) {
-    dir_raw_load<PREC>(r, z, cdiag, d_in, gidx(t.x, t.y, zz), t.in_xy && zz >= 0 && zz < n, o);
+    dir_raw_load<PREC, true, FLEX>(r, z, cdiag, d_in, gidx(t.x, t.y, zz),
+                                   t.in_xy && zz >= 0 && zz < n, o);
   };
   auto load_hy = [&](int zz, DirRaw<PREC>& o) {
-    dir_raw_load<PREC>(r, z, cdiag, d_in, gidx(t.x, hy, zz), has_hy && in_box(t.x, hy, zz), o);
+    dir_raw_load<PREC, false, false>(r, z, cdiag, d_in, gidx(t.x, hy, zz),
+                                     has_hy && in_box(t.x, hy, zz), o);
   };
   auto load_hx = [&](int zz, float& a, float& d, uint8_t& g) {
     if (has_hx && in_box(hx, t.y, zz)) {
@@ -466,12 +475,18 @@ __global__ void __launch_bounds__(kBlock)
   float hxa, hxd;
   uint8_t hxg;
   float dm[4], dc[4], dp[4];
+  // diagonal codes and (flexible) r of the current plane's group
+  uint32_t gc;
+  float rc[4];
   {
     DirRaw<PREC> c0;
     load_center(t.z0 - 1, c0);
     load_center(t.z0, c1);
     dir_raw_eval<PREC>(c0, beta, dm);
     dir_raw_eval<PREC>(c1, beta, dc);
+    gc = c1.g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rc[e] = c1.rr[e];
   }
   load_center(t.z0 + 1, c1);
   load_hy(t.z0, h1);
@@ -487,6 +502,7 @@ __global__ void __launch_bounds__(kBlock)
     load_center(zz + 2, c2);
     load_hy(zz + 1, h1);
     load_hx(zz + 1, hxa, hxd, hxg);
+    float(&sd)[ZM_TY + 2][ZM_W] = sd2[zz & 1];
 #pragma unroll
     for (int e = 0; e < 4; ++e) sd[t.ty + 1][1 + 4 * t.gx + e] = dc[e];
     if (has_hx) sd[t.ty + 1][hcol] = hxv;
@@ -497,29 +513,26 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     if (t.in_xy) {
       const int64_t idx = gidx(t.x, t.y, zz);
-      uint8_t dg[4];
-      ldg<4>(cdiag + idx, dg);
       const int c0 = 1 + 4 * t.gx;
       float qv[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        const uint32_t dg = (gc >> (8 * e)) & 255u;
         const float s = sd[t.ty + 1][c0 + e - 1] + sd[t.ty + 1][c0 + e + 1] + sd[t.ty][c0 + e] +
                         sd[t.ty + 2][c0 + e] + dm[e] + dp[e];
-        qv[e] = dg[e] ? (float)dg[e] * dc[e] - s : 0.f;
+        qv[e] = dg ? (float)dg * dc[e] - s : 0.f;
         v[0] += (double)dc[e] * (double)qv[e];
       }
       if (FLEX) {
-        float rv[4];
-        ldf<4>(r + idx, rv);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[1] += (double)dc[e] * (double)rv[e];
+        for (int e = 0; e < 4; ++e) v[1] += (double)dc[e] * (double)rc[e];
       }
       stf<4>(d_out + idx, dc);
       stf<4>(q + idx, qv);
     }
-    __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dm[e] = dc[e], dc[e] = dp[e];
+    for (int e = 0; e < 4; ++e) dm[e] = dc[e], dc[e] = dp[e], rc[e] = c1.rr[e];
+    gc = c1.g;
     c1 = c2;
   }
   store_partials<2>(v, partials, xcd_logical_block(blockIdx.x, gridDim.x));
@@ -533,7 +546,8 @@ __global__ void __launch_bounds__(kBlock)
                double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
   count_work(work);
-  __shared__ double sx[ZM_TY + 2][ZM_W];
+  // two plane slots, one barrier per plane (as in k_dir_spmv_zm)
+  __shared__ double sx2[2][ZM_TY + 2][ZM_W];
   const ZTile t = ztile(n, zc);
   const int64_t sz = (int64_t)n * n;
   auto gidx = [&](int xx, int yy, int zz) -> int64_t { return xx + (int64_t)n * yy + sz * zz; };
@@ -547,12 +561,28 @@ __global__ void __launch_bounds__(kBlock)
     if (xx < 0 || xx >= n || yy < 0 || yy >= n) return 0.0;
     return x[gidx(xx, yy, zz)];
   };
+  // b and the diagonal codes of the thread's group, loaded one plane ahead
+  auto group_bg = [&](int zz, float (&bo)[4], uint32_t& go) {
+    if (t.in_xy && zz < t.z1) {
+      const int64_t idx = gidx(t.x, t.y, zz);
+      ldf<4>(b + idx, bo);
+      go = *reinterpret_cast<const uint32_t*>(cdiag + idx);
+    } else {
+      bo[0] = bo[1] = bo[2] = bo[3] = 0.f;
+      go = 0u;
+    }
+  };
   double xm[4], xc[4], xp[4];
+  float bc[4], bn[4];
+  uint32_t gc, gn;
   group_x(t.in_xy ? t.x : -1, t.y, t.z0 - 1, xm);
   group_x(t.in_xy ? t.x : -1, t.y, t.z0, xc);
+  group_bg(t.z0, bc, gc);
   double v[2] = {0.0, 0.0};
   for (int zz = t.z0; zz < t.z1; ++zz) {
     group_x(t.in_xy ? t.x : -1, t.y, zz + 1, xp);
+    group_bg(zz + 1, bn, gn);
+    double(&sx)[ZM_TY + 2][ZM_W] = sx2[zz & 1];
 #pragma unroll
     for (int e = 0; e < 4; ++e) sx[t.ty + 1][1 + 4 * t.gx + e] = xc[e];
     if (t.gx == 0) sx[t.ty + 1][0] = cell_x(t.x0 - 1, t.y, zz);
@@ -572,25 +602,23 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     if (t.in_xy) {
       const int64_t idx = gidx(t.x, t.y, zz);
-      uint8_t dg[4];
-      float bv[4], rf[4];
-      ldg<4>(cdiag + idx, dg);
-      ldf<4>(b + idx, bv);
+      float rf[4];
       const int c0 = 1 + 4 * t.gx;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
+        const uint32_t dg = (gc >> (8 * e)) & 255u;
         const double s = sx[t.ty + 1][c0 + e - 1] + sx[t.ty + 1][c0 + e + 1] + sx[t.ty][c0 + e] +
                          sx[t.ty + 2][c0 + e] + xm[e] + xp[e];
-        const double rc = dg[e] ? (double)bv[e] - ((double)dg[e] * xc[e] - s) : 0.0;
+        const double rc = dg ? (double)bc[e] - ((double)dg * xc[e] - s) : 0.0;
         rf[e] = (float)rc;
         v[0] += rc * rc;
-        if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg[e]];
+        if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg];
       }
       stf<4>(r + idx, rf);
     }
-    __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xm[e] = xc[e], xc[e] = xp[e];
+    for (int e = 0; e < 4; ++e) xm[e] = xc[e], xc[e] = xp[e], bc[e] = bn[e];
+    gc = gn;
   }
   store_partials<2>(v, partials, xcd_logical_block(blockIdx.x, gridDim.x));
 }
@@ -1278,7 +1306,8 @@ __global__ void __launch_bounds__(kBlock)
                       double* partials, int* __restrict__ work) {
   if (flags[F_DONE]) return;
   count_work(work);
-  __shared__ float sd[DZ_TY + 2][DZ_TX + 2];
+  // two plane slots, one barrier per plane (as in k_dir_spmv_zm)
+  __shared__ float sd2[2][DZ_TY + 2][DZ_TX + 2];
   const int comp = blockIdx.y;
   const Dims dm3 = face_dims(n, comp);
   const int64_t sy = dm3.nx, sz = (int64_t)dm3.nx * dm3.ny;
@@ -1374,6 +1403,7 @@ __global__ void __launch_bounds__(kBlock)
       // next loads before the barrier
       load_own(zz + 2, c2);
       load_halo(zz + 1);
+      float(&sd)[DZ_TY + 2][DZ_TX + 2] = sd2[zz & 1];
 #pragma unroll
       for (int k = 0; k < DZ_K; ++k) sd[1 + tg + 4 * k][1 + tx] = dcv[k];
       if (hx != -1) sd[hrow][hcol] = hv;
@@ -1401,7 +1431,6 @@ __global__ void __launch_bounds__(kBlock)
           v[0] += (double)dv * (double)qv;
         }
       }
-      __syncthreads();
 #pragma unroll
       for (int k = 0; k < DZ_K; ++k) dmv[k] = dcv[k], dcv[k] = dpv[k], cc[k] = cn[k];
       c1 = c2;

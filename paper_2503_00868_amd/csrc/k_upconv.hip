@@ -114,51 +114,70 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
         for (int r = 0; r < UR; ++r) acc[p][r] = f32x4u{0.f, 0.f, 0.f, 0.f};
 
+      // The (oz, ox, K-step) steps in order; each loads rows Yw-1 .. Yw+4 of
+      // coarse plane Z+oz, shifted by ox.  The loads of step s+1 are issued
+      // before the MFMAs of step s, and out-of-volume rows (loaded from a
+      // clamped, valid address) are zeroed only when their step runs, so
+      // that no wave waits for a load right after issuing it.
+      constexpr int NSTEP = 9 * KS;
+      auto load_step = [&](int s, uint4 (&raw)[UR + 2], uint32_t& okm) {
+        const int oz = s / (3 * KS) - 1, ox = (s / KS) % 3 - 1, ks = s % KS;
+        const int cx = X0 + col + ox, cz = Z + oz;
+        const bool xz_ok = (unsigned)cx < (unsigned)nc && (unsigned)cz < (unsigned)nc;
+        okm = 0u;
 #pragma unroll
-      for (int oz = -1; oz <= 1; ++oz)
+        for (int rr = 0; rr < UR + 2; ++rr) {
+          const int cy = Yw + rr - 1;
+          const bool ok = xz_ok && (unsigned)cy < (unsigned)nc;
+          const int64_t v = ok ? (int64_t)cx + (int64_t)nc * (cy + (int64_t)nc * cz) : 0;
+          raw[rr] = *reinterpret_cast<const uint4*>(coarse + v * CC + ks * 32 + 8 * g);
+          okm |= ok ? 1u << rr : 0u;
+        }
+      };
+      uint4 ra[UR + 2], rb[UR + 2];
+      uint32_t oka, okb;
+      load_step(0, ra, oka);
 #pragma unroll
-        for (int ox = -1; ox <= 1; ++ox)
+      for (int s = 0; s < NSTEP; ++s) {
+        const int oz = s / (3 * KS) - 1, ox = (s / KS) % 3 - 1, ks = s % KS;
+        uint4(&cur)[UR + 2] = (s & 1) ? rb : ra;
+        const uint32_t okc = (s & 1) ? okb : oka;
+        if (s + 1 < NSTEP) {
+          if (s & 1)
+            load_step(s + 1, ra, oka);
+          else
+            load_step(s + 1, rb, okb);
+        }
+        bf16x8u f[UR + 2];
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            // rows Yw-1 .. Yw+4 of coarse plane Z+oz, shifted by ox.  Branch-free:
-            // out-of-volume rows load a clamped (valid) address and are zeroed
-            // by a select, so the scheduler can issue these loads early.
-            bf16x8u f[UR + 2];
-            const int cx = X0 + col + ox, cz = Z + oz;
-            const bool xz_ok = (unsigned)cx < (unsigned)nc && (unsigned)cz < (unsigned)nc;
+        for (int rr = 0; rr < UR + 2; ++rr) {
+          const uint4 val = (okc >> rr) & 1u ? cur[rr] : make_uint4(0u, 0u, 0u, 0u);
+          f[rr] = *reinterpret_cast<const bf16x8u*>(&val);
+        }
 #pragma unroll
-            for (int rr = 0; rr < UR + 2; ++rr) {
-              const int cy = Yw + rr - 1;
-              const bool ok = xz_ok && (unsigned)cy < (unsigned)nc;
-              const int64_t v = ok ? (int64_t)cx + (int64_t)nc * (cy + (int64_t)nc * cz) : 0;
-              const uint4 raw = *reinterpret_cast<const uint4*>(coarse + v * CC + ks * 32 + 8 * g);
-              const uint4 val = ok ? raw : make_uint4(0u, 0u, 0u, 0u);
-              f[rr] = *reinterpret_cast<const bf16x8u*>(&val);
-            }
+        for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
-            for (int oy = -1; oy <= 1; ++oy)
+          for (int pz = 0; pz < 2; ++pz) {
+            if (oz == (pz ? -1 : 1)) continue;  // parity 0 never reads +1, parity 1 never -1
 #pragma unroll
-              for (int pz = 0; pz < 2; ++pz) {
-                if (oz == (pz ? -1 : 1)) continue;  // parity 0 never reads +1, parity 1 never -1
+            for (int py = 0; py < 2; ++py) {
+              if (oy == (py ? -1 : 1)) continue;
 #pragma unroll
-                for (int py = 0; py < 2; ++py) {
-                  if (oy == (py ? -1 : 1)) continue;
+              for (int px = 0; px < 2; ++px) {
+                if (ox == (px ? -1 : 1)) continue;
+                const int p = px + 2 * py + 4 * pz;
+                const int tap =
+                    (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
+                const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
+                    wl + (((p * 8 + tap) * (CC / 8) + ks * 4 + g) * 16 + col) * 8);
 #pragma unroll
-                  for (int px = 0; px < 2; ++px) {
-                    if (ox == (px ? -1 : 1)) continue;
-                    const int p = px + 2 * py + 4 * pz;
-                    const int tap =
-                        (ox + (px ? 0 : 1)) + 2 * (oy + (py ? 0 : 1)) + 4 * (oz + (pz ? 0 : 1));
-                    const bf16x8u bw = *reinterpret_cast<const bf16x8u*>(
-                        wl + (((p * 8 + tap) * (CC / 8) + ks * 4 + g) * 16 + col) * 8);
-#pragma unroll
-                    for (int r = 0; r < UR; ++r)
-                      acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[r + oy + 1], bw,
-                                                                          acc[p][r], 0, 0, 0);
-                  }
-                }
+                for (int r = 0; r < UR; ++r)
+                  acc[p][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[r + oy + 1], bw,
+                                                                      acc[p][r], 0, 0, 0);
               }
+            }
           }
+      }
 
       // epilogue: one fine (y-parity, z-parity) slab at a time through LDS,
       // as UR rows of 2*UX fine voxels x 16 channels
