@@ -56,27 +56,42 @@ __device__ inline TileXYZ tile_of(int n, int b) {
 int conv_tiles(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ); }
 
 // Stage channels [c0, c0+CK) of the (possibly concatenated) input over the
-// halo of a tile into LDS as [HV][CK] bf16; zero outside the volume.
+// halo of a tile into LDS as [HV][CK] bf16; zero outside the volume.  All of
+// a thread's loads are issued (from valid clamped addresses) before the
+// first store, so the staging waits for one load latency, not one per item.
 template <int CK>
 __device__ inline void load_halo(__bf16* __restrict__ lds, const NetSrc& s, int n, TileXYZ t,
                                  int c0) {
   constexpr int PV = CK / 8;  // 16-byte vectors per voxel
+  constexpr int NV = HV * PV;
+  constexpr int NI = (NV + kBlock - 1) / kBlock;
   const int nc = n / 2;
-  for (int vi = threadIdx.x; vi < HV * PV; vi += kBlock) {
+  uint4 raw[NI];
+  bool ok[NI];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int vi = threadIdx.x + k * kBlock;
     const int hv = vi / PV, part = vi - hv * PV;
     const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
     const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
-    uint4 val = make_uint4(0u, 0u, 0u, 0u);
-    if (inside(gx, gy, gz, n)) {
-      const int c = c0 + part * 8;
+    ok[k] = vi < NV && inside(gx, gy, gz, n);
+    const int c = c0 + part * 8;
+    const __bf16* src = s.a;
+    if (ok[k]) {
       if (c < s.ca) {
         const int64_t v = s.up ? vox(gx >> 1, gy >> 1, gz >> 1, nc) : vox(gx, gy, gz, n);
-        val = *reinterpret_cast<const uint4*>(s.a + v * s.ca + c);
+        src = s.a + v * s.ca + c;
       } else {
-        val = *reinterpret_cast<const uint4*>(s.b + vox(gx, gy, gz, n) * s.cb + (c - s.ca));
+        src = s.b + vox(gx, gy, gz, n) * s.cb + (c - s.ca);
       }
     }
-    *reinterpret_cast<uint4*>(lds + hv * CK + part * 8) = val;
+    raw[k] = *reinterpret_cast<const uint4*>(src);
+  }
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int vi = threadIdx.x + k * kBlock;
+    if (vi < NV)
+      *reinterpret_cast<uint4*>(lds + vi * 8) = ok[k] ? raw[k] : make_uint4(0u, 0u, 0u, 0u);
   }
 }
 
@@ -108,14 +123,26 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+#pragma unroll 1
   for (int c0 = 0; c0 < CIN; c0 += CK) {
     __syncthreads();
     load_halo<CK>(lds, src, n, t, c0);
     if (WL) {
-      for (int q = threadIdx.x; q < TAPS * 2 * COUT; q += kBlock) {
-        const int co = q % COUT, half = (q / COUT) & 1, tap = q / (2 * COUT);
-        *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) = *reinterpret_cast<const uint4*>(
-            w + ((int64_t)co * TAPS + tap) * CIN + c0 + half * 8);
+      // all loads of the thread first, then the stores (as in load_halo)
+      constexpr int NW = TAPS * 2 * COUT;
+      constexpr int NWI = (NW + kBlock - 1) / kBlock;
+      uint4 wr[NWI];
+#pragma unroll
+      for (int k = 0; k < NWI; ++k) {
+        const int q = threadIdx.x + k * kBlock;
+        const int qq = q < NW ? q : 0;
+        const int co = qq % COUT, half = (qq / COUT) & 1, tap = qq / (2 * COUT);
+        wr[k] = *reinterpret_cast<const uint4*>(w + ((int64_t)co * TAPS + tap) * CIN + c0 + half * 8);
+      }
+#pragma unroll
+      for (int k = 0; k < NWI; ++k) {
+        const int q = threadIdx.x + k * kBlock;
+        if (q < NW) *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) = wr[k];
       }
     }
     __syncthreads();
