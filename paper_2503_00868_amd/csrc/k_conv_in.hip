@@ -3,11 +3,14 @@
 //
 // With two input channels a K = 32 MFMA step holds 16 taps x 2 channels, so
 // the 27 taps take 2 steps per output row (instead of 15 steps of 2 taps x 16
-// zero-padded channels).  Lane (g, col) of the A operand carries voxel col and
-// k = 8g + 2j + ch, i.e. tap 16s + 4g + j, channel ch: it gathers 4 taps of
-// the (r, mask) pair, 4 bytes each, from an LDS ring of three input planes
-// (z-marching as in k_conv_zm.hip).  r and the mask are read directly from
-// the solver's arrays, so the 2-channel input tensor is never stored.
+// zero-padded channels).  Lane (g, col) of the input operand carries voxel
+// col and k = 8g + 2j + ch, i.e. tap 16s + 4g + j, channel ch: it gathers 4
+// taps of the (r, mask) pair, 4 bytes each, from an LDS ring of three input
+// planes (z-marching as in k_conv_zm.hip).  The weights are the MFMA's A
+// operand and the input its B operand, so the result is [output channel]
+// [voxel] and each lane stores 4 channels of one voxel straight from its
+// registers.  r and the mask are read directly from the solver's arrays, so
+// the 2-channel input tensor is never stored.
 #include "common.h"
 #include "ctx.h"
 #include "net.h"
@@ -47,7 +50,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   if (flags && flags[F_DONE]) return;
   count_work(work);
   __shared__ uint32_t ring[4][IRV];  // (r / rms, mask) as two bf16; four slots as in k_conv_zm
-  __shared__ __attribute__((aligned(16))) __bf16 stage[4 * 4 * IT * 16];
   const double rms = n_liquid > 0.0 ? sqrt(*sumsq / n_liquid) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
   const float inv = rms > 0.0 ? (float)(1.0 / rms) : 0.f;
@@ -75,7 +77,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   }
   auto live = [&](int zi) -> bool { return !act || live_s[zi - z0 + 1] != 0; };
 
-  // B fragments: step s, k = 8g + i -> tap 16s + 4g + i/2, channel i % 2
+  // weight fragments: step s, output channel col, k = 8g + i -> tap
+  // 16s + 4g + i/2, channel i % 2
   bf16x8i bw[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -169,30 +172,24 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
           af[2 * j] = pp[0];
           af[2 * j + 1] = pp[1];
         }
-        acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[s], acc[a], 0, 0, 0);
+        // weights as A, input as B: D = [output channel][voxel]
+        acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[s], af, acc[a], 0, 0, 0);
       }
     }
 
-    // ReLU, bf16, coalesced stores through LDS (rows y0 + 4 wv + a)
-    __bf16* st = stage + wv * (4 * IT * 16);
+    // ReLU, bf16: lane (g, col) holds channels 4g .. 4g+3 of voxel x0 + col
+    // in row y0 + 4 wv + a and stores them as one 8-byte word (a wave's
+    // store of one row is 512 contiguous bytes)
+    const int x = x0 + col;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float v = acc[a][i];
-        st[((a * IT) + 4 * g + i) * 16 + col] = (__bf16)(v > 0.f ? v : 0.f);
-      }
-    wave_sync();  // per-wave staging
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int it = lane + 64 * k;  // (row a, voxel, half)
-      const int lv = it >> 1, part = it & 1;
-      const int a = lv / IT, xl = lv % IT;
-      const int x = x0 + xl, y = y0 + 4 * wv + a;
+    for (int a = 0; a < 4; ++a) {
+      const int y = y0 + 4 * wv + a;
       if (x >= n || y >= n) continue;
+      __bf16 h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)(acc[a][i] > 0.f ? acc[a][i] : 0.f);
       const int64_t v = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
-      *reinterpret_cast<uint4*>(out + v * 16 + part * 8) =
-          *reinterpret_cast<const uint4*>(st + lv * 16 + part * 8);
+      *reinterpret_cast<uint2*>(out + v * 16 + 4 * g) = *reinterpret_cast<const uint2*>(h);
     }
   };
   for (int z = z0; z < z1; z += 2) {
