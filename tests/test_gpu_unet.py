@@ -38,7 +38,7 @@ def test_param_count_matches_oracle():
     assert net_weights.param_count() == oracle_unet.param_count()
 
 
-@pytest.mark.parametrize("n,seed", [(16, 0), (20, 1), (32, 2)])
+@pytest.mark.parametrize("n,seed", [(16, 0), (20, 1), (32, 2), (40, 3)])
 def test_net_forward_parity(torch_gpu, n, seed):
     torch = torch_gpu
     banner(f"unet forward n={n}")
@@ -116,7 +116,7 @@ def test_tile_skip_is_bitwise_dense(torch_gpu, n, which):
     sim.net_set_tile_skip(True)
 
 
-@pytest.mark.parametrize("n,batch", [(16, 1), (16, 2)])
+@pytest.mark.parametrize("n,batch", [(16, 1), (16, 2), (24, 1), (40, 1)])
 def test_net_grad_parity(torch_gpu, orc, n, batch):
     torch = torch_gpu
     banner(f"unet grad n={n} batch={batch}")
