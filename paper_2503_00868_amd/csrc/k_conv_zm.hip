@@ -450,8 +450,17 @@ __global__ void __launch_bounds__(kBlock)
 // CIN: channels held per ring voxel (multiple of 16; the source may have
 // fewer, the rest is zero).  WS: channel stride of the packed weights.
 // COUT: output channels (16 or 48).
+// The 16 -> 16 pool layer runs at three waves per SIMD (its LDS allows three
+// blocks per CU; the register limit costs a few spilled values): 296 -> 267 us
+// for c2 at 256^3.  The add layer does not fit that limit.
+template <int CIN, int COUT, int EPI>
+constexpr int zm_pa_min_waves() {
+  return CIN == 16 && COUT == 16 && EPI == NET_EPI_RELU_POOL ? 3 : 1;
+}
+
 template <int CIN, int WS, int COUT, int EPI>
 __global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(zm_pa_min_waves<CIN, COUT, EPI>())))
     k_conv_zm_pa(int n, int zc, NetSrc src, const __bf16* __restrict__ w, NetOut out,
               const int* __restrict__ flags) {
   if (flags && flags[F_DONE]) return;
