@@ -240,6 +240,36 @@ int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, cons
                           const float* d_lu, const float* d_lv, const float* d_lw, float* d_gu,
                           float* d_gv, float* d_gw);
 
+/* ---- recurrent convolutional pressure solver (Section 3.4.1) -----------
+ * The paper solves the pressure Poisson equation inside its optimisation
+ * with a PeRCNN-style recurrent convolution whose kernel is fitted on
+ * pressure pairs from an implicit solve.  One layer here is
+ *   p_{k+1}(c) = L(c) s(c) ( sum_t W_t p_k(c + t) + w_b b(c) ),
+ * t over the 27 offsets of a 3x3x3 stencil (tap (dx+1) + 3 (dy+1) + 9 (dz+1)),
+ * p_k = 0 outside the box, L the liquid mask of the context and s = 6 / n_c
+ * (n_c the Poisson diagonal of c, the number of its non-solid faces); b is a
+ * right-hand side as the projection forms it.  W = 1/6 on the six face taps
+ * with w_b = 1/6 is one Jacobi sweep of the projection's Poisson system.
+ * h_w: host array of 28 floats, W_0 .. W_26 then w_b.  Cell arrays are n^3
+ * float32 on the device, [z][y][x].  Work is enqueued on the context's
+ * stream and uses two of its cell buffers, so it must not overlap another
+ * call on the same context.  Outputs must not alias inputs. */
+
+/* K >= 0 layers from d_p0.  d_out (nullable) receives p_K; d_hist (nullable,
+ * (K+1) n^3 floats) receives p_0 .. p_K for sim_percnn_backward.  At least
+ * one of the two must be given.  Returns SIM_ERR_INVALID_ARG for NULL inputs,
+ * K < 0 or aliasing outputs. */
+int sim_percnn_forward(sim_ctx* ctx, const float* h_w, int32_t K, const float* d_p0,
+                       const float* d_b, float* d_out, float* d_hist);
+
+/* Reverse pass of sim_percnn_forward for a loss L with dL/dp_K = d_g, given
+ * the states d_hist it recorded (same h_w, K, d_b).  d_gp0 (nullable)
+ * receives dL/dp_0, d_gb (nullable) dL/db; h_grad_w (host, 28 doubles)
+ * receives dL/dW_0 .. dL/dW_26 and dL/dw_b.  Synchronises the stream. */
+int sim_percnn_backward(sim_ctx* ctx, const float* h_w, int32_t K, const float* d_b,
+                        const float* d_hist, const float* d_g, float* d_gp0, float* d_gb,
+                        double* h_grad_w);
+
 /* ---- kernel timing for benchmarks -------------------------------------
  * When enabled, HIP events on the context's stream bracket every launch of
  * the kernels below (the finalize reductions are not included); durations
@@ -261,6 +291,8 @@ enum {
     SIM_KERN_MIC0,              /* one MIC(0) apply (all hyperplane launches)        */
     SIM_KERN_NET,               /* one U-Net preconditioner apply                   */
     SIM_KERN_ADVECT_ADJOINT,    /* advection adjoint scatter                        */
+    SIM_KERN_PERCNN,            /* one recurrent conv solver layer                  */
+    SIM_KERN_PERCNN_ADJ,        /* one reverse layer of the recurrent conv solver   */
     SIM_KERN_COUNT
 };
 int sim_profile_enable(sim_ctx* ctx, int32_t on);

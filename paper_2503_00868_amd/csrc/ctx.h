@@ -95,6 +95,7 @@ struct sim_ctx {
   float* rprev = nullptr;   // flexible CG
   float* precon = nullptr;  // MIC(0) factor
   float* mq = nullptr;      // MIC(0) forward-sweep result
+  double* pc_acc = nullptr; // recurrent conv solver: weight-gradient sums (28)
   double* xw = nullptr;     // warm start: pressure of the previous rollout step
   double* xwa = nullptr;    // warm start: previous adjoint pressure
 

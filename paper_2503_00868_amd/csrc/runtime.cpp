@@ -128,6 +128,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->lam = cv.take<float>(F3n);
   t->lam2 = cv.take<float>(F3n);
   t->partials = cv.take<double>((size_t)kPartialDoubles);
+  t->pc_acc = cv.take<double>(32);
   // control block: scalars then flags, copied to the host in one transfer
   char* ctrl = cv.take<char>(kCtrlBytes);
   t->scal = reinterpret_cast<double*>(ctrl);

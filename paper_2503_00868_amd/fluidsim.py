@@ -27,7 +27,8 @@ SIM_ERR_STATE = -6
 
 SIM_PRECOND_JACOBI, SIM_PRECOND_MIC0, SIM_PRECOND_LEARNED = 0, 1, 2
 KERNEL_KINDS = ["pcg_dir_spmv", "pcg_update", "pcg_check", "advect", "diffuse_explicit",
-                "dcg_dir_spmv", "dcg_update", "mic0", "net", "advect_adjoint"]
+                "dcg_dir_spmv", "dcg_update", "mic0", "net", "advect_adjoint", "percnn",
+                "percnn_adj"]
 SIM_DIFFUSION_AUTO, SIM_DIFFUSION_EXPLICIT, SIM_DIFFUSION_IMPLICIT = 0, 1, 2
 
 PRECONDS = {"jacobi": SIM_PRECOND_JACOBI, "mic0": SIM_PRECOND_MIC0, "learned": SIM_PRECOND_LEARNED}
@@ -88,6 +89,9 @@ SIGNATURES = {
     "sim_op_poisson_apply": (c_int32, [_P, _P, _P]),
     "sim_op_precond_apply": (c_int32, [_P, c_int32, _P, _P]),
     "sim_op_advect_adjoint": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_percnn_forward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P]),
+    "sim_percnn_backward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P, _P,
+                                      POINTER(c_double)]),
     "sim_profile_enable": (c_int32, [_P, c_int32]),
     "sim_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
     "sim_destroy": (c_int32, [_P]),
@@ -303,6 +307,34 @@ class Sim:
         self._chk(lib().sim_harvest_pairs(self.ctx, *map(_ptr, u), arr, k, mode, tol,
                                           _ptr(r_out), _ptr(e_out), byref(st)))
         return r_out, e_out, st.as_dict()
+
+    # -- recurrent convolutional pressure solver
+    @staticmethod
+    def _percnn_w(w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).ravel())
+        if w.size != 28:
+            raise ValueError("28 weights: W_0 .. W_26, w_b")
+        return w, w.ctypes.data_as(POINTER(c_float))
+
+    def percnn_forward(self, w, K, p0, b, out=None, hist=None):
+        """K recurrent layers from p0 (cell tensors); returns out (p_K) or,
+        with hist ((K+1, n, n, n) float32), the recorded states."""
+        wa, wp = self._percnn_w(w)
+        if out is None and hist is None:
+            out = self.cells_tensor()
+        self._chk(lib().sim_percnn_forward(self.ctx, wp, int(K), _ptr(p0), _ptr(b),
+                                           _ptr(out) if out is not None else None,
+                                           _ptr(hist) if hist is not None else None))
+        return out if out is not None else hist
+
+    def percnn_backward(self, w, K, b, hist, g, gp0=None, gb=None):
+        """Reverse pass: returns dL/d(W, w_b) (28 float64) and fills gp0, gb."""
+        wa, wp = self._percnn_w(w)
+        gw = (c_double * 28)()
+        self._chk(lib().sim_percnn_backward(self.ctx, wp, int(K), _ptr(b), _ptr(hist), _ptr(g),
+                                            _ptr(gp0) if gp0 is not None else None,
+                                            _ptr(gb) if gb is not None else None, gw))
+        return np.array(gw[:], dtype=np.float64)
 
     # -- kernel timing
     def profile_enable(self, on=True):

@@ -1,0 +1,138 @@
+"""GPU parity of the recurrent convolutional pressure solver against its
+FP64 oracle: every recorded state of the forward pass, the reverse pass
+(input, right-hand-side and weight gradients), and, at 256^3, sampled cells
+of each layer recomputed one by one from the layer's definition."""
+import numpy as np
+import pytest
+
+from oracle import percnn as orc_pc
+from paper_2503_00868_amd import inputs
+
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _sim(cell):
+    from paper_2503_00868_amd.fluidsim import Sim
+    return Sim(cell, precond="jacobi")
+
+
+def _weights(seed, jacobi=False):
+    W, wb = orc_pc.jacobi_kernel()
+    if not jacobi:
+        W = W + 0.03 * np.random.default_rng(seed).standard_normal(27)
+        wb = 0.2
+    return np.concatenate([W, [wb]]).astype(np.float32)
+
+
+def _case(n, seed):
+    cell = inputs.gen_mask(n, seed)
+    liquid = cell == inputs.LIQUID
+    rng = np.random.default_rng(100 + seed)
+    p0 = rng.standard_normal((n, n, n)).astype(np.float32)  # every cell: p0 is an input
+    b = np.where(liquid, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    return cell, p0, b
+
+
+@pytest.mark.parametrize("n,seed,jacobi", [(32, 0, True), (32, 1, False), (40, 2, False)])
+def test_forward_states_match_oracle(torch_gpu, n, seed, jacobi):
+    torch = torch_gpu
+    K = 6
+    banner(f"percnn forward n={n} K={K} jacobi={jacobi}")
+    cell, p0, b = _case(n, seed)
+    w = _weights(seed, jacobi)
+    sim = _sim(cell)
+    hist = torch.zeros((K + 1, n, n, n), dtype=torch.float32, device="cuda")
+    out = sim.cells_tensor()
+    sim.percnn_forward(w, K, sim.cells_tensor(p0), sim.cells_tensor(b), out=out, hist=hist)
+    H = hist.cpu().numpy().astype(np.float64)
+    ref = orc_pc.forward(cell, p0.astype(np.float64), b.astype(np.float64), w[:27].astype(np.float64),
+                         float(w[27]), K)
+    assert np.array_equal(H[0], p0.astype(np.float64))
+    for k in range(1, K + 1):
+        err = np.abs(H[k] - ref[k]).max() / np.abs(ref[k]).max()
+        assert err < 2e-6 * k, (k, err)
+        assert np.all(H[k][cell != inputs.LIQUID] == 0)
+    assert np.array_equal(out.cpu().numpy(), hist[K].cpu().numpy())
+    # without the history: ping-pong buffers, same result bitwise
+    out2 = sim.percnn_forward(w, K, sim.cells_tensor(p0), sim.cells_tensor(b))
+    assert np.array_equal(out2.cpu().numpy(), out.cpu().numpy())
+    # K = 0 copies p0
+    out0 = sim.percnn_forward(w, 0, sim.cells_tensor(p0), sim.cells_tensor(b))
+    assert np.array_equal(out0.cpu().numpy(), p0)
+
+
+@pytest.mark.parametrize("n,seed", [(32, 3), (40, 4)])
+def test_reverse_pass_matches_oracle(torch_gpu, n, seed):
+    torch = torch_gpu
+    K = 4
+    banner(f"percnn reverse n={n} K={K}")
+    cell, p0, b = _case(n, seed)
+    w = _weights(seed)
+    g = np.random.default_rng(seed).standard_normal((n, n, n)).astype(np.float32)
+    sim = _sim(cell)
+    hist = torch.zeros((K + 1, n, n, n), dtype=torch.float32, device="cuda")
+    sim.percnn_forward(w, K, sim.cells_tensor(p0), sim.cells_tensor(b), hist=hist)
+    gp0, gb = sim.cells_tensor(), sim.cells_tensor()
+    gw = sim.percnn_backward(w, K, sim.cells_tensor(b), hist, sim.cells_tensor(g), gp0=gp0, gb=gb)
+    ps = [h for h in hist.cpu().numpy().astype(np.float64)]
+    r_gp, r_gb, r_gW, r_gwb = orc_pc.backward(cell, ps, b.astype(np.float64),
+                                              w[:27].astype(np.float64), float(w[27]),
+                                              g.astype(np.float64))
+    e_gp = np.abs(gp0.cpu().numpy() - r_gp).max() / np.abs(r_gp).max()
+    e_gb = np.abs(gb.cpu().numpy() - r_gb).max() / np.abs(r_gb).max()
+    ref_w = np.concatenate([r_gW, [r_gwb]])
+    e_w = np.abs(gw - ref_w).max() / np.abs(ref_w).max()
+    banner(f"  rel err gp0 {e_gp:.2e} gb {e_gb:.2e} gw {e_w:.2e}")
+    assert e_gp < 1e-5 and e_gb < 1e-5 and e_w < 1e-5, (e_gp, e_gb, e_w)
+    # dL/dp0 and dL/db are the transpose of the forward map (linear in p0, b)
+    lhs = float(np.sum(ps[-1] * g))
+    rhs = float(np.sum(p0 * gp0.cpu().numpy()) + np.sum(b * gb.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(ps[-1] ** 2) * np.sum(g.astype(np.float64) ** 2))
+
+
+def test_full_size_layers_at_sampled_cells(torch_gpu):
+    """256^3, two layers in the launch configuration of the benchmark: each
+    recorded state checked at 4000 sampled cells (boundary planes included)
+    against the layer's definition evaluated from the previous GPU state."""
+    torch = torch_gpu
+    n, K = 256, 2
+    banner(f"percnn full size n={n}")
+    cell = inputs.gen_mask(n, 4)
+    liquid = cell == inputs.LIQUID
+    rng = np.random.default_rng(9)
+    p0 = rng.standard_normal((n, n, n)).astype(np.float32)
+    b = np.where(liquid, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    w = _weights(5)
+    sim = _sim(cell)
+    hist = torch.zeros((K + 1, n, n, n), dtype=torch.float32, device="cuda")
+    sim.percnn_forward(w, K, sim.cells_tensor(p0), sim.cells_tensor(b), hist=hist)
+    H = hist.cpu().numpy()
+    from oracle import fluid
+    nc = fluid.poisson_diag(cell)
+    pts = rng.integers(0, n, size=(4000, 3))
+    pts[:300, 0] = 0
+    pts[300:600, 0] = n - 1
+    pts[600:900, 1] = n - 1
+    pts[900:1200, 2] = 0
+    for k in range(1, K + 1):
+        prev = H[k - 1].astype(np.float64)
+        worst = 0.0
+        for z, y, x in pts:
+            acc = float(w[27]) * float(b[z, y, x])
+            for t in range(27):
+                dx, dy, dz = orc_pc.tap_offset(t)
+                zz, yy, xx = z + dz, y + dy, x + dx
+                if 0 <= zz < n and 0 <= yy < n and 0 <= xx < n:
+                    acc += float(w[t]) * prev[zz, yy, xx]
+            ref = 6.0 / nc[z, y, x] * acc if liquid[z, y, x] else 0.0
+            worst = max(worst, abs(float(H[k][z, y, x]) - ref) / (1.0 + abs(ref)))
+        assert worst < 1e-5, (k, worst)
