@@ -54,6 +54,11 @@ BYTES_PER_UNIT = {
 }
 FACE_KINDS = {"advect", "diffuse_explicit", "dcg_dir_spmv", "dcg_update", "advect_adjoint"}
 
+# Recurrent convolutional pressure solver, per cell and layer: forward p 4,
+# b 4, diag 1 in, p 4 out; reverse g 4, diag 1, p 4, b 4 in, g 4 out, and the
+# b gradient 4 + 4 read-modify-write.
+PERCNN_BYTES = {"percnn": 13.0, "percnn_adj": 25.0}
+
 # Algorithmic FLOPs of one U-Net application per fine cell: 2 * 27 * c_in *
 # c_out per voxel of each convolution (real channel counts), with the level-2
 # and level-3 voxel counts 1/8 and 1/64 of the fine level.
@@ -94,6 +99,9 @@ def parse():
                    help="skip the plain (Jacobi) PCG rollout timed beside a learned headline")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-percnn", action="store_true",
+                   help="skip the recurrent convolutional solver's measurement")
+    p.add_argument("--percnn-layers", type=int, default=100)
     p.add_argument("--cpu-n", type=int, default=128)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
@@ -191,6 +199,61 @@ def rooflines(prof, n, precond):
                  "avg_us": round(avg_s * 1e6, 1), "launches": net_launches,
                  "flop_per_launch": flop}, r_hbm)
     return r_hbm, None
+
+
+def percnn_bench(cell, ugen, nu, s, dt, g, dev, K):
+    """The recurrent convolutional pressure solver on the benchmark's state:
+    K layers with the Jacobi kernel from p = 0 (states recorded) and their
+    reverse pass for the squared error against the projection's pressure,
+    timed per layer with HIP events; plus the relative error reached."""
+    import torch
+    from paper_2503_00868_amd import percnn
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="jacobi", tol=1e-8, check_every=16, device=dev)
+    sim.set_params(nu=nu, dt=dt, s=s, gravity=g)
+    u = sim.faces()
+    sim.init_state(ugen, u)
+    a = sim.op_advect(u)
+    b = sim.cells_tensor()
+    sim.op_divergence(a, b)
+    _, p_star = sim.project(tuple(x.clone() for x in a), want_p=True)
+    p_star = p_star.to(torch.float32)
+    L = percnn.liquid_mask(sim)
+    w = percnn.jacobi_weights()
+    hist = torch.empty((K + 1, n, n, n), dtype=torch.float32, device=dev)
+    p0 = torch.zeros_like(b)
+    sim.percnn_forward(w, 2, p0, b, hist=hist[:3])  # warm-up
+    torch.cuda.synchronize()
+    sim.profile_enable(True)
+    t0 = time.perf_counter()
+    sim.percnn_forward(w, K, p0, b, hist=hist)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    err = L * (hist[K] - p_star)
+    rel = float(torch.linalg.norm(err) / torch.linalg.norm(p_star))
+    gK = (2.0 * err).contiguous()
+    t0 = time.perf_counter()
+    sim.percnn_backward(w, K, b, hist, gK)
+    t_bwd = time.perf_counter() - t0
+    prof = sim.profile_read()
+    sim.profile_enable(False)
+    sim.close()
+    del hist
+    out = {"layers": K, "kernel": "jacobi", "rel_error_vs_projection": rel,
+           "fwd_ms": round(t_fwd * 1e3, 2), "bwd_ms": round(t_bwd * 1e3, 2),
+           "cell_layers_per_s": n ** 3 * K / t_fwd}
+    for kind, bpc in PERCNN_BYTES.items():
+        ms_tot, launches = prof[kind]
+        avg_s = ms_tot / launches / 1e3
+        achieved = bpc * n ** 3 / avg_s / 1e9
+        out["roofline_" + kind] = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                   "traffic": load_traffic(kind, n, "jacobi"),
+                                   "avg_us": round(avg_s * 1e6, 2), "launches": launches,
+                                   "bytes_per_launch": bpc * n ** 3}
+    return out
 
 
 def main():
@@ -361,6 +424,13 @@ def main():
         cpu = cpu_baseline(args.cpu_n, args.seed)
         log(f"CPU oracle: {cpu['value']:.3e} cell-steps/s ({cpu['sample']})")
 
+    pc_out = None
+    if not args.no_percnn:
+        pc_out = percnn_bench(cell, ugen, nu_e, s_e, dt, g, dev,
+                              args.percnn_layers)
+        log(f"recurrent conv solver: {pc_out['layers']} layers {pc_out['fwd_ms']:.1f} ms forward, "
+            f"{pc_out['bwd_ms']:.1f} ms reverse; rel error {pc_out['rel_error_vs_projection']:.3e}")
+
     out = {
         "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
         "value": value,
@@ -388,6 +458,7 @@ def main():
         "cpu_baseline": cpu,
         "compare": compare,
         "pressure_iters_mean": float(np.mean(fwd_iters)),
+        "percnn": pc_out,
     }
     print(json.dumps(out), flush=True)
 

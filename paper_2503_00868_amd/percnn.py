@@ -1,0 +1,130 @@
+"""Kernel fitting for the recurrent convolutional pressure solver
+(sim_percnn_forward / sim_percnn_backward; Section 3.4.1, Fig.
+"percnn_str_fit").
+
+The paper fits the solver's convolution kernel on pressure fields recorded
+before and after an implicit solve, then uses the fitted kernel for the
+pressure solve inside its optimisation.  Here a pair is (p_before = 0,
+p_after = the projection's pressure, b = the projection's right-hand side)
+for one velocity field on the context's mask, and the fit minimises the
+mean over pairs of the sum over liquid cells of
+(layer^K(p_before) - p_after)^2 over the 28 weights (W_0 .. W_26, w_b) by
+Adam, with the gradient from the library's reverse pass.  Starting from the
+Jacobi kernel, the fit finds a kernel whose K layers come closer to the
+solution than K Jacobi sweeps.
+
+    python -m paper_2503_00868_amd.percnn --n 64 --layers 32
+"""
+from __future__ import annotations
+
+import argparse
+import time
+
+import numpy as np
+
+from . import inputs
+
+
+def jacobi_weights() -> np.ndarray:
+    """W = 1/6 on the six face taps, w_b = 1/6: one layer is one Jacobi sweep."""
+    w = np.zeros(28)
+    for t in range(27):
+        dx, dy, dz = t % 3 - 1, (t // 3) % 3 - 1, t // 9 - 1
+        if abs(dx) + abs(dy) + abs(dz) == 1:
+            w[t] = 1.0 / 6.0
+    w[27] = 1.0 / 6.0
+    return w
+
+
+def make_pairs(sim, velocity_seeds, dt=1.0 / 120):
+    """(p_before, p_after, b) device triples on the context's mask: the
+    seeded generator's velocity (masked to the mask's active faces), one
+    semi-Lagrangian advection, then its projection's right-hand side and
+    pressure."""
+    torch = sim.torch
+    n = sim.n
+    pairs = []
+    for s in velocity_seeds:
+        _, ug = inputs.gen_case(n, s)
+        sim.set_params(nu=1e-4, dt=dt, s=1.0)
+        u = sim.faces()
+        sim.init_state(sim.to_faces(ug), u)
+        a = sim.op_advect(u)
+        b = sim.cells_tensor()
+        sim.op_divergence(a, b)
+        _, p = sim.project(tuple(x.clone() for x in a), want_p=True)
+        pairs.append((torch.zeros_like(b), p.to(torch.float32), b))
+    return pairs
+
+
+def liquid_mask(sim):
+    return sim.torch.as_tensor(sim.cell == inputs.LIQUID, device=sim.device).to(sim.torch.float32)
+
+
+def rel_error(sim, w, K, pairs):
+    """Mean over pairs of ||L (layer^K(p_before) - p_after)|| / ||p_after||."""
+    torch = sim.torch
+    L = liquid_mask(sim)
+    errs = []
+    for pb, pa, b in pairs:
+        out = sim.percnn_forward(w, K, pb, b)
+        errs.append(float(torch.linalg.norm(L * (out - pa)) / torch.linalg.norm(pa)))
+    return float(np.mean(errs))
+
+
+def fit(sim, pairs, K, steps=100, lr=2e-3, w0=None, log=None):
+    """Adam on the 28 weights; returns (w, per-step mean loss)."""
+    torch = sim.torch
+    n = sim.n
+    L = liquid_mask(sim)
+    w = np.array(jacobi_weights() if w0 is None else w0, dtype=np.float64)
+    m = np.zeros(28)
+    v = np.zeros(28)
+    hist = torch.empty((K + 1, n, n, n), dtype=torch.float32, device=sim.device)
+    losses = []
+    for it in range(1, steps + 1):
+        loss, grad = 0.0, np.zeros(28)
+        for pb, pa, b in pairs:
+            sim.percnn_forward(w, K, pb, b, hist=hist)
+            err = L * (hist[K] - pa)
+            loss += float((err * err).sum())
+            grad += sim.percnn_backward(w, K, b, hist, (2.0 * err).contiguous())
+        loss /= len(pairs)
+        grad /= len(pairs)
+        losses.append(loss)
+        m = 0.9 * m + 0.1 * grad
+        v = 0.999 * v + 0.001 * grad * grad
+        w -= lr * (m / (1 - 0.9 ** it)) / (np.sqrt(v / (1 - 0.999 ** it)) + 1e-12)
+        if log and (it % max(1, steps // 10) == 0 or it == 1):
+            log(f"step {it}: loss {loss:.4e}")
+    return w, losses
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--layers", type=int, default=32)
+    ap.add_argument("--mask-seed", type=int, default=4)
+    ap.add_argument("--train", type=int, default=4, help="training velocity fields")
+    ap.add_argument("--test", type=int, default=2, help="held-out velocity fields")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    args = ap.parse_args(argv)
+    from .fluidsim import Sim
+    cell = inputs.gen_mask(args.n, args.mask_seed)
+    sim = Sim(cell, precond="jacobi", tol=1e-8, max_iter=100000)
+    seeds = list(range(1000, 1000 + args.train + args.test))
+    pairs = make_pairs(sim, seeds)
+    train, test = pairs[:args.train], pairs[args.train:]
+    K = args.layers
+    wj = jacobi_weights()
+    print(f"n={args.n} K={K}: Jacobi kernel, held-out rel error {rel_error(sim, wj, K, test):.4f}", flush=True)
+    t0 = time.perf_counter()
+    w, losses = fit(sim, train, K, args.steps, args.lr, log=lambda s: print(s, flush=True))
+    print(f"fit: {args.steps} steps in {time.perf_counter() - t0:.1f} s; held-out rel error "
+          f"{rel_error(sim, w, K, test):.4f}", flush=True)
+    print("W (dz, dy, dx):", np.array2string(w[:27].reshape(3, 3, 3), precision=4), "w_b", round(w[27], 4))
+
+
+if __name__ == "__main__":
+    main()
