@@ -233,8 +233,9 @@ def percnn_bench(cell, ugen, nu, s, dt, g, dev, K):
     err = L * (hist[K] - p_star)
     rel = float(torch.linalg.norm(err) / torch.linalg.norm(p_star))
     gK = (2.0 * err).contiguous()
+    gp0, gb = torch.zeros_like(b), torch.zeros_like(b)
     t0 = time.perf_counter()
-    sim.percnn_backward(w, K, b, hist, gK)
+    sim.percnn_backward(w, K, b, hist, gK, gp0=gp0, gb=gb)
     t_bwd = time.perf_counter() - t0
     prof = sim.profile_read()
     sim.profile_enable(False)
