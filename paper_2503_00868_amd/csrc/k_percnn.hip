@@ -39,7 +39,18 @@ struct PcWeights {
   float w[PC_NW];
 };
 
-__constant__ float c_six_over_n[7] = {0.f, 6.f, 3.f, 2.f, 1.5f, 1.2f, 1.f};
+// 6 / n_c for a diagonal code n_c in 0 .. 6 (0 off liquid), by selects: a
+// table indexed per lane would be a memory load waited for at once
+__device__ inline float six_over(uint32_t nc) {
+  float s = 0.f;
+  s = nc == 1u ? 6.f : s;
+  s = nc == 2u ? 3.f : s;
+  s = nc == 3u ? 2.f : s;
+  s = nc == 4u ? 1.5f : s;
+  s = nc == 5u ? 1.2f : s;
+  s = nc == 6u ? 1.f : s;
+  return s;
+}
 
 struct PcShape {
   int zc, blocks;
@@ -152,10 +163,10 @@ __global__ void __launch_bounds__(kBlock)
   for (int z = t.z0; z < t.z1; ++z) {
     store(z + 1);
     __syncthreads();
-    if (z + 2 <= t.z1) st.load(p, n, z + 2);
     float bn[4];
     uint8_t gn[4];
     centre(z + 1, bn, gn);
+    if (z + 2 <= t.z1) st.load(p, n, z + 2);
     float acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = W.w[27] * bc[j];
@@ -178,7 +189,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int y = t.y0 + 4 * t.tg + j;
-      if (x < n && y < n) out[x + (int64_t)n * y + nn * z] = c_six_over_n[gc[j]] * acc[j];
+      if (x < n && y < n) out[x + (int64_t)n * y + nn * z] = six_over(gc[j]) * acc[j];
       bc[j] = bn[j];
       gc[j] = gn[j];
     }
@@ -188,7 +199,10 @@ __global__ void __launch_bounds__(kBlock)
 // ------------------------------------------------------------- reverse
 
 // Wf: the weights with the taps reversed (Wf_t = W_{26-t}: offset -t), so
-// that g_k(c) = sum_t Wf_t u(c + t); wb = w_b.  gb (nullable) accumulates.
+// that g_k(c) = sum_t Wf_t u(c + t); wb = w_b.  GB: gb accumulates dL/db
+// (a template flag, so that its loads are unconditional and issued a plane
+// ahead).
+template <bool GB>
 __global__ void __launch_bounds__(kBlock)
     k_percnn_layer_adj(int n, int zc, PcWeights Wf, const float* __restrict__ g,
                        const uint8_t* __restrict__ cdiag, const float* __restrict__ p,
@@ -221,17 +235,21 @@ __global__ void __launch_bounds__(kBlock)
       for (int k = 0; k < PC_ITEMS; ++k) {
         const int hv = threadIdx.x + k * kBlock;
         if (hv < PC_PLANE) {
-          su[hv] = sg.valid(k) ? c_six_over_n[sd.raw[k]] * sg.raw[k] : 0.f;
+          su[hv] = sg.valid(k) ? six_over(sd.raw[k]) * sg.raw[k] : 0.f;
           sq[hv] = sp.valid(k) ? sp.raw[k] : 0.f;
         }
       }
     };
-    auto centre_b = [&](int zi, float (&bo)[4]) {
+    // b and (when accumulated) gb of the thread's 4 cells of a plane, loaded
+    // raw one plane ahead (clamped address outside; those are not stored)
+    auto centre_b = [&](int zi, float (&bo)[4], float (&go)[4]) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int y = t.y0 + 4 * t.tg + j;
         const bool ok = x < n && y < n && zi < t.z1;
-        bo[j] = b[ok ? x + (int64_t)n * y + nn * zi : 0];
+        const int64_t v = ok ? x + (int64_t)n * y + nn * zi : 0;
+        bo[j] = b[v];
+        go[j] = GB ? gb[v] : 0.f;
       }
     };
     load(t.z0 - 1);
@@ -239,14 +257,16 @@ __global__ void __launch_bounds__(kBlock)
     load(t.z0);
     store(t.z0);
     load(t.z0 + 1);
-    float bc[4];
-    centre_b(t.z0, bc);
+    float bc[4], gbc[4];
+    centre_b(t.z0, bc, gbc);
     for (int z = t.z0; z < t.z1; ++z) {
       store(z + 1);
       __syncthreads();
+      // the centre values go out first: a wait for them (in the epilogue)
+      // then does not wait for the plane loads behind them
+      float bn[4], gbn[4];
+      centre_b(z + 1, bn, gbn);
       if (z + 2 <= t.z1) load(z + 2);
-      float bn[4];
-      centre_b(z + 1, bn);
       float acc[4] = {0.f, 0.f, 0.f, 0.f};
       float uc[4];
 #pragma unroll
@@ -280,9 +300,10 @@ __global__ void __launch_bounds__(kBlock)
         if (x < n && y < n) {
           const int64_t v = x + (int64_t)n * y + nn * z;
           gout[v] = acc[j];
-          if (gb) gb[v] += Wf.w[27] * uc[j];
+          if (GB) gb[v] = gbc[j] + Wf.w[27] * uc[j];
         }
         bc[j] = bn[j];
+        gbc[j] = gbn[j];
       }
     }
   }
@@ -409,8 +430,12 @@ int sim_percnn_backward(sim_ctx* c, const float* h_w, int32_t K, const float* b,
   for (int k = K - 1; k >= 0; --k) {
     float* dst = (k == 0 && gp0) ? gp0 : (((K - 1 - k) & 1) ? c->dB : c->dA);
     prof_mark(c, SIM_KERN_PERCNN_ADJ, true);
-    hipLaunchKernelGGL(k_percnn_layer_adj, dim3(sh.blocks), dim3(kBlock), 0, c->stream, c->n, sh.zc,
-                       Wf, src, c->cdiag, hist + k * C, b, dst, gb, c->partials);
+    if (gb)
+      hipLaunchKernelGGL(k_percnn_layer_adj<true>, dim3(sh.blocks), dim3(kBlock), 0, c->stream, c->n,
+                         sh.zc, Wf, src, c->cdiag, hist + k * C, b, dst, gb, c->partials);
+    else
+      hipLaunchKernelGGL(k_percnn_layer_adj<false>, dim3(sh.blocks), dim3(kBlock), 0, c->stream, c->n,
+                         sh.zc, Wf, src, c->cdiag, hist + k * C, b, dst, gb, c->partials);
     prof_mark(c, SIM_KERN_PERCNN_ADJ, false);
     hipLaunchKernelGGL(k_percnn_fold, dim3(1), dim3(kBlock), 0, c->stream, c->partials, sh.blocks,
                        c->pc_acc);
