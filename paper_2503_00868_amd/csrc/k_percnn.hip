@@ -326,22 +326,21 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// acc[q] += sum over blocks of partials[blk * 28 + q] (one block)
+// acc[q] += sum over blocks of partials[blk * 28 + q]; block q sums term q
 __global__ void __launch_bounds__(kBlock)
     k_percnn_fold(const double* __restrict__ partials, int nblocks, double* __restrict__ acc) {
-  __shared__ double red[kBlock / 64][PC_NW];
+  __shared__ double red[kBlock / 64];
+  const int q = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = 0; q < PC_NW; ++q) {
-    double v = 0.0;
-    for (int blk = threadIdx.x; blk < nblocks; blk += kBlock) v += partials[(int64_t)blk * PC_NW + q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) red[wv][q] = v;
-  }
+  double v = 0.0;
+  for (int blk = threadIdx.x; blk < nblocks; blk += kBlock) v += partials[(int64_t)blk * PC_NW + q];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) red[wv] = v;
   __syncthreads();
-  if (threadIdx.x < PC_NW) {
+  if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-    acc[threadIdx.x] += s;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    acc[q] += s;
   }
 }
 
@@ -437,7 +436,7 @@ int sim_percnn_backward(sim_ctx* c, const float* h_w, int32_t K, const float* b,
       hipLaunchKernelGGL(k_percnn_layer_adj<false>, dim3(sh.blocks), dim3(kBlock), 0, c->stream, c->n,
                          sh.zc, Wf, src, c->cdiag, hist + k * C, b, dst, gb, c->partials);
     prof_mark(c, SIM_KERN_PERCNN_ADJ, false);
-    hipLaunchKernelGGL(k_percnn_fold, dim3(1), dim3(kBlock), 0, c->stream, c->partials, sh.blocks,
+    hipLaunchKernelGGL(k_percnn_fold, dim3(PC_NW), dim3(kBlock), 0, c->stream, c->partials, sh.blocks,
                        c->pc_acc);
     src = dst;
   }
