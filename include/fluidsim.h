@@ -270,6 +270,21 @@ int sim_percnn_backward(sim_ctx* ctx, const float* h_w, int32_t K, const float* 
                         const float* d_hist, const float* d_g, float* d_gp0, float* d_gb,
                         double* h_grad_w);
 
+/* ---- constrained divergence projection (Section 3.3, Eq. (divProj)) ----
+ * In place on (d_u, d_v, d_w) (face arrays as sim_step's): the fields are
+ * first masked to the active faces (the variables), then `iters` iterations
+ * of the constraint projection run over the liquid cells' constraints
+ * C_i = (div v)_i: lambda_i = -C_i / (sum_k |dC_i/dv_k|^2 + eps), every face
+ * moved by the multipliers of its two cells at once.  With eps = 0 one
+ * iteration is one Jacobi sweep of the projection's pressure system applied
+ * as a pressure update; the iterations converge to sim_project's field.
+ * h_rel_div (nullable) receives |b(v_K)| / |b(v_0)| (L2 of the projection's
+ * right-hand side after and before; synchronises the stream).  Uses the
+ * context's pressure and right-hand-side buffers.  SIM_ERR_INVALID_ARG for
+ * NULL fields, iters < 0 or eps < 0 / not finite. */
+int sim_constrained_project(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, int32_t iters,
+                            double eps, double* h_rel_div);
+
 /* ---- kernel timing for benchmarks -------------------------------------
  * When enabled, HIP events on the context's stream bracket every launch of
  * the kernels below (the finalize reductions are not included); durations

@@ -92,6 +92,7 @@ SIGNATURES = {
     "sim_percnn_forward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P]),
     "sim_percnn_backward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P, _P,
                                       POINTER(c_double)]),
+    "sim_constrained_project": (c_int32, [_P, _P, _P, _P, c_int32, c_double, POINTER(c_double)]),
     "sim_profile_enable": (c_int32, [_P, c_int32]),
     "sim_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
     "sim_destroy": (c_int32, [_P]),
@@ -335,6 +336,14 @@ class Sim:
                                             _ptr(gp0) if gp0 is not None else None,
                                             _ptr(gb) if gb is not None else None, gw))
         return np.array(gw[:], dtype=np.float64)
+
+    def constrained_project(self, u, iters, eps=0.0):
+        """Constrained divergence projection in place; returns the relative
+        L2 divergence left (|b(u_K)| / |b(u_0)|)."""
+        rel = c_double()
+        self._chk(lib().sim_constrained_project(self.ctx, *map(_ptr, u), int(iters), float(eps),
+                                                byref(rel)))
+        return rel.value
 
     # -- kernel timing
     def profile_enable(self, on=True):
