@@ -58,6 +58,11 @@ FACE_KINDS = {"advect", "diffuse_explicit", "dcg_dir_spmv", "dcg_update", "advec
 # b 4, diag 1 in, p 4 out; reverse g 4, diag 1, p 4, b 4 in, g 4 out, and the
 # b gradient 4 + 4 read-modify-write.
 PERCNN_BYTES = {"percnn": 13.0, "percnn_adj": 25.0}
+# One constrained-projection iteration, per cell, as the three kernels move
+# it: divergence (three face arrays 12, diagonal 1 in; b 4 out), multipliers
+# (b 4, diagonal 1 in; lambda 8 out), pressure update (lambda 8, face codes 3,
+# faces 12 in; faces 12 out).
+CONSTRAINED_BYTES = 65.0
 
 # Algorithmic FLOPs of one U-Net application per fine cell: 2 * 27 * c_in *
 # c_out per voxel of each convolution (real channel counts), with the level-2
@@ -102,6 +107,9 @@ def parse():
     p.add_argument("--no-percnn", action="store_true",
                    help="skip the recurrent convolutional solver's measurement")
     p.add_argument("--percnn-layers", type=int, default=100)
+    p.add_argument("--no-constrained", action="store_true",
+                   help="skip the constrained divergence projection's measurement")
+    p.add_argument("--constrained-iters", type=int, default=100)
     p.add_argument("--cpu-n", type=int, default=128)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
@@ -254,6 +262,42 @@ def percnn_bench(cell, ugen, nu, s, dt, g, dev, K):
                                    "traffic": load_traffic(kind, n, "jacobi"),
                                    "avg_us": round(avg_s * 1e6, 2), "launches": launches,
                                    "bytes_per_launch": bpc * n ** 3}
+    return out
+
+
+def constrained_bench(cell, ugen, nu, s, dt, g, dev, K):
+    """The constrained divergence projection on the benchmark's advected
+    state: K iterations without and with relaxation (eps = half the largest
+    constraint-gradient norm), timed with HIP events on the library's
+    stream, and the relative divergence left."""
+    import torch
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="jacobi", device=dev)
+    sim.set_params(nu=nu, dt=dt, s=s, gravity=g)
+    u = sim.faces()
+    sim.init_state(ugen, u)
+    a = sim.op_advect(u)
+    out = {"iters": K}
+    for name, eps in (("eps0", 0.0), ("relaxed", 3.0 * n * n)):
+        uu = tuple(x.clone() for x in a)
+        sim.constrained_project(tuple(x.clone() for x in a), 2, eps)  # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        rel = sim.constrained_project(uu, K, eps)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        out[name] = {"eps": eps, "ms": round(ms, 2), "us_per_iter": round(ms / K * 1e3, 2),
+                     "rel_divergence_left": rel}
+    us = out["eps0"]["us_per_iter"]
+    achieved = CONSTRAINED_BYTES * n ** 3 / (us * 1e-6) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "constrained iteration (3 kernels)",
+                       "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": load_traffic("constrained", n, "jacobi"),
+                       "avg_us": us, "bytes_per_iter": CONSTRAINED_BYTES * n ** 3}
+    sim.close()
     return out
 
 
@@ -432,6 +476,13 @@ def main():
         log(f"recurrent conv solver: {pc_out['layers']} layers {pc_out['fwd_ms']:.1f} ms forward, "
             f"{pc_out['bwd_ms']:.1f} ms reverse; rel error {pc_out['rel_error_vs_projection']:.3e}")
 
+    cp_out = None
+    if not args.no_constrained:
+        cp_out = constrained_bench(cell, ugen, nu_e, s_e, dt, g, dev, args.constrained_iters)
+        log(f"constrained projection: {cp_out['iters']} iterations {cp_out['eps0']['ms']:.1f} ms "
+            f"({cp_out['eps0']['us_per_iter']:.1f} us each), divergence left "
+            f"{cp_out['eps0']['rel_divergence_left']:.3e} (relaxed {cp_out['relaxed']['rel_divergence_left']:.3e})")
+
     out = {
         "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
         "value": value,
@@ -460,6 +511,7 @@ def main():
         "compare": compare,
         "pressure_iters_mean": float(np.mean(fwd_iters)),
         "percnn": pc_out,
+        "constrained": cp_out,
     }
     print(json.dumps(out), flush=True)
 
