@@ -6,9 +6,9 @@
 // number of active faces of i (the Poisson diagonal), sum_k |dC_i/dv_k|^2 =
 // n_c / h^2 and C_i = -b_i / h^2, so lambda_i = b_i / (n_c + eps h^2), and the
 // face update v_f += (lambda_low - lambda_high) / h is the projection's
-// pressure update with p = lambda.  One iteration is therefore the
-// divergence kernel, the multiplier kernel below and the pressure-update
-// kernel of the projection.
+// pressure update with p = lambda.  One iteration is therefore the kernel
+// below (the projection's divergence and the multiplier in one pass) and
+// the projection's pressure-update kernel.
 #include <cmath>
 
 #include "common.h"
@@ -18,16 +18,29 @@
 namespace fs {
 
 // lambda (FP64, as the pressure update reads it) = b / (n_c + eps h^2) on
-// liquid cells, 0 elsewhere
+// liquid cells, 0 elsewhere, with b = -h (signed outflow) formed as the
+// projection's divergence kernel forms it (FP32, same order)
 __global__ void __launch_bounds__(kBlock)
-    k_cp_lambda(int64_t C, const float* __restrict__ b, const uint8_t* __restrict__ cdiag,
-                double eps_h2, double* __restrict__ lam) {
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < C; i += (int64_t)gridDim.x * kBlock) {
-    const uint8_t d = cdiag[i];
-    lam[i] = d ? (double)b[i] / ((double)d + eps_h2) : 0.0;
+    k_cp_lambda(int n, const uint8_t* __restrict__ cdiag, CF3 in, double eps_h2,
+                double* __restrict__ lam) {
+  const int64_t nn = (int64_t)n * n, C = nn * n;
+  const float h = 1.0f / (float)n;
+  for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
+       idx += (int64_t)gridDim.x * kBlock) {
+    const uint8_t d = cdiag[idx];
+    double out = 0.0;
+    if (d) {
+      const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / nn);
+      const int64_t iu = i + (int64_t)(n + 1) * (j + (int64_t)n * k);
+      const int64_t iv = i + (int64_t)n * (j + (int64_t)(n + 1) * k);
+      const float flux = (in.c[0][iu + 1] - in.c[0][iu]) + (in.c[1][iv + n] - in.c[1][iv]) +
+                         (in.c[2][idx + nn] - in.c[2][idx]);
+      const float b = -h * flux;
+      out = (double)b / ((double)d + eps_h2);
+    }
+    lam[idx] = out;
   }
 }
-
 
 }  // namespace fs
 
@@ -57,9 +70,8 @@ extern "C" int sim_constrained_project(sim_ctx* c, float* u, float* v, float* w,
   if (h_rel_div && div_norm2(&bb0)) return SIM_ERR_HIP;
   const double eps_h2 = eps / ((double)c->n * c->n);
   for (int it = 0; it < iters; ++it) {
-    launch_divergence(c, cu, c->b);
-    hipLaunchKernelGGL(k_cp_lambda, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->C, c->b,
-                       c->cdiag, eps_h2, c->x);
+    hipLaunchKernelGGL(k_cp_lambda, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n,
+                       c->cdiag, cu, eps_h2, c->x);
     launch_pressure_update(c, c->x, U);
   }
   if (h_rel_div) {
