@@ -60,3 +60,34 @@ class _MSE(torch.autograd.Function):
     def backward(ctx, gJ):
         s = gJ.to(torch.float32)
         return (None, ctx.g[0] * s, ctx.g[1] * s, ctx.g[2] * s, None, None, None)
+
+
+class PercnnSolve(torch.autograd.Function):
+    """K layers of the recurrent convolutional pressure solver (Section
+    3.4.1; sim_percnn_forward) with its reverse pass (sim_percnn_backward):
+    gradients flow to the 28 weights (W_0 .. W_26, w_b; a float64 tensor on
+    any device), to the starting pressure p0 and to the right-hand side b."""
+
+    @staticmethod
+    def forward(ctx, w, p0, b, sim, K):
+        n = sim.n
+        wn = w.detach().to("cpu", torch.float64).numpy()
+        hist = torch.empty((K + 1, n, n, n), dtype=torch.float32, device=p0.device)
+        p0c, bc = p0.contiguous(), b.contiguous()
+        sim.percnn_forward(wn, K, p0c, bc, hist=hist)
+        ctx.sim, ctx.K, ctx.wn = sim, K, wn
+        ctx.save_for_backward(w, bc, hist)
+        return hist[K].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        w, b, hist = ctx.saved_tensors
+        sim = ctx.sim
+        gp0, gb = torch.empty_like(b), torch.empty_like(b)
+        gw = sim.percnn_backward(ctx.wn, ctx.K, b, hist, g.contiguous(), gp0=gp0, gb=gb)
+        return torch.as_tensor(gw, dtype=w.dtype, device=w.device), gp0, gb, None, None
+
+
+def percnn_solve(w, p0, b, sim, K):
+    """p_K of K recurrent layers, differentiable in (w, p0, b)."""
+    return PercnnSolve.apply(w, p0, b, sim, K)

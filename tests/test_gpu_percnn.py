@@ -173,3 +173,32 @@ def test_fit_beats_jacobi_at_fixed_depth(torch_gpu):
     banner(f"  held-out rel error: Jacobi {e_j:.4f}, fitted {e_f:.4f}; loss {losses[0]:.3e} -> {losses[-1]:.3e}")
     assert losses[-1] < 0.7 * losses[0]
     assert e_f < 0.9 * e_j
+
+
+def test_autograd_function_matches_oracle(torch_gpu):
+    """PercnnSolve: a torch loss through K layers gives the oracle's
+    gradients in the weights, the start and the right-hand side."""
+    torch = torch_gpu
+    from paper_2503_00868_amd.autograd import percnn_solve
+    n, K = 24, 5
+    banner(f"percnn autograd n={n} K={K}")
+    cell, p0, b = _case(n, 7)
+    w = _weights(7).astype(np.float64)
+    sim = _sim(cell)
+    wt = torch.tensor(w, requires_grad=True)
+    p0t = sim.cells_tensor(p0).requires_grad_(True)
+    bt = sim.cells_tensor(b).requires_grad_(True)
+    g = np.random.default_rng(3).standard_normal((n, n, n)).astype(np.float32)
+    gt = sim.cells_tensor(g)
+    out = percnn_solve(wt, p0t, bt, sim, K)
+    (out * gt).sum().backward()
+    w32 = w.astype(np.float32).astype(np.float64)  # the library computes with float32 weights
+    ps = orc_pc.forward(cell, p0.astype(np.float64), b.astype(np.float64), w32[:27], w32[27], K)
+    r_gp, r_gb, r_gW, r_gwb = orc_pc.backward(cell, ps, b.astype(np.float64), w32[:27], w32[27],
+                                              g.astype(np.float64))
+    ref_w = np.concatenate([r_gW, [r_gwb]])
+    e_w = np.abs(wt.grad.numpy() - ref_w).max() / np.abs(ref_w).max()
+    e_p = np.abs(p0t.grad.cpu().numpy() - r_gp).max() / np.abs(r_gp).max()
+    e_b = np.abs(bt.grad.cpu().numpy() - r_gb).max() / np.abs(r_gb).max()
+    banner(f"  rel err dW {e_w:.2e} dp0 {e_p:.2e} db {e_b:.2e}")
+    assert e_w < 1e-5 and e_p < 1e-5 and e_b < 1e-5
