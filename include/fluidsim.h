@@ -239,6 +239,17 @@ int sim_op_precond_apply(sim_ctx* ctx, int32_t precond, const float* d_r, float*
 int sim_op_advect_adjoint(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
                           const float* d_lu, const float* d_lv, const float* d_lw, float* d_gu,
                           float* d_gv, float* d_gw);
+/* The paper's upwind analytic convection gradient (Section 3.4.1), a
+ * surrogate for the advection adjoint above: for the convected field
+ * (d_u, d_v, d_w) and lam = dJ/d(convected field) (d_lu, d_lv, d_lw),
+ * d_g_i = lam_i - dt sum_c Lam_c D_i V_c on active faces (0 elsewhere), with
+ * V_c, Lam_c the components at the face's position (four-face means across
+ * components) and D_i the first-order upwind difference along the face's
+ * axis against the sign of v_i.  dt from sim_set_params.  Outputs must not
+ * alias inputs. */
+int sim_op_convection_grad_upwind(sim_ctx* ctx, const float* d_u, const float* d_v,
+                                  const float* d_w, const float* d_lu, const float* d_lv,
+                                  const float* d_lw, float* d_gu, float* d_gv, float* d_gw);
 
 /* ---- recurrent convolutional pressure solver (Section 3.4.1) -----------
  * The paper solves the pressure Poisson equation inside its optimisation

@@ -89,6 +89,7 @@ SIGNATURES = {
     "sim_op_poisson_apply": (c_int32, [_P, _P, _P]),
     "sim_op_precond_apply": (c_int32, [_P, c_int32, _P, _P]),
     "sim_op_advect_adjoint": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_op_convection_grad_upwind": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sim_percnn_forward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P]),
     "sim_percnn_backward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P, _P,
                                       POINTER(c_double)]),
@@ -295,6 +296,13 @@ class Sim:
         out = out if out is not None else self.faces()
         self._chk(lib().sim_op_advect_adjoint(self.ctx, *map(_ptr, u), *map(_ptr, lam),
                                               *map(_ptr, out)))
+        return out
+
+    def op_convection_grad_upwind(self, u, lam, out=None):
+        """The paper's upwind convection gradient for the convected field u."""
+        out = out if out is not None else self.faces()
+        self._chk(lib().sim_op_convection_grad_upwind(self.ctx, *map(_ptr, u), *map(_ptr, lam),
+                                                      *map(_ptr, out)))
         return out
 
     def harvest_pairs(self, u, iters, tol=1e-10, r_out=None, e_out=None, mode=0):
