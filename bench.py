@@ -63,6 +63,10 @@ PERCNN_BYTES = {"percnn": 13.0, "percnn_adj": 25.0}
 # lambda 8 out), pressure update (lambda 8, face codes 3, faces 12 in; faces
 # 12 out).
 CONSTRAINED_BYTES = 56.0
+# The paper's upwind convection gradient, per face: own component of the
+# convected field 4, lambda 4, face code 1 in; gradient 4 out (the other
+# components' values around the face are re-reads of cached lines).
+UPWIND_BYTES = 13.0
 
 # Algorithmic FLOPs of one U-Net application per fine cell: 2 * 27 * c_in *
 # c_out per voxel of each convolution (real channel counts), with the level-2
@@ -110,6 +114,8 @@ def parse():
     p.add_argument("--no-constrained", action="store_true",
                    help="skip the constrained divergence projection's measurement")
     p.add_argument("--constrained-iters", type=int, default=100)
+    p.add_argument("--no-upwind", action="store_true",
+                   help="skip the upwind convection gradient's measurement")
     p.add_argument("--cpu-n", type=int, default=128)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
@@ -301,6 +307,40 @@ def constrained_bench(cell, ugen, nu, s, dt, g, dev, K):
     return out
 
 
+def upwind_bench(cell, ugen, nu, s, dt, g, dev, reps=10):
+    """The paper's upwind convection gradient at the benchmark's state (the
+    convected field after one advection, a seeded lambda), timed over `reps`
+    calls with HIP events, with its HBM roofline."""
+    import torch
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="jacobi", device=dev)
+    sim.set_params(nu=nu, dt=dt, s=s, gravity=g)
+    u = sim.faces()
+    sim.init_state(ugen, u)
+    a = sim.op_advect(u)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    lam = tuple(torch.randn(x.shape, device=dev, generator=gen) for x in a)
+    out = sim.faces()
+    sim.op_convection_grad_upwind(a, lam, out)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        sim.op_convection_grad_upwind(a, lam, out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+    faces = 3 * (n + 1) * n * n
+    achieved = UPWIND_BYTES * faces / (us * 1e-6) / 1e9
+    sim.close()
+    return {"us_per_call": round(us, 2),
+            "roofline": {"bound": "hbm", "kernel": "k_convection_grad_upwind",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": load_traffic("upwind", n, "jacobi"), "avg_us": round(us, 2),
+                         "bytes_per_call": UPWIND_BYTES * faces}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -483,6 +523,11 @@ def main():
             f"({cp_out['eps0']['us_per_iter']:.1f} us each), divergence left "
             f"{cp_out['eps0']['rel_divergence_left']:.3e} (relaxed {cp_out['relaxed']['rel_divergence_left']:.3e})")
 
+    up_out = None
+    if not args.no_upwind:
+        up_out = upwind_bench(cell, ugen, nu_e, s_e, dt, g, dev)
+        log(f"upwind convection gradient: {up_out['us_per_call']:.1f} us per call")
+
     out = {
         "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
         "value": value,
@@ -512,6 +557,7 @@ def main():
         "pressure_iters_mean": float(np.mean(fwd_iters)),
         "percnn": pc_out,
         "constrained": cp_out,
+        "upwind": up_out,
     }
     print(json.dumps(out), flush=True)
 
