@@ -93,62 +93,68 @@ def gradient(cell, v, lam, dt):
     return tuple(out)
 
 
+def _face_val(n, arr, c, idx):
+    """Face idx = (k, j, i) of component c, zero outside its array."""
+    k, j, i = idx
+    shp = fluid.face_shape(n, c)
+    if 0 <= k < shp[0] and 0 <= j < shp[1] and 0 <= i < shp[2]:
+        return float(arr[c][k, j, i])
+    return 0.0
+
+
+def _at_pos(n, arr, c, comp, idx):
+    """arr's component c at the position of the comp-face idx = (k, j, i)."""
+    if c == comp:
+        return _face_val(n, arr, c, idx)
+    shp = fluid.face_shape(n, comp)
+    if not all(0 <= x < s for x, s in zip(idx, shp)):
+        return 0.0
+    ai, ac = 2 - comp, 2 - c
+    s = 0.0
+    for da in (-1, 0):
+        for dc in (0, 1):
+            q = list(idx)
+            q[ai] = idx[ai] + da
+            q[ac] = idx[ac] + dc
+            if not (0 <= q[ai] < n):
+                continue
+            s += 0.25 * _face_val(n, arr, c, tuple(q))
+    return s
+
+
+def face_gradient(n, v, lam, dt, comp, idx):
+    """dJ/dv'_comp at the comp-face idx = (k, j, i), taken as active (the
+    caller zeroes non-active faces), by the definition face by face."""
+    h = 1.0 / n
+    ax = 2 - comp
+    lo, hi = list(idx), list(idx)
+    lo[ax] -= 1
+    hi[ax] += 1
+    acc = float(lam[comp][tuple(idx)])
+    for c in range(3):
+        V0 = _at_pos(n, v, c, comp, tuple(idx))
+        d = ((V0 - _at_pos(n, v, c, comp, tuple(lo))) if v[comp][tuple(idx)] > 0
+             else (_at_pos(n, v, c, comp, tuple(hi)) - V0)) / h
+        acc -= dt * _at_pos(n, lam, c, comp, tuple(idx)) * d
+    return acc
+
+
 def gradient_loops(cell, v, lam, dt):
-    """The same, face by face with explicit loops (small grids only)."""
+    """The same as gradient(), face by face with explicit loops (small grids
+    only)."""
     cell = np.asarray(cell, dtype=np.uint8)
     n = cell.shape[0]
-    h = 1.0 / n
     v = [np.asarray(a, dtype=np.float64) for a in v]
     lam = [np.asarray(a, dtype=np.float64) for a in lam]
-
-    def face_val(arr, c, idx):
-        k, j, i = idx
-        shp = fluid.face_shape(n, c)
-        if 0 <= k < shp[0] and 0 <= j < shp[1] and 0 <= i < shp[2]:
-            return arr[c][k, j, i]
-        return 0.0
-
-    def at_pos(arr, c, comp, idx):
-        """arr's component c at the position of comp-face idx = (k, j, i)."""
-        if c == comp:
-            return face_val(arr, c, idx)
-        shp = fluid.face_shape(n, comp)
-        if not all(0 <= x < s for x, s in zip(idx, shp)):
-            return 0.0
-        pos = list(idx)  # [k, j, i]
-        ai, ac = 2 - comp, 2 - c
-        s = 0.0
-        for da in (-1, 0):
-            for dc in (0, 1):
-                q = list(pos)
-                q[ai] = pos[ai] + da
-                q[ac] = pos[ac] + dc
-                if not (0 <= q[ai] < n):
-                    continue
-                s += 0.25 * face_val(arr, c, tuple(q))
-        return s
-
     out = []
     for comp in range(3):
         act = fluid.face_classes(cell, comp) == fluid.ACTIVE
         shp = fluid.face_shape(n, comp)
         g = np.zeros(shp)
-        ax = 2 - comp
         for k in range(shp[0]):
             for j in range(shp[1]):
                 for i in range(shp[2]):
-                    if not act[k, j, i]:
-                        continue
-                    idx = [k, j, i]
-                    lo, hi = list(idx), list(idx)
-                    lo[ax] -= 1
-                    hi[ax] += 1
-                    acc = lam[comp][k, j, i]
-                    for c in range(3):
-                        V0 = at_pos(v, c, comp, tuple(idx))
-                        d = ((V0 - at_pos(v, c, comp, tuple(lo))) if v[comp][k, j, i] > 0
-                             else (at_pos(v, c, comp, tuple(hi)) - V0)) / h
-                        acc -= dt * at_pos(lam, c, comp, tuple(idx)) * d
-                    g[k, j, i] = acc
+                    if act[k, j, i]:
+                        g[k, j, i] = face_gradient(n, v, lam, dt, comp, (k, j, i))
         out.append(g)
     return tuple(out)
