@@ -19,64 +19,85 @@ struct UpFaces {
   const float* a[3];
 };
 
-// face (x, y, z) of component c (zero outside its array)
-__device__ inline float up_face(const UpFaces& f, int n, int c, int x, int y, int z) {
-  const int nx = n + (c == 0), ny = n + (c == 1), nz = n + (c == 2);
+// face (x, y, z) of component C (zero outside its array); a component holds
+// fewer than 2^31 faces for n <= 1024, so 32-bit indexes suffice
+template <int C>
+__device__ inline float up_face(const UpFaces& f, int n, int x, int y, int z) {
+  const int nx = n + (C == 0), ny = n + (C == 1), nz = n + (C == 2);
   if ((unsigned)x >= (unsigned)nx || (unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz)
     return 0.f;
-  return f.a[c][x + (int64_t)nx * (y + (int64_t)ny * z)];
+  return f.a[C][x + nx * (y + ny * z)];
 }
 
-// component c at the position of the i-face (x, y, z)
-__device__ inline float up_at(const UpFaces& f, int n, int c, int i, int x, int y, int z) {
-  if (c == i) return up_face(f, n, c, x, y, z);
-  const int nx = n + (i == 0), ny = n + (i == 1), nz = n + (i == 2);
-  if ((unsigned)x >= (unsigned)nx || (unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz)
-    return 0.f;
-  float s = 0.f;
+// component C at the position of the I-face (x, y, z)
+template <int C, int I>
+__device__ inline float up_at(const UpFaces& f, int n, int x, int y, int z) {
+  if constexpr (C == I) {
+    return up_face<C>(f, n, x, y, z);
+  } else {
+    const int nx = n + (I == 0), ny = n + (I == 1), nz = n + (I == 2);
+    if ((unsigned)x >= (unsigned)nx || (unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz)
+      return 0.f;
+    float s = 0.f;
 #pragma unroll
-  for (int da = -1; da <= 0; ++da)
+    for (int da = -1; da <= 0; ++da)
 #pragma unroll
-    for (int dc = 0; dc <= 1; ++dc) {
-      int q[3] = {x, y, z};
-      q[i] += da;  // the cells on either side along the face's axis
-      q[c] += dc;  // the two c-faces of the cell along axis c
-      if ((unsigned)q[i] >= (unsigned)n) continue;
-      s += up_face(f, n, c, q[0], q[1], q[2]);
-    }
-  return 0.25f * s;
+      for (int dc = 0; dc <= 1; ++dc) {
+        int q[3] = {x, y, z};
+        q[I] += da;  // the cells on either side along the face's axis
+        q[C] += dc;  // the two C-faces of the cell along axis C
+        if ((unsigned)q[I] >= (unsigned)n) continue;
+        s += up_face<C>(f, n, q[0], q[1], q[2]);
+      }
+    return 0.25f * s;
+  }
 }
 
-__global__ void __launch_bounds__(kBlock)
-    k_convection_grad_upwind(int n, int64_t F, const uint8_t* __restrict__ fcode, UpFaces v,
-                             UpFaces lam, float dt_over_h, float* __restrict__ g0,
-                             float* __restrict__ g1, float* __restrict__ g2) {
-  const int i = blockIdx.y;  // face component
-  float* g = i == 0 ? g0 : (i == 1 ? g1 : g2);
-  const int nx = n + (i == 0), ny = n + (i == 1);
-  const int64_t count = (int64_t)nx * ny * (n + (i == 2));
-  const uint8_t* code = fcode + i * F;
-  for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < count;
-       idx += (int64_t)gridDim.x * kBlock) {
+// sum_c Lam_c(f) D_I V_c(f) for the I-face (x, y, z), nb its upwind neighbour
+template <int C, int I>
+__device__ inline float up_term(const UpFaces& v, const UpFaces& lam, int n, int x, int y, int z,
+                                const int (&nb)[3], float v0, float sgn) {
+  const float vc = C == I ? v0 : up_at<C, I>(v, n, x, y, z);
+  const float d = sgn * (vc - up_at<C, I>(v, n, nb[0], nb[1], nb[2]));
+  return up_at<C, I>(lam, n, x, y, z) * d;
+}
+
+template <int I>
+__device__ inline void upwind_faces(int n, const uint8_t* __restrict__ code, const UpFaces& v,
+                                    const UpFaces& lam, float dt_over_h, float* __restrict__ g) {
+  const unsigned nx = n + (I == 0), ny = n + (I == 1);
+  const unsigned count = nx * ny * (unsigned)(n + (I == 2));
+  for (unsigned idx = blockIdx.x * kBlock + threadIdx.x; idx < count; idx += gridDim.x * kBlock) {
     if (!(code[idx] & FC_ACTIVE)) {
       g[idx] = 0.f;
       continue;
     }
-    const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
-    const bool pos = v.a[i][idx] > 0.f;
-    int lo[3] = {x, y, z}, hi[3] = {x, y, z};
-    lo[i] -= 1;
-    hi[i] += 1;
-    float acc = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float v0 = up_at(v, n, c, i, x, y, z);
-      const float d = pos ? v0 - up_at(v, n, c, i, lo[0], lo[1], lo[2])
-                          : up_at(v, n, c, i, hi[0], hi[1], hi[2]) - v0;
-      acc += up_at(lam, n, c, i, x, y, z) * d;
-    }
-    g[idx] = lam.a[i][idx] - dt_over_h * acc;
+    const unsigned row = idx / nx, zu = row / ny;
+    const int x = (int)(idx - row * nx), y = (int)(row - zu * ny), z = (int)zu;
+    const float v0 = v.a[I][idx];
+    // the upwind neighbour: one face back along axis I when v_I > 0, else one
+    // forward; D_I V_c = sgn (V_c(f) - V_c(neighbour)) / h
+    const float sgn = v0 > 0.f ? 1.f : -1.f;
+    int nb[3] = {x, y, z};
+    nb[I] -= v0 > 0.f ? 1 : -1;
+    const float acc = up_term<0, I>(v, lam, n, x, y, z, nb, v0, sgn) +
+                      up_term<1, I>(v, lam, n, x, y, z, nb, v0, sgn) +
+                      up_term<2, I>(v, lam, n, x, y, z, nb, v0, sgn);
+    g[idx] = lam.a[I][idx] - dt_over_h * acc;
   }
+}
+
+// grid (blocks, 3): blockIdx.y is the face component, uniform per block
+__global__ void __launch_bounds__(kBlock)
+    k_convection_grad_upwind(int n, int64_t F, const uint8_t* __restrict__ fcode, UpFaces v,
+                             UpFaces lam, float dt_over_h, float* __restrict__ g0,
+                             float* __restrict__ g1, float* __restrict__ g2) {
+  if (blockIdx.y == 0)
+    upwind_faces<0>(n, fcode, v, lam, dt_over_h, g0);
+  else if (blockIdx.y == 1)
+    upwind_faces<1>(n, fcode + F, v, lam, dt_over_h, g1);
+  else
+    upwind_faces<2>(n, fcode + 2 * F, v, lam, dt_over_h, g2);
 }
 
 }  // namespace fs

@@ -71,3 +71,37 @@ def test_against_exact_adjoint_and_central_differences(torch_gpu):
            f"cosine(exact, surrogate) {cos:.4f}")
     assert abs(dd_ex - fd) <= 1e-4 * abs(fd)
     assert np.isfinite(dd_up) and cos > 0.5
+
+
+def test_full_size_sampled(torch_gpu):
+    """256^3, the benchmark's size and launch: non-active faces exactly 0;
+    sampled active faces (random ones, and some on the first, second, middle
+    and last planes and on a few fixed rows) against the oracle's face-by-face
+    definition."""
+    n = 256
+    banner(f"upwind convection gradient n={n}, sampled faces")
+    cell, ug = inputs.gen_case(n, 4)
+    rng = np.random.default_rng(6)
+    v = f32(fluid.mask_faces(cell, tuple(np.asarray(g) + 0.2 * rng.standard_normal(np.shape(g)) for g in ug)))
+    lam = f32(tuple(rng.standard_normal(fluid.face_shape(n, c)) for c in range(3)))
+    sim = _sim(cell)
+    g = to_np(sim.op_convection_grad_upwind(sim.to_faces(v), sim.to_faces(lam)))
+    v64 = [np.asarray(a, np.float64) for a in v]
+    l64 = [np.asarray(a, np.float64) for a in lam]
+    worst, scale = 0.0, 0.0
+    for comp in range(3):
+        act = fluid.face_classes(cell, comp) == fluid.ACTIVE
+        assert not np.any(g[comp][~act]), comp
+        shp = act.shape
+        picks = [tuple(rng.integers(0, s) for s in shp) for _ in range(800)]
+        for y in (7, 8, 15, 16, shp[1] - 1):
+            for z in (0, 1, shp[0] // 2, shp[0] - 1):
+                picks += [(z, y, int(x)) for x in rng.integers(0, shp[2], 4)]
+        picks = [p for p in picks if act[p]]
+        assert len(picks) > 250
+        for p in picks:
+            ref = orc_up.face_gradient(n, v64, l64, DT, comp, p)
+            worst = max(worst, abs(float(g[comp][p]) - ref))
+            scale = max(scale, abs(ref))
+    banner(f"  max rel err {worst / scale:.2e}")
+    assert worst <= 1e-5 * scale, (worst, scale)
