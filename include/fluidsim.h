@@ -167,6 +167,28 @@ int sim_loss_mse(sim_ctx* ctx, const float* d_u, const float* d_v, const float* 
                  const float* d_tu, const float* d_tv, const float* d_tw, double* h_loss,
                  float* d_gu, float* d_gv, float* d_gw);
 
+/* The paper's masked cosine + L2 velocity loss (Section 3.4.2,
+ * Eq. (optLoss)) between the simulated field (d_u, d_v, d_w) and a reference
+ * (d_tu, d_tv, d_tw), both MAC face arrays of the context's grid.  Per cell,
+ * with a and b the two velocities at the cell centre (component c the mean
+ * of the cell's two c-faces):
+ *   l = alpha (1 - a.b / sqrt((|a|^2 + eps^2)(|b|^2 + eps^2))) + beta |a - b|^2
+ * weighted by the cell's class from the context's cell types:
+ * h_weights[0] for air (empty) cells, h_weights[1] for liquid cells with no
+ * air neighbour among the six (occupied), h_weights[2] for liquid cells with
+ * one (surface); solid cells and the outside of the box weigh 0.
+ * h_loss receives J = sum w l / sum w (0 when sum w = 0).  (d_gu, d_gv, d_gw)
+ * (all or none) receive dJ/d(d_u, d_v, d_w) on every face: half of dJ/da of
+ * each cell the face separates.  Uses the context's partial-sum buffers and
+ * three of its solver buffers (free outside a solve); synchronises the
+ * stream.  SIM_ERR_INVALID_ARG for NULL inputs, a partial gradient set, a
+ * gradient output aliasing an input, non-finite alpha or beta, eps < 0 or
+ * not finite, or a negative / non-finite weight. */
+int sim_loss_cos_l2(sim_ctx* ctx, const float* d_u, const float* d_v, const float* d_w,
+                    const float* d_tu, const float* d_tv, const float* d_tw, double alpha,
+                    double beta, double eps, const double* h_weights, double* h_loss,
+                    float* d_gu, float* d_gv, float* d_gw);
+
 /* ---- learned preconditioner (Section 3.4.1 analogue) ---------------------
  * A 3-level 3-D U-Net (16/32/64 channels, 3x3x3 bias-free convolutions,
  * ReLU, 2x average pooling, nearest upsampling with skip concatenation, one

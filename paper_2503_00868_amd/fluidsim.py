@@ -74,6 +74,8 @@ SIGNATURES = {
     "sim_backward": (c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, POINTER(c_double),
                                POINTER(sim_stats)]),
     "sim_loss_mse": (c_int32, [_P, _P, _P, _P, _P, _P, _P, POINTER(c_double), _P, _P, _P]),
+    "sim_loss_cos_l2": (c_int32, [_P, _P, _P, _P, _P, _P, _P, c_double, c_double, c_double,
+                                  POINTER(c_double), POINTER(c_double), _P, _P, _P]),
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
     "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
     "sim_net_forward": (c_int32, [_P, _P, _P]),
@@ -263,6 +265,16 @@ class Sim:
         J = c_double()
         self._chk(lib().sim_loss_mse(self.ctx, *map(_ptr, u), *map(_ptr, target), byref(J),
                                      *map(_ptr, g)))
+        return J.value, (g if want_grad else None)
+
+    def loss_cos_l2(self, u, ref, alpha, beta, eps, weights, want_grad=True, out=None):
+        """The paper's masked cosine + L2 velocity loss of u against ref, and
+        dJ/du (into `out` when given); weights = (empty, occupied, surface)."""
+        g = (out if out is not None else self.faces()) if want_grad else (None, None, None)
+        J = c_double()
+        w = (c_double * 3)(*[float(x) for x in weights])
+        self._chk(lib().sim_loss_cos_l2(self.ctx, *map(_ptr, u), *map(_ptr, ref), float(alpha),
+                                        float(beta), float(eps), w, byref(J), *map(_ptr, g)))
         return J.value, (g if want_grad else None)
 
     def op_advect(self, u, out=None):

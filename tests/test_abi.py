@@ -133,6 +133,8 @@ def test_null_arguments():
     assert L.sim_percnn_backward(None, None, 1, *([None] * 6)) == fsb.SIM_ERR_INVALID_ARG
     assert L.sim_constrained_project(None, None, None, None, 1, 0.0, None) == fsb.SIM_ERR_INVALID_ARG
     assert L.sim_op_convection_grad_upwind(None, *([None] * 9)) == fsb.SIM_ERR_INVALID_ARG
+    assert L.sim_loss_cos_l2(None, *([None] * 6), 1.0, 1.0, 0.0, None, None, None, None,
+                             None) == fsb.SIM_ERR_INVALID_ARG
     assert fsb.lib().sim_last_error(None) == b"NULL context"
 
 
