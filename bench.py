@@ -67,6 +67,9 @@ CONSTRAINED_BYTES = 56.0
 # convected field 4, lambda 4, face code 1 in; gradient 4 out (the other
 # components' values around the face are re-reads of cached lines).
 UPWIND_BYTES = 13.0
+# The paper's masked cosine + L2 velocity loss with its gradient, per cell:
+# simulated and reference faces 12 + 12, cell type 1 in; gradient 12 out.
+LOSS_BYTES = 37.0
 
 # Algorithmic FLOPs of one U-Net application per fine cell: 2 * 27 * c_in *
 # c_out per voxel of each convolution (real channel counts), with the level-2
@@ -116,6 +119,8 @@ def parse():
     p.add_argument("--constrained-iters", type=int, default=100)
     p.add_argument("--no-upwind", action="store_true",
                    help="skip the upwind convection gradient's measurement")
+    p.add_argument("--no-loss", action="store_true",
+                   help="skip the masked cosine + L2 loss's measurement")
     p.add_argument("--cpu-n", type=int, default=128)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
@@ -341,6 +346,40 @@ def upwind_bench(cell, ugen, nu, s, dt, g, dev, reps=10):
                          "bytes_per_call": UPWIND_BYTES * faces}}
 
 
+def loss_bench(cell, ugen, nu, s, dt, g, dev, reps=10):
+    """The paper's masked cosine + L2 velocity loss and its gradient at the
+    benchmark's state (the field after one advection against the initial
+    one; weights 0.2 / 1 / 2 for empty / occupied / surface cells), timed
+    over `reps` calls with HIP events (each call reads J back to the host),
+    with its HBM roofline."""
+    import torch
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="jacobi", device=dev)
+    sim.set_params(nu=nu, dt=dt, s=s, gravity=g)
+    u = sim.faces()
+    sim.init_state(ugen, u)
+    a = sim.op_advect(u)
+    out = sim.faces()
+    args = (1.0, 1.0, 1e-3, (0.2, 1.0, 2.0))
+    J, _ = sim.loss_cos_l2(a, u, *args, out=out)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        sim.loss_cos_l2(a, u, *args, out=out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+    cells = n ** 3
+    achieved = LOSS_BYTES * cells / (us * 1e-6) / 1e9
+    sim.close()
+    return {"J": J, "us_per_call": round(us, 2),
+            "roofline": {"bound": "hbm", "kernel": "k_loss_cells + k_loss_fold + k_loss_face_grad",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_us": round(us, 2), "bytes_per_call": LOSS_BYTES * cells}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -528,6 +567,11 @@ def main():
         up_out = upwind_bench(cell, ugen, nu_e, s_e, dt, g, dev)
         log(f"upwind convection gradient: {up_out['us_per_call']:.1f} us per call")
 
+    loss_out = None
+    if not args.no_loss:
+        loss_out = loss_bench(cell, ugen, nu_e, s_e, dt, g, dev)
+        log(f"masked cosine + L2 loss with gradient: {loss_out['us_per_call']:.1f} us per call")
+
     out = {
         "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
         "value": value,
@@ -558,6 +602,7 @@ def main():
         "percnn": pc_out,
         "constrained": cp_out,
         "upwind": up_out,
+        "loss": loss_out,
     }
     print(json.dumps(out), flush=True)
 
