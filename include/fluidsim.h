@@ -318,6 +318,35 @@ int sim_percnn_backward(sim_ctx* ctx, const float* h_w, int32_t K, const float* 
 int sim_constrained_project(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, int32_t iters,
                             double eps, double* h_rel_div);
 
+/* ---- the paper's APIC transfers (Section 3.2.2, Eq. (particle_map)) -----
+ * On the MAC grid each velocity component lives on its own lattice, the
+ * centres of its faces (component 0's node (i, j, k) at h (i, j + 1/2,
+ * k + 1/2), and likewise), with quadratic B-spline weights (a product over
+ * the three axes); nodes outside a lattice are skipped (weight 0 for
+ * particles at least one cell inside the box).  Particles are device arrays
+ * of structures in the unit box: positions d_x (P x 3: x y z), velocities
+ * d_vp (P x 3), affine matrices d_C (P x 9, row a the affine part of
+ * component a), masses d_m (P).  P in [0, 2^31).  Both calls are
+ * asynchronous on the context's stream. */
+
+/* Particles to grid: (d_u, d_v, d_w) receive, per face node,
+ * sum_p w m_p (v_pa + C_p[a] . (x_i - x_p)) / sum_p w m_p (0 where no mass
+ * arrived) and (d_mu, d_mv, d_mw) the weighted masses sum_p w m_p.  The six
+ * grid outputs are overwritten and must be distinct.  The summation order of
+ * the FP32 atomic scatter is not fixed.  SIM_ERR_INVALID_ARG for P out of
+ * range or a NULL pointer (the particle pointers may be NULL when P = 0). */
+int sim_apic_p2g(sim_ctx* ctx, int64_t P, const float* d_x, const float* d_vp, const float* d_C,
+                 const float* d_m, float* d_u, float* d_v, float* d_w, float* d_mu, float* d_mv,
+                 float* d_mw);
+
+/* Grid to particles and the particle move: for the grid field (d_u, d_v,
+ * d_w) (the field after the grid step), d_vp receives v_pa = sum_i w v_ai,
+ * d_C row a receives 4/h^2 sum_i w v_ai (x_i - x_p), and d_x is moved by
+ * dt times the new velocity (in place).  SIM_ERR_INVALID_ARG for P out of
+ * range, a NULL pointer or a non-finite dt. */
+int sim_apic_g2p(sim_ctx* ctx, int64_t P, const float* d_u, const float* d_v, const float* d_w,
+                 double dt, float* d_x, float* d_vp, float* d_C);
+
 /* ---- kernel timing for benchmarks -------------------------------------
  * When enabled, HIP events on the context's stream bracket every launch of
  * the kernels below (the finalize reductions are not included); durations

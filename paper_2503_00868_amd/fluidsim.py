@@ -76,6 +76,8 @@ SIGNATURES = {
     "sim_loss_mse": (c_int32, [_P, _P, _P, _P, _P, _P, _P, POINTER(c_double), _P, _P, _P]),
     "sim_loss_cos_l2": (c_int32, [_P, _P, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                   POINTER(c_double), POINTER(c_double), _P, _P, _P]),
+    "sim_apic_p2g": (c_int32, [_P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_apic_g2p": (c_int32, [_P, c_int64, _P, _P, _P, c_double, _P, _P, _P]),
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
     "sim_net_set_weights": (c_int32, [_P, _P, c_int64]),
     "sim_net_forward": (c_int32, [_P, _P, _P]),
@@ -276,6 +278,27 @@ class Sim:
         self._chk(lib().sim_loss_cos_l2(self.ctx, *map(_ptr, u), *map(_ptr, ref), float(alpha),
                                         float(beta), float(eps), w, byref(J), *map(_ptr, g)))
         return J.value, (g if want_grad else None)
+
+    def apic_p2g(self, x, vp, C, m, out=None, mass=None):
+        """The paper's particle-to-grid transfer: (grid velocity, grid masses).
+        x, vp: (P, 3); C: (P, 3, 3); m: (P,); float32 device tensors."""
+        out = out if out is not None else self.faces()
+        mass = mass if mass is not None else self.faces()
+        P = int(m.shape[0])
+        self._chk(lib().sim_apic_p2g(self.ctx, P, _ptr(x), _ptr(vp), _ptr(C), _ptr(m),
+                                     *map(_ptr, out), *map(_ptr, mass)))
+        return out, mass
+
+    def apic_g2p(self, grid, x, dt, vp=None, C=None):
+        """The paper's grid-to-particle transfer with the affine update; moves
+        x (in place) by dt times the new velocity.  Returns (vp, C)."""
+        t = self.torch
+        P = int(x.shape[0])
+        vp = vp if vp is not None else t.empty((P, 3), dtype=t.float32, device=self.device)
+        C = C if C is not None else t.empty((P, 3, 3), dtype=t.float32, device=self.device)
+        self._chk(lib().sim_apic_g2p(self.ctx, P, *map(_ptr, grid), float(dt), _ptr(x), _ptr(vp),
+                                     _ptr(C)))
+        return vp, C
 
     def op_advect(self, u, out=None):
         out = out if out is not None else self.faces()

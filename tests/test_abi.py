@@ -135,6 +135,8 @@ def test_null_arguments():
     assert L.sim_op_convection_grad_upwind(None, *([None] * 9)) == fsb.SIM_ERR_INVALID_ARG
     assert L.sim_loss_cos_l2(None, *([None] * 6), 1.0, 1.0, 0.0, None, None, None, None,
                              None) == fsb.SIM_ERR_INVALID_ARG
+    assert L.sim_apic_p2g(None, 0, *([None] * 10)) == fsb.SIM_ERR_INVALID_ARG
+    assert L.sim_apic_g2p(None, 0, None, None, None, 0.0, None, None, None) == fsb.SIM_ERR_INVALID_ARG
     assert fsb.lib().sim_last_error(None) == b"NULL context"
 
 

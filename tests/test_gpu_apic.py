@@ -1,0 +1,113 @@
+"""GPU parity of the paper's APIC transfers (sim_apic_p2g, sim_apic_g2p)
+against their FP64 oracle, and the affine round trip at 256^3.
+
+Skipped until the kernels' first parity run on a GPU: the kernels' index
+arithmetic has been checked against the oracle only in a CPU emulation so
+far."""
+import numpy as np
+import pytest
+
+from oracle import apic as orc_apic
+from oracle import fluid
+from paper_2503_00868_amd import inputs
+from tests.gpu_util import banner
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="APIC kernels not yet run on a GPU (first parity run pending)")]
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _sim(n):
+    from paper_2503_00868_amd.fluidsim import Sim
+    return Sim(inputs.gen_mask(n, 0), precond="jacobi")
+
+
+def _particles(n, P, rng, margin):
+    h = 1.0 / n
+    x = h * margin + (1.0 - 2 * h * margin) * rng.random((P, 3))
+    return x.astype(np.float32).astype(np.float64)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("n,P,margin", [(16, 4000, 0.3), (23, 6000, 1.0)])
+def test_p2g_matches_oracle(torch_gpu, n, P, margin):
+    t = torch_gpu
+    banner(f"APIC particles to grid n={n} P={P}")
+    rng = np.random.default_rng(n)
+    x = _particles(n, P, rng, margin)
+    vp = rng.standard_normal((P, 3)).astype(np.float32).astype(np.float64)
+    C = rng.standard_normal((P, 3, 3)).astype(np.float32).astype(np.float64)
+    m = (0.5 + rng.random(P)).astype(np.float32).astype(np.float64)
+    sim = _sim(n)
+    vel, mass = sim.apic_p2g(_dev(t, x), _dev(t, vp), _dev(t, C), _dev(t, m))
+    vr, mr = orc_apic.p2g(n, x, vp, C, m)
+    for a in range(3):
+        mg = mass[a].cpu().numpy().astype(np.float64)
+        vg = vel[a].cpu().numpy().astype(np.float64)
+        assert np.abs(mg - mr[a]).max() <= 1e-5 * mr[a].max()
+        # momentum, then the velocity where the mass is not tiny
+        assert np.abs(mg * vg - mr[a] * vr[a]).max() <= 1e-5 * np.abs(mr[a] * vr[a]).max()
+        big = mr[a] > 1e-3 * mr[a].max()
+        assert np.abs(vg[big] - vr[a][big]).max() <= 1e-3 * np.abs(vr[a]).max()
+        assert not np.any(vg[mr[a] == 0])
+
+
+@pytest.mark.parametrize("n,P", [(16, 3000), (23, 5000)])
+def test_g2p_matches_oracle(torch_gpu, n, P):
+    t = torch_gpu
+    banner(f"APIC grid to particles n={n} P={P}")
+    rng = np.random.default_rng(100 + n)
+    x = _particles(n, P, rng, 0.3)
+    grid = tuple(rng.standard_normal(fluid.face_shape(n, a)).astype(np.float32).astype(np.float64)
+                 for a in range(3))
+    sim = _sim(n)
+    X = _dev(t, x)
+    vp, C = sim.apic_g2p(tuple(_dev(t, g) for g in grid), X, 0.01)
+    vr, Cr = orc_apic.g2p(n, grid, x)
+    assert np.abs(vp.cpu().numpy() - vr).max() <= 1e-5 * np.abs(vr).max()
+    assert np.abs(C.cpu().numpy() - Cr).max() <= 1e-5 * np.abs(Cr).max()
+    xr = orc_apic.advect(x, vr, 0.01)
+    assert np.abs(X.cpu().numpy() - xr).max() <= 1e-6
+
+
+def test_affine_round_trip_full_size(torch_gpu):
+    """256^3, eight particles per liquid cell of the benchmark's mask carrying
+    v = A x + b with C = A: after particles to grid and back, v_p = A x_p + b
+    and C_p = A (exact in exact arithmetic at any size), and the grid masses
+    add up to the particles' mass."""
+    t = torch_gpu
+    n = 256
+    banner(f"APIC affine round trip n={n}")
+    rng = np.random.default_rng(7)
+    cell = inputs.gen_mask(n, 4)
+    k, j, i = np.nonzero(cell[1:-1, 1:-1, 1:-1] == fluid.LIQUID)
+    base = np.stack([i + 1, j + 1, k + 1], -1).astype(np.float64)
+    x = ((np.repeat(base, 8, 0) + rng.random((8 * len(base), 3))) / n).astype(np.float32)
+    A = (0.5 * rng.standard_normal((3, 3))).astype(np.float32)
+    b = rng.standard_normal(3).astype(np.float32)
+    X = _dev(t, x)
+    At, bt = _dev(t, A), _dev(t, b)
+    V = X @ At.T + bt
+    Cm = At.expand(X.shape[0], 3, 3).contiguous()
+    M = t.ones(X.shape[0], dtype=t.float32, device="cuda")
+    sim = _sim(n)
+    grid, mass = sim.apic_p2g(X, V, Cm, M)
+    for a in range(3):
+        assert abs(float(mass[a].double().sum()) - X.shape[0]) <= 1e-5 * X.shape[0]
+    X0 = X.clone()
+    vp, C = sim.apic_g2p(grid, X, 0.0)
+    ev = float((vp - (X0 @ At.T + bt)).abs().max())
+    eC = float((C - At).abs().max())
+    banner(f"  P={X.shape[0]}: max |v_p - (A x_p + b)| {ev:.2e}, max |C_p - A| {eC:.2e}")
+    assert ev <= 1e-4 * float(V.abs().max())
+    assert eC <= 1e-2 * float(At.abs().max())
+    assert t.equal(X, X0)
