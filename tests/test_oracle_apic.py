@@ -1,7 +1,8 @@
 """Pins for the APIC transfers' oracle: the quadratic B-spline's moments,
 brute-force particle-to-grid loops, mass and momentum conservation, the
 exact round trip of affine velocity fields (the property the affine part
-exists for), constant fields, and the particle move."""
+exists for), the first moments of the grid momentum, constant fields, and
+the particle move."""
 import numpy as np
 import pytest
 
@@ -112,3 +113,28 @@ def test_constant_field_and_move():
     assert np.abs(Cp).max() < 1e-11
     x2 = apic.advect(xp, vp, 0.01)
     assert np.abs(x2 - (xp + 0.01 * c)).max() < 1e-15
+
+
+def test_first_moments_of_momentum():
+    """sum_i m_i v_ai x_ib = sum_p m_p (v_pa x_pb + (h^2/4) C_p[a, b]) for all
+    components a and axes b (all stencils inside the lattices): the moments
+    behind APIC's conservation of angular momentum."""
+    n, P = 9, 250
+    rng = np.random.default_rng(11)
+    xp = _particles(n, P, rng)
+    vp = rng.standard_normal((P, 3))
+    Cp = rng.standard_normal((P, 3, 3))
+    mp = 0.5 + rng.random(P)
+    vel, mass = apic.p2g(n, xp, vp, Cp, mp)
+    h = 1.0 / n
+    for a in range(3):
+        shp = fluid.face_shape(n, a)
+        off = [0.5, 0.5, 0.5]
+        off[a] = 0.0
+        k, j, i = np.meshgrid(*[np.arange(s) for s in shp], indexing="ij")
+        pos = np.stack([(i + off[0]) * h, (j + off[1]) * h, (k + off[2]) * h], -1)
+        mom = mass[a] * vel[a]
+        for b in range(3):
+            grid = float((mom * pos[..., b]).sum())
+            part = float((mp * (vp[:, a] * xp[:, b] + 0.25 * h * h * Cp[:, a, b])).sum())
+            assert abs(grid - part) <= 1e-11 * max(1.0, abs(part)), (a, b, grid, part)
