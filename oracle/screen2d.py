@@ -112,3 +112,43 @@ def project(a, b, vz, z, mask):
     ga = (pa[:, 1:] - pa[:, :-1]) / du   # edge i between pixels i-1 and i
     gb = (pb[1:, :] - pb[:-1, :]) / dv
     return np.where(fa, a - ga, a), np.where(fb, b - gb, b), p
+
+
+def mainstream_fill(vel, detected, normal, radius):
+    """The paper's mainstream-guided interpolation (Section 3.3, the equation
+    before Eq. (div2DV)): for each pixel k where detection failed,
+    v_k = sum_{i in B(k)} w(i) max(0, n_k . v_i / |v_i|) v_i.
+
+    Reading R25: B(k) holds the detected pixels within Euclidean distance
+    `radius` (in pixels) of k; w(i) = 1 - d(i, k) / (radius + 1), normalised
+    to sum to 1 over B(k); a zero v_i contributes nothing; v_k = 0 when B(k)
+    is empty.  vel (H, W, 3) velocities in NDC space, detected (H, W) bool,
+    normal (H, W, 3) unit mainstream directions.  Detected pixels keep their
+    velocity."""
+    vel = np.asarray(vel, dtype=np.float64)
+    det = np.asarray(detected, dtype=bool)
+    nrm = np.asarray(normal, dtype=np.float64)
+    H, W, _ = vel.shape
+    r = int(radius)
+    mag = np.linalg.norm(vel, axis=-1)
+    unit = np.where(mag[..., None] > 0, vel / np.where(mag > 0, mag, 1.0)[..., None], 0.0)
+    num = np.zeros((H, W, 3))
+    wsum = np.zeros((H, W))
+    for dj in range(-r, r + 1):
+        for di in range(-r, r + 1):
+            d = np.hypot(dj, di)
+            if (dj == 0 and di == 0) or d > r:
+                continue
+            w = 1.0 - d / (r + 1)
+            # neighbour i = k + (dj, di), for every pixel k that has one in the image
+            kj = slice(max(0, -dj), min(H, H - dj))
+            ki = slice(max(0, -di), min(W, W - di))
+            nj = slice(max(0, dj), min(H, H + dj))
+            ni = slice(max(0, di), min(W, W + di))
+            ok = det[nj, ni]
+            cosv = np.maximum(0.0, (nrm[kj, ki] * unit[nj, ni]).sum(-1))
+            num[kj, ki] += (w * ok * cosv)[..., None] * vel[nj, ni]
+            wsum[kj, ki] += w * ok
+    fill = np.where(wsum[..., None] > 0, num / np.where(wsum > 0, wsum, 1.0)[..., None], 0.0)
+    return np.where(det[..., None], vel, fill)
+

@@ -103,3 +103,67 @@ def test_dense_brute_force():
     x = sol[:n]
     got = np.array([a2[j, i] if kk == "a" else b2[j, i] for kk, j, i in edges])
     assert np.abs(got - x).max() <= 1e-9 * max(1.0, np.abs(x).max())
+
+
+def _fill_loops(vel, det, nrm, r):
+    H, W, _ = vel.shape
+    out = vel.copy()
+    for j in range(H):
+        for i in range(W):
+            if det[j, i]:
+                continue
+            num = np.zeros(3)
+            den = 0.0
+            for jj in range(H):
+                for ii in range(W):
+                    d = np.hypot(jj - j, ii - i)
+                    if not det[jj, ii] or d > r or (jj == j and ii == i):
+                        continue
+                    w = 1.0 - d / (r + 1)
+                    v = vel[jj, ii]
+                    m = np.linalg.norm(v)
+                    c = max(0.0, float(nrm[j, i] @ v) / m) if m > 0 else 0.0
+                    num += w * c * v
+                    den += w
+            out[j, i] = num / den if den > 0 else 0.0
+    return out
+
+
+def _stream_case(H, W, seed):
+    rng = np.random.default_rng(seed)
+    vel = rng.standard_normal((H, W, 3))
+    det = rng.random((H, W)) < 0.5
+    n = rng.standard_normal((H, W, 3))
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    return vel, det, n
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_mainstream_fill_matches_loops(r):
+    vel, det, n = _stream_case(9, 11, r)
+    vel[2, 3] = 0.0  # a zero velocity contributes nothing
+    det[2, 3] = True
+    got = s2.mainstream_fill(vel, det, n, r)
+    assert np.abs(got - _fill_loops(vel, det, n, r)).max() < 1e-13
+
+
+def test_mainstream_fill_closed_forms():
+    """Neighbours all moving along the mainstream with speed V give V n;
+    neighbours against it or across it give 0; scaling every detected
+    velocity by c > 0 scales the fill by c."""
+    H, W, r = 8, 8, 2
+    det = np.ones((H, W), dtype=bool)
+    det[4, 4] = False
+    n = np.zeros((H, W, 3))
+    n[..., 0] = 1.0
+    vel = np.zeros((H, W, 3))
+    vel[..., 0] = 2.5
+    assert np.allclose(s2.mainstream_fill(vel, det, n, r)[4, 4], [2.5, 0.0, 0.0], atol=1e-14)
+    assert np.allclose(s2.mainstream_fill(-vel, det, n, r)[4, 4], 0.0)
+    across = np.zeros((H, W, 3))
+    across[..., 1] = 1.0
+    assert np.allclose(s2.mainstream_fill(across, det, n, r)[4, 4], 0.0)
+    vel2, det2, n2 = _stream_case(10, 10, 7)
+    a = s2.mainstream_fill(vel2, det2, n2, 2)
+    b = s2.mainstream_fill(3.0 * vel2, det2, n2, 2)
+    assert np.abs(b - 3.0 * a).max() < 1e-12
