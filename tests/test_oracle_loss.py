@@ -146,3 +146,36 @@ def test_gradient_matches_central_differences(eps):
         minus[c][idx] -= h
         fd = (orc_loss.loss(cell, plus, r, *args)[0] - orc_loss.loss(cell, minus, r, *args)[0]) / (2 * h)
         assert abs(fd - g[c][idx]) <= 1e-6 * max(1e-3, abs(fd)), (c, idx, fd, g[c][idx])
+
+
+def test_centre_velocity_of_a_linear_field_is_exact():
+    """Faces carrying a field linear in position, u_c = a_c + B[c] . x_face:
+    the mean of a cell's two c-faces is exactly a_c + B[c] . x_centre (a
+    linear function's value at the midpoint), so the L2 term against a zero
+    reference equals the closed-form sum of |a + B x_centre|^2 over the
+    weighted cells.  Averaging along the wrong axis, or a shifted index,
+    gives another value (B has entries along every axis)."""
+    n = 7
+    h = 1.0 / n
+    cell, _ = inputs.gen_case(n, 1)
+    cell = np.asarray(cell, np.uint8)
+    a = np.array([0.3, -0.2, 0.1])
+    B = np.array([[1.0, -0.5, 0.25], [0.75, 2.0, -1.0], [-0.3, 0.6, 1.5]])  # B[c][axis x, y, z]
+    sim = []
+    for c in range(3):
+        shp = fluid.face_shape(n, c)
+        k, j, i = np.meshgrid(*[np.arange(s) for s in shp], indexing="ij")
+        pos = [(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h]
+        pos[c] = (i, j, k)[c] * h  # the face sits on a cell boundary along its own axis
+        sim.append(a[c] + B[c, 0] * pos[0] + B[c, 1] * pos[1] + B[c, 2] * pos[2])
+    k, j, i = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    xc = np.stack([(i + 0.5) * h, (j + 0.5) * h, (k + 0.5) * h], -1)
+    vel = a + xc @ B.T  # exact centre velocity (n, n, n, 3)
+    assert np.abs(orc_loss.cell_vectors(sim) - vel).max() <= 1e-14
+    zero = tuple(np.zeros(fluid.face_shape(n, c)) for c in range(3))
+    weights = (0.2, 1.0, 2.0)
+    cls = orc_loss.classes(cell)
+    wt = np.choose(np.minimum(cls, 3), list(weights) + [0.0])
+    ref = float((wt * (vel * vel).sum(-1)).sum() / wt.sum())
+    J, _ = orc_loss.loss(cell, sim, zero, 0.0, 1.0, 0.0, weights)
+    assert abs(J - ref) <= 1e-13 * ref
