@@ -67,6 +67,7 @@ def lib():
             "orc_pcg": (_i, [_i, _U8, _D, _D, _i, _d, _i, _dp]),
             "orc_true_relres": (_d, [_i, _U8, _D, _D]),
             "orc_advect_adjoint": (None, [_i, _U8, _D, _D, _D, _d, _D, _D, _D, _D, _D, _D]),
+            "orc_advect_ddt": (None, [_i, _U8, _D, _D, _D, _d, _D, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -319,48 +320,87 @@ def advect_adjoint(cell, fields, dt, lam):
     return out
 
 
-def step_adjoint(cell, u_n, lam, nu, dt, g=GRAVITY, mode="auto", tol=1e-12):
-    """Reverse one step.  Given lam = dJ/du_{n+1}, returns (dJ/du_n, dJ/dnu
-    contribution).  The projection is a symmetric projector on the active
-    faces and the diffusion operator is symmetric, so each is its own
-    transpose; gravity adds a constant."""
+def advect_ddt(cell, fields, dt):
+    """d(advect(fields))/d(dt) per face: the departure point's motion with the
+    time step (active faces; zero elsewhere)."""
+    cell = _cell(cell)
+    n = _n(cell)
+    u, v, w = (_f64(f) for f in fields)
+    out = zeros_faces(n)
+    lib().orc_advect_ddt(n, cell, u, v, w, dt * n, *out)
+    return out
+
+
+def step_adjoint(cell, u_n, lam, nu, dt, g=GRAVITY, mode="auto", tol=1e-12, convection="exact"):
+    """Reverse one step.  Given lam = dJ/du_{n+1}, returns dJ/du_n and this
+    step's partial derivatives {"dnu", "ddt", "dg"} of J.
+
+    The projection is a symmetric projector on the active faces and the
+    diffusion operator is symmetric, so each is its own transpose.  The
+    scaled pressure does not depend on dt (R8).  dt enters the step three
+    times: the back-trace distance, the body-force increment dt*g on active
+    faces, and the viscous factor nu*dt (so the viscous part of dJ/ddt is
+    nu/dt times that of dJ/dnu).  convection="upwind" replaces the exact
+    transpose of the velocity dependence of advection by the paper's upwind
+    surrogate (Section 3.4.1; upwind.py); the dt and g derivatives are the
+    same in both modes."""
+    from . import upwind
     n = _n(_cell(cell))
+    g = tuple(float(x) for x in g)
     a = add_force(cell, advect(cell, u_n, dt), dt, g)
     explicit = diffusion_is_explicit(n, nu, dt, mode)
     lam1, _, _, _ = project(cell, lam, tol)
     if explicit:
         la = tuple(laplacian(cell, c, a[c]) for c in range(3))
-        dnu = dt * _dot(lam1, la)
+        visc = _dot(lam1, la)
         lam2, _, _ = diffuse(cell, lam1, nu, dt, "explicit")
     else:
         uss, _, _ = diffuse(cell, a, nu, dt, "implicit", tol)
         mu, _, _ = diffuse(cell, lam1, nu, dt, "implicit", tol)
         lu = tuple(laplacian(cell, c, uss[c]) for c in range(3))
-        dnu = dt * _dot(mu, lu)
+        visc = _dot(mu, lu)
         lam2 = mu
     lam3 = mask_faces(cell, lam2)
-    return advect_adjoint(cell, u_n, dt, lam3), dnu
+    lsum = [float(l.sum()) for l in lam3]  # lam3 is zero off the active faces
+    parts = {
+        "dnu": dt * visc,
+        "dg": np.array([dt * x for x in lsum]),
+        "ddt": nu * visc + sum(gc * x for gc, x in zip(g, lsum))
+        + _dot(lam3, advect_ddt(cell, u_n, dt)),
+    }
+    if convection == "exact":
+        lam_n = advect_adjoint(cell, u_n, dt, lam3)
+    elif convection == "upwind":
+        lam_n = upwind.gradient(cell, u_n, lam3, dt)
+    else:
+        raise ValueError("convection must be 'exact' or 'upwind'")
+    return lam_n, parts
 
 
-def rollout_grad(cell, u_gen, nu, s, steps, dt, target, g=GRAVITY, mode="auto", tol=1e-12):
-    """Loss and its exact discrete gradient.
+def rollout_grad(cell, u_gen, nu, s, steps, dt, target, g=GRAVITY, mode="auto", tol=1e-12,
+                 convection="exact"):
+    """Loss and its gradient (the exact discrete one, or with the paper's
+    upwind convection surrogate).
 
-    Returns dict with J, dJ/dnu, dJ/ds, dJ/du_gen, and the gradients in the
-    normalised parameters theta_nu = log nu, theta_s = log s (exponential
-    activation, Section 3.4.2)."""
+    Returns a dict with J, dJ/dnu, dJ/ds, dJ/ddt, dJ/dg (3), dJ/du_gen, and
+    the gradients in the normalised parameters theta_nu = log nu, theta_s =
+    log s, theta_dt = log dt (exponential activation, Section 3.4.2)."""
     states = rollout(cell, u_gen, nu, s, steps, dt, g, mode, tol)
     J = loss(cell, states[-1], target)
     lam = loss_grad(cell, states[-1], target)
-    dnu = 0.0
+    dnu, ddt, dg = 0.0, 0.0, np.zeros(3)
     for t in range(steps - 1, -1, -1):
-        lam, dn = step_adjoint(cell, states[t], lam, nu, dt, g, mode, tol)
-        dnu += dn
+        lam, parts = step_adjoint(cell, states[t], lam, nu, dt, g, mode, tol, convection)
+        dnu += parts["dnu"]
+        ddt += parts["ddt"]
+        dg = dg + parts["dg"]
     lam0 = mask_faces(cell, lam)
     ugm = mask_faces(cell, u_gen)
     ds = _dot(lam0, ugm)
     dug = tuple(s * l for l in lam0)
-    return {"J": J, "dnu": dnu, "ds": ds, "du_gen": dug,
-            "dtheta_nu": nu * dnu, "dtheta_s": s * ds, "uT": states[-1]}
+    return {"J": J, "dnu": dnu, "ds": ds, "ddt": ddt, "dg": dg, "du_gen": dug,
+            "dtheta_nu": nu * dnu, "dtheta_s": s * ds, "dtheta_dt": dt * ddt,
+            "uT": states[-1]}
 
 
 def max_abs_divergence(cell, fields):

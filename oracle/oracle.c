@@ -198,6 +198,40 @@ void orc_advect(int n, const uint8_t* cell, const double* u, const double* v, co
     }
 }
 
+/* Derivative of the advected value of every active face with respect to the
+ * time step (the advection's own dependence on dt; the body force is
+ * separate).  The departure point x_d = x_f - dt U(x_f) moves by -U(x_f) per
+ * unit of dt, so d a_f / d dt = -grad I_c(x_d) . U(x_f).  In grid units
+ * (X = x / h) the sample gradient is per cell and dX_d / d dt = -U / h.
+ * Non-active faces get zero. */
+void orc_advect_ddt(int n, const uint8_t* cell, const double* u, const double* v, const double* w,
+                    double dt_over_h, double* du, double* dv, double* dw) {
+    for (int comp = 0; comp < 3; ++comp) {
+        int d[3];
+        face_dims(n, comp, d);
+        const double* src = pick(comp, u, v, w);
+        double* dst = comp == 0 ? du : (comp == 1 ? dv : dw);
+        for (int k = 0; k < d[2]; ++k)
+            for (int j = 0; j < d[1]; ++j)
+                for (int i = 0; i < d[0]; ++i) {
+                    long id = fidx(d, i, j, k);
+                    dst[id] = 0.0;
+                    if (face_class(n, cell, comp, i, j, k) != ORC_ACTIVE) continue;
+                    double gf[3] = {i + (comp == 0 ? 0.0 : 0.5), j + (comp == 1 ? 0.0 : 0.5),
+                                    k + (comp == 2 ? 0.0 : 0.5)};
+                    double U[3];
+                    for (int a = 0; a < 3; ++a) U[a] = orc_sample(n, a, pick(a, u, v, w), gf, NULL);
+                    double gd[3];
+                    for (int a = 0; a < 3; ++a) gd[a] = gf[a] - dt_over_h * U[a];
+                    double grad[3];
+                    orc_sample(n, comp, src, gd, grad);
+                    double s = 0.0;
+                    for (int a = 0; a < 3; ++a) s -= grad[a] * U[a] * (double)n;
+                    dst[id] = s;
+                }
+    }
+}
+
 /* Body force applied explicitly on active faces (Section 3.2.2). */
 void orc_add_force(int n, const uint8_t* cell, double* u, double* v, double* w, double dt,
                    const double g[3]) {

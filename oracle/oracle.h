@@ -37,6 +37,9 @@ double orc_sample(int n, int comp, const double* f, const double g[3], double gr
 
 void orc_advect(int n, const uint8_t* cell, const double* u, const double* v, const double* w,
                 double dt_over_h, double* au, double* av, double* aw);
+/* d(advected face value)/d(dt) on active faces (0 elsewhere) */
+void orc_advect_ddt(int n, const uint8_t* cell, const double* u, const double* v, const double* w,
+                    double dt_over_h, double* du, double* dv, double* dw);
 void orc_add_force(int n, const uint8_t* cell, double* u, double* v, double* w,
                    double dt, const double g[3]);
 void orc_laplacian(int n, const uint8_t* cell, int comp, const double* f, double* out);
