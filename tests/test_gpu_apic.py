@@ -1,9 +1,5 @@
 """GPU parity of the paper's APIC transfers (sim_apic_p2g, sim_apic_g2p)
-against their FP64 oracle, and the affine round trip at 256^3.
-
-Skipped until the kernels' first parity run on a GPU: the kernels' index
-arithmetic has been checked against the oracle only in a CPU emulation so
-far."""
+against their FP64 oracle, and the affine round trip at 256^3."""
 import numpy as np
 import pytest
 
@@ -12,8 +8,7 @@ from oracle import fluid
 from paper_2503_00868_amd import inputs
 from tests.gpu_util import banner
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="APIC kernels not yet run on a GPU (first parity run pending)")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")

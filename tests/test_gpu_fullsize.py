@@ -70,12 +70,22 @@ def test_fullsize_advect_and_viscosity(torch_gpu, orc, full_case):
         assert mx < 2e-6, (l2, mx)
 
 
-def test_fullsize_projection_properties(torch_gpu, orc, full_case):
-    banner("256^3 projection: residual, update and divergence from the GPU pressure")
+@pytest.mark.parametrize("precond", ["jacobi", "learned"])
+def test_fullsize_projection_properties(torch_gpu, orc, full_case, precond):
+    """With "learned", the benchmark's flexible CG with the committed network
+    (FP64 check every 4 iterations), whose own residual check the oracle
+    recomputes here."""
+    banner(f"256^3 projection ({precond}): residual, update and divergence from the GPU pressure")
     cell, _, u0 = full_case
     u = orc.add_force(cell, orc.advect(cell, u0, DT), DT)
     u = tuple(x.astype(np.float32).astype(np.float64) for x in u)
-    sim = _sim(cell)
+    if precond == "learned":
+        from paper_2503_00868_amd import unet as net_weights
+        from paper_2503_00868_amd.train import DEFAULT_WEIGHTS
+        sim = _sim(cell, precond="learned", check_every=4)
+        sim.net_set_weights(net_weights.load_weights(DEFAULT_WEIGHTS, device="cuda"))
+    else:
+        sim = _sim(cell)
     U = sim.to_faces(u)
     st, p = sim.project(U, want_p=True)
     assert st["rel_residual"] <= 1e-6
@@ -91,8 +101,11 @@ def test_fullsize_projection_properties(torch_gpu, orc, full_case):
     # what remains of the divergence is the solve's residual (plus FP32 rounding)
     b_out = orc.divergence_rhs(cell, got)
     ratio = np.linalg.norm(b_out) / np.linalg.norm(b)
-    banner(f"  {st['iters']} iterations, residual {relres:.2e}, divergence ratio {ratio:.2e}")
+    banner(f"  {st['iters']} iterations (fallback {st['fallback_used']}), residual {relres:.2e}, "
+           f"divergence ratio {ratio:.2e}")
     assert ratio < 1e-5
+    if precond == "learned":
+        assert st["fallback_used"] == 0 and st["iters"] < 200
 
 
 def test_fullsize_rollout_stats_and_gradient_fd(torch_gpu, full_case):

@@ -140,3 +140,39 @@ def test_backward_requires_recording(torch_gpu, orc):
     with pytest.raises(FluidSimError) as e:
         sim.backward(sim.faces())
     assert e.value.code == SIM_ERR_STATE
+
+
+@pytest.mark.parametrize("n,warm", [(16, False), (16, True), (32, True)])
+def test_learned_gradient_matches_oracle(torch_gpu, orc, n, warm):
+    """The benchmark's preconditioner in both directions: the forward and the
+    adjoint projections run flexible CG with the committed network (its
+    Jacobi-PCG restart included), to 1e-9.  The gradient must still be the
+    oracle's exact discrete one to 1e-4, since every solve meets the same
+    residual test whatever the preconditioner."""
+    torch = torch_gpu
+    from paper_2503_00868_amd import unet as net_weights
+    from paper_2503_00868_amd.autograd import mse_loss, rollout
+    from paper_2503_00868_amd.fluidsim import Sim
+    from paper_2503_00868_amd.train import DEFAULT_WEIGHTS
+    banner(f"gradient {n}^3 learned preconditioner warm={warm}")
+    steps, K, nu_t, nu_e, s_t, s_e = 5, 2, 4e-3, 2e-3, 1.2, 0.8
+    cell, ug = case(n, 100, 2.0)
+    target = orc.rollout(cell, ug, nu_t, s_t, steps, DT, mode="explicit", tol=1e-12)[-1]
+    ref = orc.rollout_grad(cell, ug, nu_e, s_e, steps, DT, target, mode="explicit", tol=1e-12)
+    sim = Sim(cell, precond="learned", diffusion="explicit", tol=1e-9, check_every=4,
+              max_steps=steps, checkpoint_every=K, warm_start=warm)
+    sim.net_set_weights(net_weights.load_weights(DEFAULT_WEIGHTS, device="cuda"))
+    th_nu = torch.tensor(math.log(nu_e), dtype=torch.float64, requires_grad=True)
+    th_s = torch.tensor(math.log(s_e), dtype=torch.float64, requires_grad=True)
+    ugen = tuple(t.requires_grad_(True) for t in sim.to_faces(ug))
+    uT = rollout(th_nu, th_s, ugen, sim, steps, DT)
+    J = mse_loss(sim, uT, sim.to_faces(target))
+    J.backward()
+    banner(f"  J {J.item():.6e} vs {ref['J']:.6e}; dth_nu {th_nu.grad.item():.6e} vs "
+           f"{ref['dtheta_nu']:.6e}; dth_s {th_s.grad.item():.6e} vs {ref['dtheta_s']:.6e}")
+    assert abs(J.item() - ref["J"]) <= 1e-4 * ref["J"]
+    for got, want, name in ((th_nu.grad.item(), ref["dtheta_nu"], "nu"),
+                            (th_s.grad.item(), ref["dtheta_s"], "s")):
+        assert abs(got - want) <= 1e-4 * abs(want), (name, got, want)
+    l2, mx = rel_err(to_np(tuple(t.grad for t in ugen)), ref["du_gen"])
+    assert l2 <= 1e-4, (l2, mx)
