@@ -66,6 +66,10 @@ enum {
 
 enum { SIM_PRECOND_JACOBI = 0, SIM_PRECOND_MIC0 = 1, SIM_PRECOND_LEARNED = 2 };
 enum { SIM_DIFFUSION_AUTO = 0, SIM_DIFFUSION_EXPLICIT = 1, SIM_DIFFUSION_IMPLICIT = 2 };
+/* Transpose of the advection's velocity dependence in sim_backward: the
+ * exact discrete one, or the paper's upwind analytic surrogate of the
+ * convection gradient (Section 3.4.1; sim_op_convection_grad_upwind). */
+enum { SIM_CONVGRAD_EXACT = 0, SIM_CONVGRAD_UPWIND = 1 };
 
 /* Static configuration, fixed for the life of a context. */
 typedef struct {
@@ -95,6 +99,9 @@ typedef struct {
                                   recompute then starts every projection from the stored
                                   pressure (the solve stops at its first check with no
                                   iteration) and takes the viscosity output as stored */
+    int32_t convection_grad;   /* SIM_CONVGRAD_*: what sim_backward takes for the transpose of
+                                  the advection's dependence on the velocity (the derivatives
+                                  in dt and gravity are the exact ones in both modes) */
 } sim_desc;
 
 /* Dynamic parameters (sim_set_params).  Density is 1: the solver works with
@@ -130,7 +137,9 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
                size_t workspace_bytes, void* hip_stream, sim_ctx** out);
 
 /* Set nu, s, dt and gravity; host only, checks ranges.  Required before
- * sim_step / sim_init_state / sim_backward. */
+ * sim_step / sim_init_state / sim_backward.  Forgets any recorded rollout
+ * (it ran with the previous parameters): sim_backward then returns
+ * SIM_ERR_STATE until sim_step records again. */
 int sim_set_params(sim_ctx* ctx, const sim_params* params);
 
 /* u0 = s * ugen on active faces, 0 elsewhere (the fitted initial velocity
@@ -151,11 +160,17 @@ int sim_step(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, int32_t nsteps, i
 int sim_project(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, double* d_p_out,
                 sim_stats* h_stats);
 
-/* Reverse-mode gradient of the last recorded rollout.  In: dJ/du_T
- * (d_gu, d_gv, d_gw).  Out: (d_gu0, d_gv0, d_gw0) = dJ/du0 on active faces, or
- * dJ/dugen = s * dJ/du0 when d_ugen_* are given (the same ugen that
- * sim_init_state used).  h_grad[0] = dJ/dnu; h_grad[1] = dJ/ds (0 when ugen
- * is NULL).  h_stats (nullable) receives one entry with the summed iterations. */
+/* Reverse-mode gradient of the last recorded rollout (Section 3.4.2: the
+ * gradients of the loss with respect to the simulation parameters).  In:
+ * dJ/du_T (d_gu, d_gv, d_gw).  Out: (d_gu0, d_gv0, d_gw0) = dJ/du0 on active
+ * faces, or dJ/dugen = s * dJ/du0 when d_ugen_* are given (the same ugen that
+ * sim_init_state used).  h_grad (host, 6 doubles): [0] dJ/dnu, [1] dJ/ds (0
+ * when ugen is NULL), [2] dJ/ddt (the back-trace distance, the body-force
+ * increment dt*g and the viscous factor nu*dt; the scaled pressure does not
+ * depend on dt), [3..5] dJ/dgravity.  The transpose of the advection is the
+ * one desc.convection_grad selects.  h_stats (nullable) receives one entry
+ * with the summed iterations.  SIM_ERR_STATE without a recorded rollout (or
+ * after sim_set_params). */
 int sim_backward(sim_ctx* ctx, const float* d_gu, const float* d_gv, const float* d_gw,
                  const float* d_ugen_u, const float* d_ugen_v, const float* d_ugen_w,
                  float* d_gu0, float* d_gv0, float* d_gw0, double* h_grad, sim_stats* h_stats);

@@ -33,6 +33,10 @@ enum ScalarSlot {
   S_ALPHA_Q0,    // alphas of the first three iterations of a four-step iterate update
   S_ALPHA_Q1,
   S_ALPHA_Q2,
+  S_ADV_DT,      // backward: sum over steps of <lam, d advect / d dt> (departure-point motion)
+  S_LSUM0,       //   sums over steps of the adjoint at the body force, per component
+  S_LSUM1,       //   (active faces): dJ/dg_c = dt * S_LSUMc
+  S_LSUM2,
   S_COUNT = 32
 };
 enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };
@@ -59,6 +63,7 @@ enum FinMode : int {
   FIN_FCG_BETA,      // [zq]          -> BETA = -zq / DQ
   FIN_DCG_INIT,      // [bb, rz, rr]  -> BB, RZ, RZ_PREV, RR, BETA = 0; done at tol
   FIN_SLOT,          // [v]           -> scal[slot] = (acc ? scal[slot] : 0) + scale * v
+  FIN_SLOTS4,        // [v0..v3]      -> scal[slot + q] = (acc ? scal[slot + q] : 0) + scale * vq
 };
 
 }  // namespace fs
@@ -198,7 +203,16 @@ void launch_dcg_check(sim_ctx* c, float alpha, double tol);
 void launch_dcg_finish(sim_ctx* c, F3 out);
 
 // adjoint and loss
-void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth);
+// Adds (d advect / d u)^T lam to g (scatter = true; g is not touched when
+// false) and accumulates into scal[S_ADV_DT] the sum over active faces of
+// lam * d advect / d dt, and into scal[S_LSUM0 + c] the sum of lam over the
+// active c-faces (accumulate = 0 first clears the four slots).
+void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth, bool scatter,
+                           int accumulate);
+// The paper's upwind convection surrogate of the advection adjoint: g =
+// lam - dt sum_c Lam_c D_i V_c on active faces (0 elsewhere), v the
+// convected field (upwind.hip).
+void launch_convection_grad_upwind(sim_ctx* c, CF3 v, CF3 lam, F3 g);
 void launch_zero_faces(sim_ctx* c, F3 out);
 // scal[slot] = (accumulate ? scal[slot] : 0) + scale * <a, L y>
 void launch_dot_lap(sim_ctx* c, CF3 a, CF3 y, int slot, double scale, int accumulate);

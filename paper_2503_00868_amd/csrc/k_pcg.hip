@@ -107,10 +107,10 @@ __global__ void __launch_bounds__(kBlock)
   const bool in_loop = mode == FIN_DQ || mode == FIN_RZ_UPD || mode == FIN_RZ_FIRST ||
                        mode == FIN_CHECK || mode == FIN_FCG_DQDR || mode == FIN_FCG_BETA;
   if (in_loop && flags[F_DONE]) return;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kBlock)
     for (int q = 0; q < nv; ++q) v[q] += partials[(int64_t)b * nv + q];
-  block_sum<3>(v);
+  block_sum<4>(v);
   if (threadIdx.x != 0) return;
   switch (mode) {
     case FIN_PCG_INIT:
@@ -179,6 +179,9 @@ __global__ void __launch_bounds__(kBlock)
       break;
     case FIN_SLOT:
       scal[slot] = (acc ? scal[slot] : 0.0) + scale * v[0];
+      break;
+    case FIN_SLOTS4:
+      for (int q = 0; q < 4; ++q) scal[slot + q] = (acc ? scal[slot + q] : 0.0) + scale * v[q];
       break;
   }
 }

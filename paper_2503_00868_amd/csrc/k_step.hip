@@ -493,14 +493,24 @@ __device__ inline void sample3_grad(const float* __restrict__ f, Dims d, int i, 
   g[2] = cz ? 0.f : gz;
 }
 
+// One thread per face.  With SCATTER the transpose above is scattered into
+// g; in both forms the thread adds, in FP64, lam times the derivative of its
+// advected value with respect to dt (the departure point moves by -U per
+// unit dt: -n grad I . U in lattice units) and lam itself (the body force
+// dt * g_c is added to every active face), for the block partials
+// [dt term, lam sum of component 0, 1, 2].
+template <bool SCATTER>
 __global__ void __launch_bounds__(kBlock)
     k_advect_adjoint(int n, const uint8_t* __restrict__ fcode, CF3 u, CF3 lam, F3 g, float dth,
-                     int64_t F) {
+                     int64_t F, double* partials) {
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
   const Dims dd[3] = {face_dims(n, 0), face_dims(n, 1), face_dims(n, 2)};
   const uint8_t* __restrict__ code = fcode + comp * F;
-  const Chunk ch = block_chunk(F, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const Chunk ch = block_chunk(F, gridDim.x, lb);
+  const float fn = (float)n;
+  double acc_dt = 0.0, acc_l = 0.0;
   Walker w;
   w.init(d, ch.begin + threadIdx.x, kBlock);
   for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
@@ -519,20 +529,32 @@ __global__ void __launch_bounds__(kBlock)
     const float rx = -dth * U[0], ry = -dth * U[1], rz = -dth * U[2];
     float grad[3];
     sample3_grad(u.c[comp], d, w.i, w.j, w.k, rx, ry, rz, grad);
-    scatter3(g.c[comp], d, w.i, w.j, w.k, rx, ry, rz, l);
+    acc_l += (double)l;
+    acc_dt -= (double)l * (double)(fn * (grad[0] * U[0] + grad[1] * U[1] + grad[2] * U[2]));
+    if (SCATTER) {
+      scatter3(g.c[comp], d, w.i, w.j, w.k, rx, ry, rz, l);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float s = l * (-dth) * grad[a];
-      if (s != 0.f) scatter3(g.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2], s);
+      for (int a = 0; a < 3; ++a) {
+        const float s = l * (-dth) * grad[a];
+        if (s != 0.f) scatter3(g.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2], s);
+      }
     }
   }
+  double v[4] = {acc_dt, comp == 0 ? acc_l : 0.0, comp == 1 ? acc_l : 0.0, comp == 2 ? acc_l : 0.0};
+  store_partials<4>(v, partials, comp * gridDim.x + lb);
 }
 
-void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth) {
+void launch_advect_adjoint(sim_ctx* c, CF3 u, CF3 lam, F3 g, float dth, bool scatter,
+                           int accumulate) {
   prof_mark(c, SIM_KERN_ADVECT_ADJOINT, true);
-  hipLaunchKernelGGL(k_advect_adjoint, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->n,
-                     c->fcode, u, lam, g, dth, c->F);
+  if (scatter)
+    hipLaunchKernelGGL(k_advect_adjoint<true>, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream,
+                       c->n, c->fcode, u, lam, g, dth, c->F, c->partials);
+  else
+    hipLaunchKernelGGL(k_advect_adjoint<false>, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream,
+                       c->n, c->fcode, u, lam, g, dth, c->F, c->partials);
   prof_mark(c, SIM_KERN_ADVECT_ADJOINT, false);
+  launch_finalize(c, 3 * c->grid_faces, 4, FIN_SLOTS4, 0.0, 0, S_ADV_DT, 1.0, accumulate);
 }
 
 }  // namespace fs

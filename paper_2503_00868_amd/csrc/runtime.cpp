@@ -182,6 +182,8 @@ const char* validate_desc(const sim_desc* d) {
   if (d->warm_start != 0 && d->warm_start != 1) return "warm_start must be 0 or 1";
   if (d->store_pressures != 0 && d->store_pressures != 1) return "store_pressures must be 0 or 1";
   if (d->store_pressures && d->max_steps == 0) return "store_pressures needs max_steps > 0";
+  if (d->convection_grad != SIM_CONVGRAD_EXACT && d->convection_grad != SIM_CONVGRAD_UPWIND)
+    return "convection_grad must be EXACT or UPWIND";
   return nullptr;
 }
 
@@ -757,6 +759,8 @@ int sim_set_params(sim_ctx* c, const sim_params* p) {
     }
   c->params = *p;
   c->params_set = 1;
+  // a recorded rollout belongs to the parameters it ran with
+  c->recorded = 0;
   return SIM_OK;
 }
 
@@ -860,7 +864,10 @@ int sim_loss_mse(sim_ctx* c, const float* u, const float* v, const float* w, con
 //   lam1 = P lam                        (projection is a symmetric projector)
 //   explicit: dJ/dnu += dt <lam1, L a>,   lam2 = (I + nu dt L) lam1
 //   implicit: mu = (I - nu dt L)^-1 lam1, dJ/dnu += dt <mu, L u**>, lam2 = mu
-//   lam = (d advect / d u)^T lam2       (gravity adds a constant)
+//   lam = (d advect / d u)^T lam2, or the paper's upwind surrogate of it
+//   dJ/dg_c += dt sum_{active c-faces} lam2;  dJ/ddt += <lam2, d advect / d dt>
+//                                                     + g . (those sums)
+// and at the end dJ/ddt += (nu / dt) dJ/dnu (the viscous factor is nu dt).
 int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, const float* ugu,
                  const float* ugv, const float* ugw, float* g0u, float* g0v, float* g0w,
                  double* h_grad, sim_stats* stats) {
@@ -887,8 +894,10 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
   F3 lam2 = stacked(c, c->lam2);
   sim_stats st{};
   int worst = SIM_OK;
+  const bool upwind = c->desc.convection_grad == SIM_CONVGRAD_UPWIND;
   launch_copy_faces(c, cf3(gu, gv, gw), lam);
   HIPCHK(hipMemsetAsync(c->scal + S_DOT1, 0, sizeof(double), c->stream));
+  HIPCHK(hipMemsetAsync(c->scal + S_ADV_DT, 0, 4 * sizeof(double), c->stream));
   if (c->xwa) HIPCHK(hipMemsetAsync(c->xwa, 0, sizeof(double) * c->C, c->stream));
   for (int s0 = ((T - 1) / K) * K; T > 0 && s0 >= 0; s0 -= K) {
     const int s1 = std::min(s0 + K, T);
@@ -953,9 +962,16 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
         launch_dot_lap(c, cstacked(c, c->lam2), cf3(op.c[0], op.c[1], op.c[2]), S_DOT1,
                        c->params.dt, 1);
       }
-      launch_zero_faces(c, lam);
-      launch_advect_adjoint(c, cf3(us.c[0], us.c[1], us.c[2]), cstacked(c, c->lam2), lam,
-                            (float)(c->params.dt * c->n));
+      const float dth = (float)(c->params.dt * c->n);
+      if (upwind) {
+        launch_convection_grad_upwind(c, cf3(us.c[0], us.c[1], us.c[2]), cstacked(c, c->lam2), lam);
+        launch_advect_adjoint(c, cf3(us.c[0], us.c[1], us.c[2]), cstacked(c, c->lam2), lam, dth,
+                              false, 1);
+      } else {
+        launch_zero_faces(c, lam);
+        launch_advect_adjoint(c, cf3(us.c[0], us.c[1], us.c[2]), cstacked(c, c->lam2), lam, dth,
+                              true, 1);
+      }
       rc = launch_status(c);
       if (rc) return rc;
     }
@@ -971,12 +987,17 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
   }
   int rc = launch_status(c);
   if (rc) return rc;
-  double host[3];
-  HIPCHK(hipMemcpyAsync(host, c->scal + S_DOT0, 3 * sizeof(double), hipMemcpyDeviceToHost,
-                        c->stream));
+  double host[S_LSUM2 + 1];
+  HIPCHK(hipMemcpyAsync(host, c->scal, sizeof host, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  h_grad[0] = host[1];
-  h_grad[1] = host[2];
+  const double dt = c->params.dt, dnu = host[S_DOT1];
+  h_grad[0] = dnu;
+  h_grad[1] = host[S_DOT2];
+  h_grad[2] = host[S_ADV_DT] + (c->params.nu / dt) * dnu;
+  for (int a = 0; a < 3; ++a) {
+    h_grad[2] += c->params.gravity[a] * host[S_LSUM0 + a];
+    h_grad[3 + a] = dt * host[S_LSUM0 + a];
+  }
   st.status = worst;
   if (stats) *stats = st;
   return worst;
@@ -1170,7 +1191,7 @@ int sim_op_advect_adjoint(sim_ctx* c, const float* u, const float* v, const floa
     return SIM_ERR_INVALID_ARG;
   }
   launch_advect_adjoint(c, cf3(u, v, w), cf3(lu, lv, lw), f3(g0, g1, g2),
-                        (float)(c->params.dt * c->n));
+                        (float)(c->params.dt * c->n), true, 0);
   return launch_status(c);
 }
 

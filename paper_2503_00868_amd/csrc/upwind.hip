@@ -100,6 +100,13 @@ __global__ void __launch_bounds__(kBlock)
     upwind_faces<2>(n, fcode + 2 * F, v, lam, dt_over_h, g2);
 }
 
+void launch_convection_grad_upwind(sim_ctx* c, CF3 v, CF3 lam, F3 g) {
+  UpFaces fv{{v.c[0], v.c[1], v.c[2]}}, fl{{lam.c[0], lam.c[1], lam.c[2]}};
+  hipLaunchKernelGGL(k_convection_grad_upwind, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream,
+                     c->n, c->F, c->fcode, fv, fl, (float)(c->params.dt * c->n), g.c[0], g.c[1],
+                     g.c[2]);
+}
+
 }  // namespace fs
 
 using namespace fs;
@@ -120,8 +127,6 @@ extern "C" int sim_op_convection_grad_upwind(sim_ctx* c, const float* u, const f
         c->err = "sim_op_convection_grad_upwind: an output aliases an input";
         return SIM_ERR_INVALID_ARG;
       }
-  UpFaces fv{{u, v, w}}, fl{{lu, lv, lw}};
-  hipLaunchKernelGGL(k_convection_grad_upwind, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream,
-                     c->n, c->F, c->fcode, fv, fl, (float)(c->params.dt * c->n), g0, g1, g2);
+  launch_convection_grad_upwind(c, CF3{{u, v, w}}, CF3{{lu, lv, lw}}, F3{{g0, g1, g2}});
   return hipGetLastError() == hipSuccess ? SIM_OK : SIM_ERR_HIP;
 }

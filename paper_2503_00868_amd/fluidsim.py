@@ -31,7 +31,10 @@ KERNEL_KINDS = ["pcg_dir_spmv", "pcg_update", "pcg_check", "advect", "diffuse_ex
                 "percnn_adj"]
 SIM_DIFFUSION_AUTO, SIM_DIFFUSION_EXPLICIT, SIM_DIFFUSION_IMPLICIT = 0, 1, 2
 
+SIM_CONVGRAD_EXACT, SIM_CONVGRAD_UPWIND = 0, 1
+
 PRECONDS = {"jacobi": SIM_PRECOND_JACOBI, "mic0": SIM_PRECOND_MIC0, "learned": SIM_PRECOND_LEARNED}
+CONVGRADS = {"exact": SIM_CONVGRAD_EXACT, "upwind": SIM_CONVGRAD_UPWIND}
 DIFFUSIONS = {"auto": SIM_DIFFUSION_AUTO, "explicit": SIM_DIFFUSION_EXPLICIT,
               "implicit": SIM_DIFFUSION_IMPLICIT}
 
@@ -40,7 +43,8 @@ class sim_desc(ctypes.Structure):
     _fields_ = [("n", c_int32), ("precond", c_int32), ("diffusion", c_int32),
                 ("max_iter", c_int32), ("check_every", c_int32), ("checkpoint_every", c_int32),
                 ("max_steps", c_int32), ("learned_max_iter", c_int32), ("tol", c_double),
-                ("diff_tol", c_double), ("warm_start", c_int32), ("store_pressures", c_int32)]
+                ("diff_tol", c_double), ("warm_start", c_int32), ("store_pressures", c_int32),
+                ("convection_grad", c_int32)]
 
 
 class sim_params(ctypes.Structure):
@@ -160,13 +164,15 @@ def sim_create(desc: sim_desc, cell_host: np.ndarray, workspace, stream_handle: 
 
 def make_desc(n, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6, max_iter=20000,
               check_every=8, checkpoint_every=8, max_steps=0, learned_max_iter=200,
-              warm_start=False, store_pressures=False):
+              warm_start=False, store_pressures=False, convection_grad="exact"):
     return sim_desc(n=n, precond=PRECONDS[precond] if isinstance(precond, str) else precond,
                     diffusion=DIFFUSIONS[diffusion] if isinstance(diffusion, str) else diffusion,
                     max_iter=max_iter, check_every=check_every, checkpoint_every=checkpoint_every,
                     max_steps=max_steps, learned_max_iter=learned_max_iter, tol=tol,
                     diff_tol=diff_tol, warm_start=int(bool(warm_start)),
-                    store_pressures=int(bool(store_pressures)))
+                    store_pressures=int(bool(store_pressures)),
+                    convection_grad=(CONVGRADS[convection_grad] if isinstance(convection_grad, str)
+                                     else convection_grad))
 
 
 def face_shapes(n):
@@ -179,7 +185,8 @@ class Sim:
 
     def __init__(self, cell, precond="jacobi", diffusion="auto", tol=1e-6, diff_tol=1e-6,
                  max_iter=20000, check_every=8, checkpoint_every=8, max_steps=0,
-                 learned_max_iter=200, warm_start=False, store_pressures=False, device="cuda"):
+                 learned_max_iter=200, warm_start=False, store_pressures=False,
+                 convection_grad="exact", device="cuda"):
         import torch
         self.torch = torch
         cell = np.ascontiguousarray(cell, dtype=np.uint8)
@@ -187,7 +194,7 @@ class Sim:
         self.device = torch.device(device)
         self.desc = make_desc(n, precond, diffusion, tol, diff_tol, max_iter, check_every,
                               checkpoint_every, max_steps, learned_max_iter, warm_start,
-                              store_pressures)
+                              store_pressures, convection_grad)
         size = sim_workspace_size(self.desc)
         self.ws = torch.empty(size, dtype=torch.uint8, device=self.device)
         assert self.ws.data_ptr() % 256 == 0
@@ -195,6 +202,10 @@ class Sim:
         self.ctx = sim_create(self.desc, cell, self.ws, self.stream.cuda_stream)
         self.cell = cell
         self.params = None
+        # bumped by every recorded rollout and every set_params (which makes
+        # the library forget its recording): a backward can tell whether the
+        # recording it needs is still the current one
+        self.record_gen = 0
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -233,6 +244,7 @@ class Sim:
         p = sim_params(nu=nu, s=s, dt=dt, gravity=(c_double * 3)(*gravity))
         self._chk(lib().sim_set_params(self.ctx, byref(p)))
         self.params = dict(nu=nu, dt=dt, s=s, gravity=tuple(gravity))
+        self.record_gen += 1
 
     def init_state(self, ugen, out):
         self._chk(lib().sim_init_state(self.ctx, *map(_ptr, ugen), *map(_ptr, out)))
@@ -240,6 +252,8 @@ class Sim:
 
     def step(self, u, nsteps=1, record=False, allow=(SIM_OK, SIM_OK_FALLBACK)):
         st = (sim_stats * max(nsteps, 1))()
+        if record:
+            self.record_gen += 1
         rc = lib().sim_step(self.ctx, *map(_ptr, u), nsteps, int(record), st)
         self._chk(rc, allow)
         return [st[q].as_dict() for q in range(nsteps)]
@@ -252,14 +266,20 @@ class Sim:
         self._chk(rc, allow)
         return st.as_dict(), p
 
-    def backward(self, g, ugen=None, out=None):
+    def backward(self, g, ugen=None, out=None, full=False):
+        """Gradient of the last recorded rollout.  Returns (dJ/du0 or dJ/dugen,
+        dJ/dnu, dJ/ds, stats), or with full=True (dJ/du0, grads, stats) where
+        grads = {"nu", "s", "dt", "gravity" (3-tuple)}."""
         out = out if out is not None else self.faces()
-        grad = (c_double * 2)()
+        grad = (c_double * 6)()
         st = sim_stats()
         ug = ugen if ugen is not None else (None, None, None)
         rc = lib().sim_backward(self.ctx, *map(_ptr, g), *map(_ptr, ug), *map(_ptr, out), grad,
                                 byref(st))
         self._chk(rc)
+        if full:
+            return out, {"nu": grad[0], "s": grad[1], "dt": grad[2],
+                         "gravity": (grad[3], grad[4], grad[5])}, st.as_dict()
         return out, grad[0], grad[1], st.as_dict()
 
     def loss_mse(self, u, target, want_grad=True):
