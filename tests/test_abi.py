@@ -146,3 +146,12 @@ def test_net_param_count_matches_architecture():
     chans = [(2, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32), (32, 32),
              (48, 16), (16, 16), (16, 1)]
     assert fsb.net_param_count() == sum(27 * a * b for a, b in chans)
+
+
+def test_workspace_size_rejects_bad_convection_grad():
+    d = _desc()
+    d.convection_grad = 2
+    assert _ws_size(d)[0] == fsb.SIM_ERR_INVALID_ARG
+    d.convection_grad = fsb.SIM_CONVGRAD_UPWIND
+    assert _ws_size(d)[0] == fsb.SIM_OK
+
