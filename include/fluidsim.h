@@ -182,6 +182,25 @@ int sim_loss_mse(sim_ctx* ctx, const float* d_u, const float* d_v, const float* 
                  const float* d_tu, const float* d_tv, const float* d_tw, double* h_loss,
                  float* d_gu, float* d_gv, float* d_gw);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * loss and gradient as sim_loss_mse without a context or workspace.  The
+ * active faces come from the cell types d_cell (n^3 bytes, as sim_create's,
+ * on the device); J goes to the device double *d_loss (nothing is copied to
+ * the host, nothing synchronises); (d_gu, d_gv, d_gw) (all or none) receive
+ * dJ/du.  The block partial sums live in one fixed array of 49,408 bytes per
+ * device inside the library (looked up on the first call on each device and
+ * kept until the process ends); the call allocates nothing.  Calls that
+ * overlap on one device race on that array.  Enqueued on hip_stream (NULL =
+ * default stream).  SIM_ERR_INVALID_ARG, before any device work, for n
+ * outside [4, 1024] (the largest grid the library takes), a NULL input, a
+ * partial gradient set or a gradient output aliasing another argument;
+ * SIM_ERR_HIP if the array's address cannot be found or a launch fails. */
+int sim_loss_mse_noalloc(int32_t n, const uint8_t* d_cell, const float* d_u, const float* d_v,
+                         const float* d_w, const float* d_tu, const float* d_tv,
+                         const float* d_tw, double* d_loss, float* d_gu, float* d_gv,
+                         float* d_gw, void* hip_stream);
+
 /* The paper's masked cosine + L2 velocity loss (Section 3.4.2,
  * Eq. (optLoss)) between the simulated field (d_u, d_v, d_w) and a reference
  * (d_tu, d_tv, d_tw), both MAC face arrays of the context's grid.  Per cell,

@@ -80,6 +80,7 @@ SIGNATURES = {
     "sim_loss_mse": (c_int32, [_P, _P, _P, _P, _P, _P, _P, POINTER(c_double), _P, _P, _P]),
     "sim_loss_cos_l2": (c_int32, [_P, _P, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                   POINTER(c_double), POINTER(c_double), _P, _P, _P]),
+    "sim_loss_mse_noalloc": (c_int32, [c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sim_apic_p2g": (c_int32, [_P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sim_apic_g2p": (c_int32, [_P, c_int64, _P, _P, _P, c_double, _P, _P, _P]),
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
@@ -145,6 +146,19 @@ def check(rc, ctx=None, allow=(SIM_OK, SIM_OK_FALLBACK)):
 
 
 # ------------------------------------------------------------------ raw ABI
+
+def loss_mse_noalloc(n, d_cell, u, target, d_loss, g=None, stream=None):
+    """sim_loss_mse_noalloc: J into the device float64 tensor d_loss (one
+    element), dJ/du into g (three face tensors) when given.  Enqueue only."""
+    gg = g if g is not None else (None, None, None)
+    rc = lib().sim_loss_mse_noalloc(int(n), _ptr(d_cell), *map(_ptr, u), *map(_ptr, target),
+                                    _ptr(d_loss), *map(_ptr, gg),
+                                    c_void_p(stream.cuda_stream if stream is not None else 0))
+    if rc == SIM_ERR_INVALID_ARG:
+        raise FluidSimError(rc, "sim_loss_mse_noalloc: n outside [4, 1024], a NULL input, a "
+                            "partial gradient set or an aliased output")
+    return check(rc)
+
 
 def sim_workspace_size(desc: sim_desc) -> int:
     out = c_size_t(0)

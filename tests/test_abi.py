@@ -155,3 +155,21 @@ def test_workspace_size_rejects_bad_convection_grad():
     d.convection_grad = fsb.SIM_CONVGRAD_UPWIND
     assert _ws_size(d)[0] == fsb.SIM_OK
 
+
+@pytest.mark.parametrize("n", [3, 1025, -1])
+def test_noalloc_loss_rejects_sizes_beyond_its_limit(n):
+    """The allocation-free loss validates on the host before any device
+    work (so this runs without a GPU)."""
+    L = fsb.lib()
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    rc = L.sim_loss_mse_noalloc(n, p, p, p, p, p, p, p, p, None, None, None, None)
+    assert rc == fsb.SIM_ERR_INVALID_ARG
+
+
+def test_noalloc_loss_rejects_null_and_partial_gradients():
+    L = fsb.lib()
+    p = [ctypes.c_void_p(0x1000 + 0x100 * q) for q in range(12)]
+    assert L.sim_loss_mse_noalloc(16, None, *p[1:8], None, None, None, None) == fsb.SIM_ERR_INVALID_ARG
+    assert L.sim_loss_mse_noalloc(16, *p[:8], p[8], None, None, None) == fsb.SIM_ERR_INVALID_ARG
+    # a gradient output aliasing an input
+    assert L.sim_loss_mse_noalloc(16, *p[:8], p[1], p[9], p[10], None) == fsb.SIM_ERR_INVALID_ARG
