@@ -352,6 +352,40 @@ int sim_percnn_backward(sim_ctx* ctx, const float* h_w, int32_t K, const float* 
 int sim_constrained_project(sim_ctx* ctx, float* d_u, float* d_v, float* d_w, int32_t iters,
                             double eps, double* h_rel_div);
 
+/* ---- screen-space constrained projection (Section 3.3, Eq. (div2DV)) ----
+ * The 2-D screen velocity of the reconstructed surface must have the
+ * divergence the divergence-free 3-D motion implies:
+ *   div v = s,  s = -(u dvz/du + v dvz/dv + 2 vz) / z,
+ * with (u, v) screen coordinates normalised to [-1, 1] at pixel centres
+ * (spacings du = 2/W, dv = 2/H), vz the out-of-plane velocity and z the depth
+ * per pixel (the derivatives second-order central, one-sided at the border).
+ * The velocity is staggered on pixel edges: d_a (the u component) on the
+ * H x (W+1) vertical edges, a[j*(W+1) + i] the edge left of pixel (j, i);
+ * d_b on the (H+1) x W horizontal edges, b[j*W + i] the edge below pixel
+ * (j, i).  d_mask (H x W bytes, nonzero = the region where detection failed
+ * and the velocity was interpolated): an edge is free when one of its two
+ * pixels is in the region and both lie in the image; every other edge keeps
+ * its value.  The free edges of (d_a, d_b) lose, in place, the gradient of the
+ * potential p that is 0 off the region and solves A p = s - div v on it (A
+ * the masked 5-point Laplacian over the free edges): the least change that
+ * meets the constraint on the region.  Every connected part of the region
+ * must border a pixel outside it, or the system is singular.
+ * The solve runs Jacobi-PCG in FP64 to the relative residual tol (0 < tol < 1),
+ * at most max_iter iterations, in the caller's workspace (256-byte aligned,
+ * sim_screen_workspace_size bytes: seven FP64 pixel vectors and 33 KB).  All
+ * pointers are device pointers except h_*; work is enqueued on hip_stream and
+ * the call returns when it is done.  h_iters and h_rel_residual (nullable)
+ * receive the iterations and the true relative residual |A p - rhs| / |rhs|.
+ * SIM_ERR_INVALID_ARG (before any device work) for H or W outside [3, 16384],
+ * a NULL pointer, tol outside (0, 1), max_iter < 1 or a misaligned workspace;
+ * SIM_ERR_WORKSPACE_TOO_SMALL; SIM_ERR_NOT_CONVERGED (the update of the last
+ * iterate is still applied) when tol was not reached or the solve broke down. */
+int sim_screen_workspace_size(int32_t H, int32_t W, size_t* bytes);
+int sim_screen_project(int32_t H, int32_t W, float* d_a, float* d_b, const float* d_vz,
+                       const float* d_z, const uint8_t* d_mask, double tol, int32_t max_iter,
+                       void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                       int32_t* h_iters, double* h_rel_residual);
+
 /* ---- the paper's APIC transfers (Section 3.2.2, Eq. (particle_map)) -----
  * On the MAC grid each velocity component lives on its own lattice, the
  * centres of its faces (component 0's node (i, j, k) at h (i, j + 1/2,

@@ -81,6 +81,9 @@ SIGNATURES = {
     "sim_loss_cos_l2": (c_int32, [_P, _P, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                   POINTER(c_double), POINTER(c_double), _P, _P, _P]),
     "sim_loss_mse_noalloc": (c_int32, [c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sim_screen_workspace_size": (c_int32, [c_int32, c_int32, POINTER(c_size_t)]),
+    "sim_screen_project": (c_int32, [c_int32, c_int32, _P, _P, _P, _P, _P, c_double, c_int32, _P,
+                                     c_size_t, _P, POINTER(c_int32), POINTER(c_double)]),
     "sim_apic_p2g": (c_int32, [_P, c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sim_apic_g2p": (c_int32, [_P, c_int64, _P, _P, _P, c_double, _P, _P, _P]),
     "sim_net_param_count": (c_int32, [POINTER(c_int64)]),
@@ -146,6 +149,29 @@ def check(rc, ctx=None, allow=(SIM_OK, SIM_OK_FALLBACK)):
 
 
 # ------------------------------------------------------------------ raw ABI
+
+def screen_project(a, b, vz, z, mask, tol=1e-10, max_iter=20000, workspace=None, stream=None):
+    """sim_screen_project in place on the float32 device tensors a (H, W+1)
+    and b (H+1, W), with vz, z (H, W) float32 and mask (H, W) uint8 on the
+    device.  The workspace is a torch uint8 tensor (allocated here when not
+    given).  Returns (iterations, true relative residual)."""
+    import torch
+    H, W = int(vz.shape[0]), int(vz.shape[1])
+    size = c_size_t(0)
+    check(lib().sim_screen_workspace_size(H, W, byref(size)))
+    if workspace is None:
+        workspace = torch.empty(size.value, dtype=torch.uint8, device=vz.device)
+    it, rel = c_int32(0), c_double(0.0)
+    st = stream if stream is not None else torch.cuda.current_stream(vz.device)
+    rc = lib().sim_screen_project(H, W, _ptr(a), _ptr(b), _ptr(vz), _ptr(z), _ptr(mask), float(tol),
+                                  int(max_iter), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(),
+                                  c_void_p(st.cuda_stream), byref(it), byref(rel))
+    if rc != SIM_OK:
+        raise FluidSimError(rc, f"sim_screen_project returned {rc} (iterations {it.value}, "
+                            f"relative residual {rel.value:.3e})")
+    return it.value, rel.value
+
 
 def loss_mse_noalloc(n, d_cell, u, target, d_loss, g=None, stream=None):
     """sim_loss_mse_noalloc: J into the device float64 tensor d_loss (one

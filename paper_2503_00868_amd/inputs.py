@@ -120,3 +120,48 @@ def gen_case(n: int, seed: int):
 
 def liquid_fraction(cell: np.ndarray) -> float:
     return float(np.mean(cell == LIQUID))
+
+
+_STREAM_SCREEN = 4
+
+
+def gen_screen(H: int, W: int, seed: int, n_blobs: int = 6, blob_range=(0.05, 0.2)):
+    """Inputs of the screen-space constrained projection (Section 3.3) for an
+    H x W image, standing in for one frame of the paper's videos:
+
+    * the interpolated screen velocity on pixel edges, a (H, W+1) and
+      b (H+1, W): a few smooth modes plus small noise, as a mainstream-guided
+      interpolation would leave it;
+    * the out-of-plane velocity vz (H, W), smooth, and the depth z (H, W) in
+      [1, 2];
+    * the region where detection failed: a union of n_blobs discs (radii a
+      fraction blob_range of min(H, W)) that never covers the whole image.
+
+    Returns float32 (a, b, vz, z) and uint8 mask."""
+    rng = _rng(seed, _STREAM_SCREEN)
+
+    def smooth(shape, modes=4):
+        yy, xx = np.meshgrid(np.linspace(0, 1, shape[0]), np.linspace(0, 1, shape[1]),
+                             indexing="ij")
+        f = np.zeros(shape)
+        for _ in range(modes):
+            kx, ky = rng.integers(1, 4, size=2)
+            ph = rng.uniform(0, 2 * np.pi, size=2)
+            f += rng.standard_normal() * np.sin(np.pi * kx * xx + ph[0]) * np.cos(np.pi * ky * yy + ph[1])
+        return f
+
+    a = smooth((H, W + 1)) + 0.05 * rng.standard_normal((H, W + 1))
+    b = smooth((H + 1, W)) + 0.05 * rng.standard_normal((H + 1, W))
+    vz = 0.3 * smooth((H, W))
+    z = 1.0 + rng.random((H, W)) * 0.2 + 0.8 * (0.5 + 0.5 * np.tanh(smooth((H, W), 2)))
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    mask = np.zeros((H, W), dtype=bool)
+    m = min(H, W)
+    for _ in range(n_blobs):
+        cj, ci = rng.uniform(0, H), rng.uniform(0, W)
+        rad = rng.uniform(blob_range[0], blob_range[1]) * m
+        mask |= (jj - cj) ** 2 + (ii - ci) ** 2 <= rad * rad
+    if mask.all():
+        mask[0, 0] = False
+    return (a.astype(np.float32), b.astype(np.float32), vz.astype(np.float32),
+            z.astype(np.float32), mask.astype(np.uint8))

@@ -173,3 +173,17 @@ def test_noalloc_loss_rejects_null_and_partial_gradients():
     assert L.sim_loss_mse_noalloc(16, *p[:8], p[8], None, None, None) == fsb.SIM_ERR_INVALID_ARG
     # a gradient output aliasing an input
     assert L.sim_loss_mse_noalloc(16, *p[:8], p[1], p[9], p[10], None) == fsb.SIM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("H,W,tol,it", [(2, 10, 1e-8, 10), (10, 20000, 1e-8, 10), (10, 10, 0.0, 10),
+                                        (10, 10, 1e-8, 0)])
+def test_screen_project_rejects_bad_arguments(H, W, tol, it):
+    """Host validation before any device work (runs without a GPU)."""
+    L = fsb.lib()
+    p = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+    rc = L.sim_screen_project(H, W, p, p, p, p, p, tol, it, ws, 1 << 30, None, None, None)
+    assert rc == fsb.SIM_ERR_INVALID_ARG
+    out = ctypes.c_size_t()
+    assert L.sim_screen_workspace_size(10, 10, ctypes.byref(out)) == fsb.SIM_OK and out.value > 0
+    assert L.sim_screen_workspace_size(2, 10, ctypes.byref(out)) == fsb.SIM_ERR_INVALID_ARG
