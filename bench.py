@@ -121,6 +121,21 @@ def parse():
                    help="skip the upwind convection gradient's measurement")
     p.add_argument("--no-loss", action="store_true",
                    help="skip the masked cosine + L2 loss's measurement")
+    p.add_argument("--no-grad-fd", action="store_true",
+                   help="skip the central-FD check of the headline gradient (exact and upwind "
+                        "convection adjoints)")
+    p.add_argument("--no-history-leg", action="store_true",
+                   help="skip the rollout timed without the pressure history")
+    p.add_argument("--no-heldout", action="store_true",
+                   help="skip learned vs plain on the held-out mask")
+    p.add_argument("--heldout-seed", type=int, default=5)
+    p.add_argument("--no-screen", action="store_true",
+                   help="skip the screen-space constrained projection's measurement")
+    p.add_argument("--no-apic", action="store_true",
+                   help="skip the APIC transfers' measurement")
+    p.add_argument("--grad-table", default="",
+                   help="only measure adjoint vs central FD (exact and upwind convection "
+                        "gradients) for these comma-separated rollout lengths and exit")
     p.add_argument("--cpu-n", type=int, default=128)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
@@ -163,24 +178,45 @@ def load_traffic(kind, n, precond):
     return rec["bytes_per_launch"]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, seed):
-    """The FP64 oracle's step (advect, force, viscosity, projection to a
-    1e-6 relative residual) on one seed at n^3, timed on the host."""
-    import numpy as np
+    """The FP64 oracle on the bench step's unit of work: one forward step
+    (advect, force, viscosity, projection to a 1e-6 relative residual) and
+    one adjoint step of it (projection solve, viscosity adjoint, advection
+    transpose, parameter terms), on one seed at n^3, timed on the host."""
     from oracle import fluid as orc
     from paper_2503_00868_amd import inputs
     cell, ug = inputs.gen_case(n, seed)
-    nu = inputs.gen_nu(seed)
-    u0 = orc.mask_faces(cell, ug)
+    nu = inputs.gen_nu(101)
+    s = inputs.gen_scale(101)
+    u0 = tuple(s * f for f in orc.mask_faces(cell, ug))
     orc.lib()
     t0 = time.perf_counter()
-    _, info = orc.step(cell, u0, nu, 1.0 / 120, tol=1e-6, diff_tol=1e-6)
-    dt = time.perf_counter() - t0
+    u1, info = orc.step(cell, u0, nu, 1.0 / 120, tol=1e-6, diff_tol=1e-6)
+    t_fwd = time.perf_counter() - t0
+    lam = orc.loss_grad(cell, u1, u0)
+    t0 = time.perf_counter()
+    orc.step_adjoint(cell, u0, lam, nu, 1.0 / 120, tol=1e-6)
+    t_adj = time.perf_counter() - t0
+    dt = t_fwd + t_adj
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n ** 3 / dt, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one step of the FP64 oracle at {n}^3, seed {seed} (plain CG to 1e-6, "
-                      f"{info.proj_iters} iterations, {'explicit' if info.explicit else 'implicit'}"
-                      f" viscosity), {dt:.1f} s"}
+            "cpu_model": cpu_model(),
+            "sample": f"one forward step ({t_fwd:.1f} s: plain CG to 1e-6, {info.proj_iters} "
+                      f"iterations, {'explicit' if info.explicit else 'implicit'} viscosity) and "
+                      f"one adjoint step ({t_adj:.1f} s) of the FP64 oracle at {n}^3, seed {seed}; "
+                      f"the headline is this unit at 256^3 (8x the cells, and about 2x the "
+                      f"iterations per solve)"}
 
 
 def rooflines(prof, n, precond):
@@ -380,6 +416,136 @@ def loss_bench(cell, ugen, nu, s, dt, g, dev, reps=10):
                          "avg_us": round(us, 2), "bytes_per_call": LOSS_BYTES * cells}}
 
 
+# The screen-space constrained projection, per pixel and CG iteration: the
+# direction + stencil kernel reads z 8, d 8, mask 1 and writes d 8, q 8; the
+# update reads the mask and, on region pixels (fraction f), d 8, q 8, x 8,
+# r 8 and writes x 8, r 8, z 8.
+def screen_bytes_per_iter(f):
+    return 33.0 + 1.0 + 56.0 * f
+
+
+def screen_bench(dev, H=1080, W=1920, seed=7, reps=3):
+    """The paper's screen-space constrained projection on a 1080 x 1920 frame
+    of the seeded generator, to a 1e-9 relative residual: ms per call,
+    iterations, and the HBM rate of its CG iterations."""
+    import torch
+    from paper_2503_00868_amd import inputs
+    from paper_2503_00868_amd.fluidsim import screen_project
+    a, b, vz, z, mask = inputs.gen_screen(H, W, seed)
+    dv = lambda x: torch.as_tensor(x, device=dev)
+    VZ, Z, M = dv(vz), dv(z), dv(mask)
+    A0, B0 = dv(a), dv(b)
+    A, B = A0.clone(), B0.clone()
+    screen_project(A, B, VZ, Z, M, tol=1e-9)  # warm-up (also allocates the workspace once)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(reps):
+        A.copy_(A0)
+        B.copy_(B0)
+        ev[0].record()
+        it, rel = screen_project(A, B, VZ, Z, M, tol=1e-9)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    t = min(ms)
+    f = float(mask.mean())
+    per_iter_s = t * 1e-3 / max(it, 1)
+    achieved = screen_bytes_per_iter(f) * H * W / per_iter_s / 1e9
+    return {"H": H, "W": W, "region_fraction": round(f, 4), "iters": it, "rel_residual": rel,
+            "ms_per_call": round(t, 3),
+            "roofline": {"bound": "hbm", "kernel": "k_s2_dir_spmv + k_s2_update (+ 2 finalize)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_us_per_iter": round(per_iter_s * 1e6, 2),
+                         "bytes_per_iter": screen_bytes_per_iter(f) * H * W}}
+
+
+def apic_bench(cell, dev, per_cell=8, reps=5):
+    """The paper's APIC transfers at the benchmark's mask: `per_cell`
+    particles jittered in every liquid cell (one cell from the walls), a
+    smooth velocity field, C = 0; particles to grid (zero, scatter with FP32
+    atomics, normalise) and grid to particles (gather, affine update, move),
+    timed with HIP events, with their HBM rates: P2G moves 64 B per particle
+    in and 24 B per face (mass and velocity, three components) out; G2P 12 B
+    per particle in, 60 out, and 12 B per face in."""
+    import torch
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="jacobi", device=dev)
+    liq = torch.as_tensor(cell, device=dev)[1:-1, 1:-1, 1:-1] == 1
+    k, j, i = torch.nonzero(liq, as_tuple=True)
+    base = torch.stack([i + 1, j + 1, k + 1], -1).to(torch.float32)
+    del liq, k, j, i
+    gen = torch.Generator(device=dev).manual_seed(11)
+    x = (base.repeat_interleave(per_cell, 0) +
+         torch.rand((base.shape[0] * per_cell, 3), device=dev, generator=gen)) / n
+    del base
+    P = x.shape[0]
+    v = torch.stack([torch.sin(6.0 * x[:, 1]), torch.cos(5.0 * x[:, 2]), 0.5 * torch.sin(4.0 * x[:, 0])], -1)
+    C = torch.zeros((P, 3, 3), dtype=torch.float32, device=dev)
+    m = torch.ones(P, dtype=torch.float32, device=dev)
+    grid, mass = sim.faces(), sim.faces()
+    vp, Cp = torch.empty_like(v), torch.empty_like(C)
+    xm = x.clone()
+    sim.apic_p2g(x, v, C, m, out=grid, mass=mass)  # warm-up
+    sim.apic_g2p(grid, xm, 0.0, vp=vp, C=Cp)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        sim.apic_p2g(x, v, C, m, out=grid, mass=mass)
+    ev[1].record()
+    for _ in range(reps):
+        sim.apic_g2p(grid, xm, 0.0, vp=vp, C=Cp)
+    ev[2].record()
+    torch.cuda.synchronize()
+    p2g_us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+    g2p_us = ev[1].elapsed_time(ev[2]) / reps * 1e3
+    F = (n + 1) * n * n
+    p2g_bytes = 64.0 * P + 24.0 * F
+    g2p_bytes = 72.0 * P + 12.0 * F
+    sim.close()
+
+    def rl(name, byts, us):
+        ach = byts / (us * 1e-6) / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_us": round(us, 2), "bytes_per_call": byts}
+    return {"particles": P, "per_liquid_cell": per_cell, "p2g_us": round(p2g_us, 1),
+            "g2p_us": round(g2p_us, 1),
+            "p2g_atomics_per_s": 2 * 27 * 3 * P / (p2g_us * 1e-6),
+            "roofline_p2g": rl("k_apic_zero + k_apic_p2g + k_apic_normalize", p2g_bytes, p2g_us),
+            "roofline_g2p": rl("k_apic_g2p", g2p_bytes, g2p_us)}
+
+
+def fd_gradient(sim, ugen, target, nu, s, dt, g, T, h=1e-3):
+    """Central FD of J in theta_nu = log nu and theta_s = log s (h = 1e-3),
+    from forward-only rollouts of `sim`."""
+    def J(tn, ts):
+        sim.set_params(nu=math.exp(tn), dt=dt, s=math.exp(ts), gravity=g)
+        u = sim.faces()
+        sim.init_state(ugen, u)
+        sim.step(u, T)
+        return sim.loss_mse(u, target, want_grad=False)[0]
+    a, b = math.log(nu), math.log(s)
+    return {"dtheta_nu": (J(a + h, b) - J(a - h, b)) / (2 * h),
+            "dtheta_s": (J(a, b + h) - J(a, b - h)) / (2 * h)}
+
+
+def adjoint_gradient(sim, ugen, target, nu, s, dt, g, T):
+    sim.set_params(nu=nu, dt=dt, s=s, gravity=g)
+    u = sim.faces()
+    sim.init_state(ugen, u)
+    sim.step(u, T, record=True)
+    J, gT = sim.loss_mse(u, target)
+    _, gr, st = sim.backward(gT, ugen=ugen, full=True)
+    return {"J": J, "dtheta_nu": nu * gr["nu"], "dtheta_s": s * gr["s"], "dJ_ddt": gr["dt"],
+            "dJ_dg": list(gr["gravity"]), "adjoint_iters": st["iters"]}
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else float("inf")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -424,14 +590,52 @@ def main():
     def check_period(pc):
         return args.check_every or (16 if pc == "jacobi" else 4)
 
-    def make_sim(pc):
-        s = Sim(cell, precond=pc, tol=1e-6, diff_tol=1e-6, max_iter=20000,
-                check_every=check_period(pc), checkpoint_every=K, max_steps=T,
-                warm_start=not args.cold, store_pressures=not args.no_pressure_history,
-                device=dev)
+    def make_sim(pc, on_cell=None, history=None, conv="exact", tol=1e-6, steps=None):
+        s = Sim(cell if on_cell is None else on_cell, precond=pc, tol=tol, diff_tol=tol,
+                max_iter=20000, check_every=check_period(pc), checkpoint_every=K,
+                max_steps=T if steps is None else steps, warm_start=not args.cold,
+                store_pressures=(not args.no_pressure_history) if history is None else history,
+                convection_grad=conv, device=dev)
         if pc == "learned":
             s.net_set_weights(weights)
         return s
+
+    def make_target(on_cell, steps):
+        tsim = Sim(on_cell, precond="jacobi", tol=1e-6, diff_tol=1e-6, max_iter=20000,
+                   check_every=16, warm_start=True, device=dev)
+        ug_dev = tsim.to_faces(inputs.gen_velocity(n, args.seed) if on_cell is cell else
+                               inputs.gen_case(n, args.heldout_seed)[1])
+        tsim.set_params(nu=nu_t, dt=dt, s=s_t, gravity=g)
+        tgt = tsim.faces()
+        tsim.init_state(ug_dev, tgt)
+        tsim.step(tgt, steps)
+        torch.cuda.synchronize()
+        tsim.close()
+        return ug_dev, tgt
+
+    if args.grad_table:
+        rows = []
+        for TT in [int(x) for x in args.grad_table.split(",")]:
+            ugen_t, tgt = make_target(cell, TT)
+            row = {"rollout": TT}
+            for conv in ("exact", "upwind"):
+                gs = make_sim(precond, history=True, conv=conv, tol=1e-7, steps=TT)
+                row[conv] = adjoint_gradient(gs, ugen_t, tgt, nu_e, s_e, dt, g, TT)
+                if conv == "exact":
+                    row["fd"] = fd_gradient(gs, ugen_t, tgt, nu_e, s_e, dt, g, TT)
+                gs.close()
+                del gs
+            for conv in ("exact", "upwind"):
+                for key in ("dtheta_nu", "dtheta_s"):
+                    row[conv]["rel_err_" + key] = _rel(row[conv][key], row["fd"][key])
+            log(f"grad table T={TT}: FD {row['fd']}; exact {row['exact']['dtheta_nu']:.4e} "
+                f"{row['exact']['dtheta_s']:.4e}; upwind {row['upwind']['dtheta_nu']:.4e} "
+                f"{row['upwind']['dtheta_s']:.4e}")
+            rows.append(row)
+            del tgt, ugen_t
+        print(json.dumps({"grad_table": rows, "n": n, "precond": precond, "tol": 1e-7,
+                          "seed": args.seed}), flush=True)
+        return
 
     # target rollout (untimed setup; the target does not depend on the
     # preconditioner, so the fastest plain one computes it)
@@ -447,6 +651,7 @@ def main():
     del tsim
     log("target rollout done")
 
+    torch.cuda.reset_peak_memory_stats(dev)
     sim = make_sim(precond)
     u = sim.faces()
 
@@ -476,6 +681,8 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = sim.profile_read()
     sim.profile_enable(False)
+    peak_mem = torch.cuda.max_memory_allocated(dev)
+    ws_bytes = sim.ws.numel()
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = n ** 3 * T / (elapsed / args.steps)
@@ -488,11 +695,92 @@ def main():
     log("kernel time in the timed region (ms, launches): " +
         ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items() if v[1]))
 
+    # the headline gradient against central FD, for the exact transpose of the
+    # advection (the timed reverse pass) and for the paper's upwind surrogate
+    grad_fd = None
+    if not args.no_grad_fd:
+        fd = fd_gradient(sim, ugen, target, nu_e, s_e, dt, g, T)
+        exact = {"dtheta_nu": nu_e * dnu, "dtheta_s": s_e * ds}
+        log(f"FD dJ/dtheta: nu {fd['dtheta_nu']:.4e} s {fd['dtheta_s']:.4e}; exact adjoint "
+            f"nu {exact['dtheta_nu']:.4e} s {exact['dtheta_s']:.4e}")
+        sim.close()
+        del sim
+        usim = make_sim(precond, conv="upwind")
+        up = adjoint_gradient(usim, ugen, target, nu_e, s_e, dt, g, T)
+        usim.close()
+        del usim
+        log(f"upwind-surrogate adjoint nu {up['dtheta_nu']:.4e} s {up['dtheta_s']:.4e}")
+        grad_fd = {"h": 1e-3, "fd": fd, "exact": exact,
+                   "upwind": {k: up[k] for k in ("dtheta_nu", "dtheta_s")}}
+        for conv in ("exact", "upwind"):
+            for key in ("dtheta_nu", "dtheta_s"):
+                grad_fd[conv]["rel_err_" + key] = _rel(grad_fd[conv][key], fd[key])
+    else:
+        sim.close()
+        del sim
+
+    # the headline rollout once more without the pressure history: the
+    # backward's segment recompute repeats every forward solve
+    no_hist = None
+    if not args.no_history_leg and not args.no_pressure_history:
+        hsim = make_sim(precond, history=False)
+        hu = hsim.faces()
+
+        def hist_step(rollout):
+            hsim.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
+            hsim.init_state(ugen, hu)
+            hsim.step(hu, rollout, record=True)
+            _, gT = hsim.loss_mse(hu, target)
+            return hsim.backward(gT, ugen=ugen)[3]
+
+        hist_step(args.warmup_rollout)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hb = hist_step(T)
+        torch.cuda.synchronize()
+        hel = time.perf_counter() - t1
+        no_hist = {"ms_per_step": round(hel * 1e3, 1), "value": n ** 3 * T / hel,
+                   "adjoint_iters": hb["iters"], "workspace_bytes": hsim.ws.numel()}
+        log(f"without the pressure history: {hel * 1e3:.1f} ms, {no_hist['value']:.3e} cell-steps/s")
+        hsim.close()
+        del hsim
+
+    # learned vs plain on a mask no weight was selected on
+    heldout = None
+    if precond == "learned" and not args.no_heldout:
+        hcell = inputs.gen_mask(n, args.heldout_seed)
+        hugen, htarget = make_target(hcell, T)
+        heldout = {"seed": args.heldout_seed,
+                   "liquid_fraction": round(inputs.liquid_fraction(hcell), 4)}
+        for pc in ("learned", "jacobi"):
+            xs = make_sim(pc, on_cell=hcell)
+            xu = xs.faces()
+
+            def xstep(rollout):
+                xs.set_params(nu=nu_e, dt=dt, s=s_e, gravity=g)
+                xs.init_state(hugen, xu)
+                st = xs.step(xu, rollout, record=True)
+                _, gT = xs.loss_mse(xu, htarget)
+                return st, xs.backward(gT, ugen=hugen)[3]
+
+            xstep(args.warmup_rollout)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            xst, xb = xstep(T)
+            torch.cuda.synchronize()
+            xel = time.perf_counter() - t1
+            heldout[pc] = {"ms_per_step": round(xel * 1e3, 1), "value": n ** 3 * T / xel,
+                           "pressure_iters_mean": float(np.mean([q["iters"] for q in xst])),
+                           "adjoint_iters": xb["iters"]}
+            log(f"held-out mask seed {args.heldout_seed}, {pc}: {xel * 1e3:.1f} ms")
+            xs.close()
+            del xs
+        heldout["learned_over_plain"] = heldout["jacobi"]["ms_per_step"] / heldout["learned"]["ms_per_step"]
+        del htarget, hugen
+
     # the same workload with plain (Jacobi) PCG, beside a learned headline
     plain = None
     if precond != "jacobi" and not args.no_plain:
-        sim.close()
-        del sim
         psim = make_sim("jacobi")
         pu = psim.faces()
 
@@ -572,6 +860,18 @@ def main():
         loss_out = loss_bench(cell, ugen, nu_e, s_e, dt, g, dev)
         log(f"masked cosine + L2 loss with gradient: {loss_out['us_per_call']:.1f} us per call")
 
+    screen_out = None
+    if not args.no_screen:
+        screen_out = screen_bench(dev)
+        log(f"screen-space projection 1080x1920: {screen_out['ms_per_call']:.2f} ms, "
+            f"{screen_out['iters']} iterations")
+
+    apic_out = None
+    if not args.no_apic:
+        apic_out = apic_bench(cell, dev)
+        log(f"APIC transfers, {apic_out['particles']} particles: P2G {apic_out['p2g_us']:.0f} us, "
+            f"G2P {apic_out['g2p_us']:.0f} us")
+
     out = {
         "metric": "cell-steps/s to 1e-6 Poisson residual at 256^3; learned-PCG vs plain PCG",
         "value": value,
@@ -595,6 +895,11 @@ def main():
                    "pressure_history": not args.no_pressure_history},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
+        "peak_mem_bytes": peak_mem,
+        "workspace_bytes": ws_bytes,
+        "grad_fd": grad_fd,
+        "no_pressure_history": no_hist,
+        "heldout": heldout,
         "plain_pcg": plain,
         "cpu_baseline": cpu,
         "compare": compare,
@@ -603,6 +908,8 @@ def main():
         "constrained": cp_out,
         "upwind": up_out,
         "loss": loss_out,
+        "screen": screen_out,
+        "apic": apic_out,
     }
     print(json.dumps(out), flush=True)
 
