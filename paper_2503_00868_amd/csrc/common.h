@@ -74,6 +74,31 @@ __device__ inline int xcd_logical_block(int b, int nblocks) {
   return prefix + b / nx;
 }
 
+// Block order of the network's z-marching kernels, whose grid is nch z-runs
+// x (tpr x tpr) xy-tiles.  Only the tiles near liquid hold work, and the
+// liquid of a volume is not spread evenly in z, so handing each XCD one
+// contiguous range of z (xcd_logical_block) loads the XCDs unevenly (1.5x the
+// mean on the 256^3 benchmark mask).  Instead XCD x = b % 8 takes the tile
+// rows ty of run c with (c + ty) % 8 == x, each row whole (x-neighbouring
+// tiles share their halo columns in that XCD's L2), in run order: every XCD
+// gets rows of every z-range.  Needs tpr % 8 == 0 (else the contiguous order).
+__device__ inline void net_block_of(int b, int nblocks, int tpr, int& tile, int& chunk) {
+  const int tiles = tpr * tpr;
+  if ((tpr & 7) == 0 && nblocks % tiles == 0) {
+    const int x = b & 7, i = b >> 3;
+    const int k = i / tpr, tx = i - k * tpr;  // k-th row of this XCD, tile tx in it
+    const int m = tpr >> 3;                   // rows per run that fall to one XCD
+    const int c = k / m, j = k - c * m;
+    const int ty = ((x - c) & 7) + 8 * j;
+    tile = ty * tpr + tx;
+    chunk = c;
+    return;
+  }
+  const int lb = xcd_logical_block(b, nblocks);
+  tile = lb % tiles;
+  chunk = lb / tiles;
+}
+
 // Orders LDS traffic between the lanes of one wave (a wave's LDS operations
 // execute in order; this keeps the compiler from moving them across).
 __device__ inline void wave_sync() {

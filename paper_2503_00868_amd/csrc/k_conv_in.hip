@@ -56,8 +56,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
 
   const int tpr = (n + IT - 1) / IT;
   const int tiles = tpr * tpr;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % tiles, chunk = lb / tiles;
+  int tile, chunk;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, chunk);
   const int x0 = (tile % tpr) * IT, y0 = (tile / tpr) * IT;
   const int z0 = chunk * zc;
   const int z1 = min(z0 + zc, n);

@@ -59,8 +59,8 @@ __global__ void __launch_bounds__(kBlock)
 
   const int tpr = (n + OT - 1) / OT;
   const int tiles = tpr * tpr;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % tiles, chunk = lb / tiles;
+  int tile, chunk;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, chunk);
   const int x0 = (tile % tpr) * OT, y0 = (tile / tpr) * OT;
   const int z0 = chunk * zc;
   const int z1 = min(z0 + zc, n);

@@ -104,9 +104,9 @@ __global__ void __launch_bounds__(kBlock)
   __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
 
   const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % tiles, chunk = lb / tiles;
   const int tpr = (n + ZT - 1) / ZT;
+  int tile, chunk;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, chunk);
   const int x0 = (tile % tpr) * ZT, y0 = (tile / tpr) * ZT;
   const int z0 = chunk * zc;
   const int z1 = min(z0 + zc, n);
@@ -479,9 +479,9 @@ __global__ void __launch_bounds__(kBlock)
   __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
 
   const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % tiles, chunk = lb / tiles;
   const int tpr = (n + ZT - 1) / ZT;
+  int tile, chunk;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, chunk);
   const int x0 = (tile % tpr) * ZT, y0 = (tile / tpr) * ZT;
   const int z0 = chunk * zc;
   const int z1 = min(z0 + zc, n);

@@ -72,8 +72,14 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ __attribute__((aligned(16))) _Float16 stage[4][UR * 2 * UX * 16];
   const int nc = n / 2;
   const int tx = (nc + UX - 1) / UX, ty = (nc + UY - 1) / UY;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tile = lb % (tx * ty), run = lb / (tx * ty);
+  int tile, run;
+  if (tx == ty) {
+    net_block_of(blockIdx.x, gridDim.x, tx, tile, run);
+  } else {
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    tile = lb % (tx * ty);
+    run = lb / (tx * ty);
+  }
   const int X0 = (tile % tx) * UX, Y0 = (tile / tx) * UY;
   const int Z0 = run * zr, Z1 = min(Z0 + zr, nc);
   if (Z0 >= nc) return;
