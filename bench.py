@@ -512,7 +512,8 @@ def apic_bench(cell, dev, per_cell=8, reps=5):
                 "avg_us": round(us, 2), "bytes_per_call": byts}
     return {"particles": P, "per_liquid_cell": per_cell, "p2g_us": round(p2g_us, 1),
             "g2p_us": round(g2p_us, 1),
-            "p2g_atomics_per_s": 2 * 27 * 3 * P / (p2g_us * 1e-6),
+            "p2g_particles_per_s": P / (p2g_us * 1e-6),
+            "g2p_particles_per_s": P / (g2p_us * 1e-6),
             "roofline_p2g": rl("k_apic_zero + k_apic_p2g + k_apic_normalize", p2g_bytes, p2g_us),
             "roofline_g2p": rl("k_apic_g2p", g2p_bytes, g2p_us)}
 
