@@ -114,6 +114,8 @@ def parse():
     p.add_argument("--no-percnn", action="store_true",
                    help="skip the recurrent convolutional solver's measurement")
     p.add_argument("--percnn-layers", type=int, default=100)
+    p.add_argument("--no-percnn-fit", action="store_true",
+                   help="skip the recurrent solver's kernel fit and its equal-time comparison")
     p.add_argument("--no-constrained", action="store_true",
                    help="skip the constrained divergence projection's measurement")
     p.add_argument("--constrained-iters", type=int, default=100)
@@ -256,6 +258,11 @@ def rooflines(prof, n, precond):
     return r_hbm, None
 
 
+def inputs_gen_case(n, seed):
+    from paper_2503_00868_amd import inputs
+    return inputs.gen_case(n, seed)
+
+
 def percnn_bench(cell, ugen, nu, s, dt, g, dev, K):
     """The recurrent convolutional pressure solver on the benchmark's state:
     K layers with the Jacobi kernel from p = 0 (states recorded) and their
@@ -309,6 +316,90 @@ def percnn_bench(cell, ugen, nu, s, dt, g, dev, K):
                                    "traffic": load_traffic(kind, n, "jacobi"),
                                    "avg_us": round(avg_s * 1e6, 2), "launches": launches,
                                    "bytes_per_launch": bpc * n ** 3}
+    return out
+
+
+def percnn_fitted_bench(cell, dev, weights, K=100, steps=60, layer_us=None):
+    """The paper's recurrent convolutional solver with a fitted kernel (Section
+    3.4.1): the kernel is fitted at the benchmark's size on (0, projection
+    pressure, right-hand side) pairs of three seeded velocity fields, one
+    sim_percnn_fit_step per Adam step; then, on a held-out field, the
+    relative pressure error ||p - p*|| / ||p*|| against wall time for the
+    fitted and the Jacobi kernels (K' layers at the measured time per layer),
+    for the flexible CG with the network and for Jacobi-PCG (their iterates
+    from sim_harvest_pairs, at the measured time per iteration)."""
+    import torch
+    from paper_2503_00868_amd import percnn
+    from paper_2503_00868_amd.fluidsim import Sim
+    n = cell.shape[0]
+    sim = Sim(cell, precond="learned", tol=1e-8, check_every=4, device=dev)
+    sim.net_set_weights(weights)
+    seeds = [1000, 1001, 1002, 1003]
+    pairs = percnn.make_pairs(sim, seeds)
+    train, test = pairs[:3], pairs[3:]
+    t0 = time.perf_counter()
+    # Adam's first steps move every weight by about lr, and K layers compound
+    # a change of the recurrence's spectral radius K times: the step size
+    # falls as 1/K (2e-3 at K = 16, where fits at 32^3 and 64^3 converge)
+    lr = 0.032 / K
+    w, losses = percnn.fit(sim, train, K, steps=steps, lr=lr)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    wj = percnn.jacobi_weights()
+    out = {"K_fit": K, "fit_steps": steps, "lr": lr, "fit_s": round(t_fit, 2), "loss_first": losses[0],
+           "loss_last": losses[-1], "weights": [round(float(x), 5) for x in w]}
+    # time per layer, per network-preconditioned CG iteration, per Jacobi-PCG iteration
+    pb, pa, b = test[0]
+    if layer_us is None:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        sim.percnn_forward(w, 10, pb, b)
+        ev[0].record()
+        sim.percnn_forward(w, 100, pb, b)
+        ev[1].record()
+        torch.cuda.synchronize()
+        layer_us = ev[0].elapsed_time(ev[1]) * 10.0
+    # the held-out field's pre-projection velocity (as make_pairs builds it)
+    _, ug = inputs_gen_case(n, seeds[-1])
+    sim.set_params(nu=1e-4, dt=1.0 / 120, s=1.0)
+    u = sim.faces()
+    sim.init_state(sim.to_faces(ug), u)
+    a = sim.op_advect(u)
+    per_it = {}
+    for pc in ("learned", "jacobi"):
+        s2 = Sim(cell, precond=pc, tol=1e-6, check_every=4 if pc == "learned" else 16, device=dev)
+        if pc == "learned":
+            s2.net_set_weights(weights)
+        uu = tuple(x.clone() for x in a)
+        s2.project(tuple(x.clone() for x in a))  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, _ = s2.project(uu)
+        torch.cuda.synchronize()
+        per_it[pc] = (time.perf_counter() - t1) * 1e3 / max(st["iters"], 1)
+        s2.close()
+    L = percnn.liquid_mask(sim)
+    norm = float(torch.linalg.norm(pa))
+    curves = {"percnn_fitted": [], "percnn_jacobi": [], "fcg_learned": [], "pcg_jacobi": []}
+    for Kp in (25, 50, 100, 200, 400, 800):
+        for name, ww in (("percnn_fitted", w), ("percnn_jacobi", wj)):
+            p = sim.percnn_forward(ww, Kp, pb, b)
+            curves[name].append({"ms": round(Kp * layer_us * 1e-3, 3), "layers": Kp,
+                                 "rel_error": float(torch.linalg.norm(L * (p - pa))) / norm})
+    for name, mode, its in (("fcg_learned", 1, [1, 2, 4, 8, 16, 32]),
+                            ("pcg_jacobi", 0, [2, 16, 64, 128, 256, 512])):
+        hs = sim if mode == 1 else Sim(cell, precond="jacobi", device=dev)
+        _, E, _ = hs.harvest_pairs(tuple(x.clone() for x in a), [0] + its, tol=1e-10, mode=mode)
+        e0 = float(torch.linalg.norm(E[0]))
+        key = "learned" if mode == 1 else "jacobi"
+        for q, k in enumerate(its):
+            curves[name].append({"ms": round(k * per_it[key], 3), "iters": k,
+                                 "rel_error": float(torch.linalg.norm(E[q + 1])) / e0})
+        del E
+        if mode == 0:
+            hs.close()
+    out.update({"layer_us": round(layer_us, 2), "fcg_iter_ms": round(per_it["learned"], 3),
+                "pcg_iter_ms": round(per_it["jacobi"], 4), "curves": curves})
+    sim.close()
     return out
 
 
@@ -843,6 +934,14 @@ def main():
                               args.percnn_layers)
         log(f"recurrent conv solver: {pc_out['layers']} layers {pc_out['fwd_ms']:.1f} ms forward, "
             f"{pc_out['bwd_ms']:.1f} ms reverse; rel error {pc_out['rel_error_vs_projection']:.3e}")
+
+    if pc_out is not None and weights is not None and not args.no_percnn_fit:
+        pc_out["fitted"] = percnn_fitted_bench(cell, dev, weights)
+        f = pc_out["fitted"]
+        log(f"recurrent conv solver fitted at {n}^3 (K={f['K_fit']}, {f['fit_steps']} steps, "
+            f"{f['fit_s']:.1f} s): loss {f['loss_first']:.3e} -> {f['loss_last']:.3e}")
+        for name, pts in f["curves"].items():
+            log(f"  {name}: " + ", ".join(f"{q['ms']:.1f} ms {q['rel_error']:.3e}" for q in pts))
 
     cp_out = None
     if not args.no_constrained:

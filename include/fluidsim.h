@@ -337,6 +337,26 @@ int sim_percnn_backward(sim_ctx* ctx, const float* h_w, int32_t K, const float* 
                         const float* d_hist, const float* d_g, float* d_gp0, float* d_gb,
                         double* h_grad_w);
 
+/* One Adam step (beta 0.9 / 0.999, eps 1e-12) of the kernel fit of the
+ * recurrent solver: the paper fits the solver's convolution on pressure
+ * fields taken before and after an implicit solve (Section 3.4.1).  For each
+ * of npairs pairs (stacked npairs x n^3 float32 device arrays: starting
+ * pressure d_p0, the solve's pressure d_target, right-hand side d_b), K >= 1
+ * layers run from p0 with their states kept in d_hist ((K+1) n^3 floats,
+ * overwritten), the loss sum over liquid cells of (p_K - target)^2 and its
+ * seed gradient 2 (p_K - target) are formed on the device, and the reverse
+ * pass gives dL/dW.  Then the 28 weights h_w (host doubles, W_0 .. W_26,
+ * w_b; in/out) take one Adam step of size lr on the mean gradient over the
+ * pairs, with the moments h_adam (host, 56 doubles: m then v; zero before
+ * step 1; in/out) and the 1-based step.  h_loss (nullable) receives the mean
+ * loss over the pairs before the update.  Uses the context's solver buffers
+ * (q, two direction buffers) and partial sums; synchronises the stream.
+ * SIM_ERR_INVALID_ARG for a NULL pointer, step < 1, K < 1, npairs < 1,
+ * lr not > 0, a non-finite weight, or d_hist overlapping a pair array. */
+int sim_percnn_fit_step(sim_ctx* ctx, double* h_w, double* h_adam, int32_t step, double lr,
+                        int32_t K, int32_t npairs, const float* d_p0, const float* d_target,
+                        const float* d_b, float* d_hist, double* h_loss);
+
 /* ---- constrained divergence projection (Section 3.3, Eq. (divProj)) ----
  * In place on (d_u, d_v, d_w) (face arrays as sim_step's): the fields are
  * first masked to the active faces (the variables), then `iters` iterations

@@ -23,6 +23,8 @@
 //   dL/dW_t += sum_c u(c) p_k(c + t),  dL/dw_b += sum_c u(c) b(c);
 // one kernel forms u on the fly from g_{k+1} and the diagonal, stages u and
 // p_k in two rings, and writes g_k, gb and 28 per-block partial sums.
+#include <cmath>
+
 #include "common.h"
 #include "ctx.h"
 
@@ -352,6 +354,22 @@ __global__ void __launch_bounds__(kBlock) k_percnn_zero(double* __restrict__ acc
       gb[i] = 0.f;
 }
 
+// The fit's loss and its seed gradient for one pair: over liquid cells
+// (Poisson diagonal non-zero) e = p_K - target, g = 2 e, and the block
+// partial of sum e^2; zero elsewhere.
+__global__ void __launch_bounds__(kBlock)
+    k_percnn_fit_seed(int64_t C, const uint8_t* __restrict__ cdiag, const float* __restrict__ pK,
+                      const float* __restrict__ target, float* __restrict__ g,
+                      double* __restrict__ partials) {
+  double v[1] = {0.0};
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < C; i += (int64_t)gridDim.x * kBlock) {
+    const float e = cdiag[i] ? pK[i] - target[i] : 0.f;
+    g[i] = 2.f * e;
+    v[0] += (double)e * (double)e;
+  }
+  store_partials<1>(v, partials, blockIdx.x);
+}
+
 }  // namespace fs
 
 using namespace fs;
@@ -451,6 +469,69 @@ int sim_percnn_backward(sim_ctx* c, const float* h_w, int32_t K, const float* b,
     return SIM_ERR_HIP;
   for (int q = 0; q < PC_NW; ++q) h_grad_w[q] = acc[q];
   return hipGetLastError() == hipSuccess ? SIM_OK : SIM_ERR_HIP;
+}
+
+// One Adam step of the kernel fit: for every pair, K layers from its p0 with
+// the states kept in d_hist, the loss and seed gradient on the device, and
+// the reverse pass for dL/dW; then the Adam update of the 28 weights here on
+// the host (beta 0.9 / 0.999, eps 1e-12).
+int sim_percnn_fit_step(sim_ctx* c, double* h_w, double* h_adam, int32_t step, double lr, int32_t K,
+                        int32_t npairs, const float* p0, const float* target, const float* b,
+                        float* hist, double* h_loss) {
+  if (!c) return SIM_ERR_INVALID_ARG;
+  if (!h_w || !h_adam || !p0 || !target || !b || !hist || step < 1 || K < 1 || npairs < 1 ||
+      !(lr > 0.0 && std::isfinite(lr))) {
+    c->err = "sim_percnn_fit_step: NULL pointer, step < 1, K < 1, npairs < 1 or lr not > 0";
+    return SIM_ERR_INVALID_ARG;
+  }
+  const int64_t C = c->C;
+  const float* ins[3] = {p0, target, b};
+  for (const float* q : ins)
+    if (q + (int64_t)npairs * C > hist && q < hist + (int64_t)(K + 1) * C) {
+      c->err = "sim_percnn_fit_step: hist overlaps a pair array";
+      return SIM_ERR_INVALID_ARG;
+    }
+  float wf[PC_NW];
+  for (int q = 0; q < PC_NW; ++q) {
+    if (!std::isfinite(h_w[q])) {
+      c->err = "sim_percnn_fit_step: non-finite weight";
+      return SIM_ERR_INVALID_ARG;
+    }
+    wf[q] = (float)h_w[q];
+  }
+  double grad[PC_NW] = {}, loss = 0.0;
+  float* g = c->q;  // the seed gradient (a solver buffer, free outside a solve)
+  const int nb = 1024;
+  for (int pr = 0; pr < npairs; ++pr) {
+    const int64_t off = (int64_t)pr * C;
+    int rc = sim_percnn_forward(c, wf, K, p0 + off, b + off, nullptr, hist);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_percnn_fit_seed, dim3(nb), dim3(kBlock), 0, c->stream, C, c->cdiag,
+                       hist + (int64_t)K * C, target + off, g, c->partials);
+    launch_finalize(c, nb, 1, FIN_SLOT, 0.0, 0, S_DOT0, 1.0, 0);
+    double gw[PC_NW];
+    rc = sim_percnn_backward(c, wf, K, b + off, hist, g, nullptr, nullptr, gw);
+    if (rc) return rc;
+    double l = 0.0;
+    if (hipMemcpyAsync(&l, c->scal + S_DOT0, sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return SIM_ERR_HIP;
+    loss += l;
+    for (int q = 0; q < PC_NW; ++q) grad[q] += gw[q];
+  }
+  const double inv = 1.0 / npairs;
+  const double c1 = 1.0 - std::pow(0.9, step), c2 = 1.0 - std::pow(0.999, step);
+  for (int q = 0; q < PC_NW; ++q) {
+    const double gq = grad[q] * inv;
+    double& m = h_adam[q];
+    double& v = h_adam[PC_NW + q];
+    m = 0.9 * m + 0.1 * gq;
+    v = 0.999 * v + 0.001 * gq * gq;
+    h_w[q] -= lr * (m / c1) / (std::sqrt(v / c2) + 1e-12);
+  }
+  if (h_loss) *h_loss = loss * inv;
+  return SIM_OK;
 }
 
 }  // extern "C"

@@ -105,6 +105,8 @@ SIGNATURES = {
     "sim_percnn_forward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P]),
     "sim_percnn_backward": (c_int32, [_P, POINTER(c_float), c_int32, _P, _P, _P, _P, _P,
                                       POINTER(c_double)]),
+    "sim_percnn_fit_step": (c_int32, [_P, POINTER(c_double), POINTER(c_double), c_int32, c_double,
+                                      c_int32, c_int32, _P, _P, _P, _P, POINTER(c_double)]),
     "sim_constrained_project": (c_int32, [_P, _P, _P, _P, c_int32, c_double, POINTER(c_double)]),
     "sim_profile_enable": (c_int32, [_P, c_int32]),
     "sim_profile_read": (c_int32, [_P, POINTER(c_double), POINTER(c_int64)]),
@@ -430,6 +432,19 @@ class Sim:
                                            _ptr(out) if out is not None else None,
                                            _ptr(hist) if hist is not None else None))
         return out if out is not None else hist
+
+    def percnn_fit_step(self, w, adam, step, lr, K, p0, target, b, hist):
+        """sim_percnn_fit_step: w (28) and adam (56) are float64 numpy arrays
+        updated in place; p0, target, b stacked (npairs, n, n, n) float32
+        device tensors; hist ((K+1), n, n, n) float32.  Returns the mean loss
+        before the update."""
+        assert w.dtype == np.float64 and w.size == 28 and adam.dtype == np.float64 and adam.size == 56
+        loss = c_double(0.0)
+        self._chk(lib().sim_percnn_fit_step(
+            self.ctx, w.ctypes.data_as(POINTER(c_double)), adam.ctypes.data_as(POINTER(c_double)),
+            int(step), float(lr), int(K), int(p0.shape[0]), _ptr(p0), _ptr(target), _ptr(b),
+            _ptr(hist), byref(loss)))
+        return loss.value
 
     def percnn_backward(self, w, K, b, hist, g, gp0=None, gb=None):
         """Reverse pass: returns dL/d(W, w_b) (28 float64) and fills gp0, gb."""

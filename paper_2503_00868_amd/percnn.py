@@ -9,7 +9,8 @@ p_after = the projection's pressure, b = the projection's right-hand side)
 for one velocity field on the context's mask, and the fit minimises the
 mean over pairs of the sum over liquid cells of
 (layer^K(p_before) - p_after)^2 over the 28 weights (W_0 .. W_26, w_b) by
-Adam, with the gradient from the library's reverse pass.  Starting from the
+Adam, each step one library call (loss, seed gradient, reverse pass and
+update inside the library).  Starting from the
 Jacobi kernel, the fit finds a kernel whose K layers come closer to the
 solution than K Jacobi sweeps.
 
@@ -73,30 +74,23 @@ def rel_error(sim, w, K, pairs):
 
 
 def fit(sim, pairs, K, steps=100, lr=2e-3, w0=None, log=None):
-    """Adam on the 28 weights; returns (w, per-step mean loss)."""
+    """Adam on the 28 weights, one library call per step
+    (sim_percnn_fit_step: the loss, its seed gradient and the reverse pass on
+    the device, the Adam update in the library); returns (w, per-step mean
+    loss)."""
     torch = sim.torch
     n = sim.n
-    L = liquid_mask(sim)
     w = np.array(jacobi_weights() if w0 is None else w0, dtype=np.float64)
-    m = np.zeros(28)
-    v = np.zeros(28)
+    adam = np.zeros(56)
+    p0 = torch.stack([pb for pb, _, _ in pairs]).contiguous()
+    target = torch.stack([pa for _, pa, _ in pairs]).contiguous()
+    b = torch.stack([bb for _, _, bb in pairs]).contiguous()
     hist = torch.empty((K + 1, n, n, n), dtype=torch.float32, device=sim.device)
     losses = []
     for it in range(1, steps + 1):
-        loss, grad = 0.0, np.zeros(28)
-        for pb, pa, b in pairs:
-            sim.percnn_forward(w, K, pb, b, hist=hist)
-            err = L * (hist[K] - pa)
-            loss += float((err * err).sum())
-            grad += sim.percnn_backward(w, K, b, hist, (2.0 * err).contiguous())
-        loss /= len(pairs)
-        grad /= len(pairs)
-        losses.append(loss)
-        m = 0.9 * m + 0.1 * grad
-        v = 0.999 * v + 0.001 * grad * grad
-        w -= lr * (m / (1 - 0.9 ** it)) / (np.sqrt(v / (1 - 0.999 ** it)) + 1e-12)
+        losses.append(sim.percnn_fit_step(w, adam, it, lr, K, p0, target, b, hist))
         if log and (it % max(1, steps // 10) == 0 or it == 1):
-            log(f"step {it}: loss {loss:.4e}")
+            log(f"step {it}: loss {losses[-1]:.4e}")
     return w, losses
 
 

@@ -202,3 +202,38 @@ def test_autograd_function_matches_oracle(torch_gpu):
     e_b = np.abs(bt.grad.cpu().numpy() - r_gb).max() / np.abs(r_gb).max()
     banner(f"  rel err dW {e_w:.2e} dp0 {e_p:.2e} db {e_b:.2e}")
     assert e_w < 1e-5 and e_p < 1e-5 and e_b < 1e-5
+
+
+def test_fit_step_matches_oracle(torch_gpu):
+    """One sim_percnn_fit_step on two pairs: the mean loss against the
+    oracle's fit loss, and the Adam update of the first step, which moves
+    every weight by lr * g / |g| (g the oracle's mean gradient), to within
+    the FP32 rounding of the weights' gradient."""
+    torch = torch_gpu
+    n, K = 24, 6
+    banner(f"percnn fit step n={n} K={K}")
+    cell, p0a, ba = _case(n, 11)
+    _, p0b, bb = _case(n, 12)
+    rng = np.random.default_rng(5)
+    liquid = cell == inputs.LIQUID
+    ta = np.where(liquid, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    tb = np.where(liquid, rng.standard_normal((n, n, n)), 0.0).astype(np.float32)
+    w = _weights(3).astype(np.float64)
+    w32 = w.astype(np.float32).astype(np.float64)
+    sim = _sim(cell)
+    dev = lambda *a: torch.as_tensor(np.stack(a), device="cuda")
+    hist = torch.empty((K + 1, n, n, n), dtype=torch.float32, device="cuda")
+    adam = np.zeros(56)
+    w_new = w.copy()
+    lr = 1e-3
+    loss = sim.percnn_fit_step(w_new, adam, 1, lr, K, dev(p0a, p0b), dev(ta, tb), dev(ba, bb), hist)
+    pairs = [(p0a.astype(np.float64), ta.astype(np.float64), ba.astype(np.float64)),
+             (p0b.astype(np.float64), tb.astype(np.float64), bb.astype(np.float64))]
+    ref_loss, gW, gwb = orc_pc.fit_loss(cell, pairs, w32[:27], w32[27], K)
+    g = np.concatenate([gW, [gwb]])
+    banner(f"  loss {loss:.8e} vs {ref_loss:.8e}")
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    np.testing.assert_allclose(adam[:28], 0.1 * g, rtol=1e-4, atol=1e-6 * np.abs(g).max())
+    # first Adam step: w - lr * g / |g| (the eps 1e-12 is negligible here)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    np.testing.assert_allclose((w - w_new)[big], lr * np.sign(g[big]), rtol=1e-6)
