@@ -36,8 +36,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 
-# Algorithmic bytes per unit (cell, or face for the viscosity CG) of each
-# timed kernel kind: every array the operation must read or write once.
+# Algorithmic bytes of each timed kernel kind: every array the operation
+# must read or write once.  Cell kinds count per cell (they stream every
+# cell).  Face kinds are (bytes per face over all 3F faces, bytes per active
+# face): the face code and the outputs a kernel writes on every face, plus
+# what it moves only on the active faces (the others it skips).
 BYTES_PER_UNIT = {
     "pcg_dir_spmv": 17.0,   # r 4 + diag 1 + d 4 in; d 4 + q 4 out (Jacobi; 21 flexible CG)
     # Jacobi PCG and the flexible CG update the FP64 iterate every fourth
@@ -46,13 +49,31 @@ BYTES_PER_UNIT = {
     # (MIC(0)-PCG updates x every iteration: 33 B.)
     "pcg_update": 21.0,
     "pcg_check": 17.0,      # x 8, b 4, diag 1 in; r 4 out
-    "advect": 9.0,          # own component 4 + face code 1 in; 4 out (per face)
-    "diffuse_explicit": 9.0,
-    "dcg_dir_spmv": 17.0,   # per face, as pcg_dir_spmv
-    "dcg_update": 33.0,
-    "advect_adjoint": 21.0,  # state 4 + lambda 4 + code 1 in; 3 x 4 scattered gradient
 }
-FACE_KINDS = {"advect", "diffuse_explicit", "dcg_dir_spmv", "dcg_update", "advect_adjoint"}
+FACE_BYTES = {
+    "advect": (5.0, 4.0),            # code 1 in, value 4 out everywhere; own component 4 in if active
+    "diffuse_explicit": (9.0, 0.0),  # value and code in, value out, every face
+    "dcg_dir_spmv": (17.0, 0.0),     # r 4, d 4, code 1 in; d 4, q 4 out, every face
+    "dcg_update": (1.0, 32.0),       # code 1 everywhere; x 8 + 8, r 4 + 4, d 4, q 4 if active
+    "advect_adjoint": (1.0, 20.0),   # code 1 everywhere; state 4, lambda 4 in, 3 x 4 scattered if active
+}
+FACE_KINDS = set(FACE_BYTES)
+
+
+def active_faces(cell):
+    """Faces that touch liquid and no solid cell (the box's outside is solid)."""
+    import numpy as np
+    c = np.pad(np.asarray(cell), 1, constant_values=2)
+    total = 0
+    for axis in (2, 1, 0):  # x, y, z faces
+        lo = [slice(1, -1)] * 3
+        hi = [slice(1, -1)] * 3
+        lo[axis] = slice(0, -1)
+        hi[axis] = slice(1, None)
+        a, b = c[tuple(lo)], c[tuple(hi)]
+        total += int(((a != 2) & (b != 2) & ((a == 1) | (b == 1))).sum())
+    return total
+
 
 # Recurrent convolutional pressure solver, per cell and layer: forward p 4,
 # b 4, diag 1 in, p 4 out; reverse g 4, diag 1, p 4, b 4 in, g 4 out, and the
@@ -221,21 +242,24 @@ def cpu_baseline(n, seed):
                       f"iterations per solve)"}
 
 
-def rooflines(prof, n, precond):
+def rooflines(prof, n, precond, n_active):
     """Roofline of the kernel kind with the most time in the timed region
     (the U-Net against the BF16 MFMA peak, every other kind against HBM),
-    and of the top HBM-bound kind."""
+    and of the top HBM-bound kind.  n_active: active faces of the mask."""
     C, F3 = n ** 3, 3 * (n + 1) * n * n
 
     def hbm(kind):
         ms_tot, launches = prof[kind]
-        units = F3 if kind in FACE_KINDS else C
-        per_unit = BYTES_PER_UNIT[kind]
-        if kind == "pcg_update" and precond == "mic0":
-            per_unit = 33.0
-        if kind == "pcg_dir_spmv" and precond == "learned":
-            per_unit = 21.0  # z 4 + d 4 + r 4 (the flexible-CG dot) + diag 1 in; d 4 + q 4 out
-        per_launch = per_unit * units
+        if kind in FACE_BYTES:
+            every, active = FACE_BYTES[kind]
+            per_launch = every * F3 + active * n_active
+        else:
+            per_unit = BYTES_PER_UNIT[kind]
+            if kind == "pcg_update" and precond == "mic0":
+                per_unit = 33.0
+            if kind == "pcg_dir_spmv" and precond == "learned":
+                per_unit = 21.0  # z 4 + d 4 + r 4 (the flexible-CG dot) + diag 1 in; d 4 + q 4 out
+            per_launch = per_unit * C
         avg_s = ms_tot / launches / 1e3
         achieved = per_launch / avg_s / 1e9
         return {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
@@ -243,7 +267,7 @@ def rooflines(prof, n, precond):
                 "traffic": load_traffic(kind, n, precond), "avg_us": round(avg_s * 1e6, 2),
                 "launches": launches, "bytes_per_launch": per_launch}
 
-    kinds = {k: v for k, v in prof.items() if k in BYTES_PER_UNIT and v[1] > 0}
+    kinds = {k: v for k, v in prof.items() if (k in BYTES_PER_UNIT or k in FACE_BYTES) and v[1] > 0}
     r_hbm = hbm(max(kinds, key=lambda k: kinds[k][0]))
     net_ms, net_launches = prof.get("net", (0.0, 0))
     if net_launches and net_ms > max(v[0] for v in kinds.values()):
@@ -783,7 +807,15 @@ def main():
         f"fwd mean {np.mean(fwd_iters):.1f}; adjoint iters {bwd_stats[-1]['iters']}; J={J:.4e} "
         f"dJ/dnu={dnu:.4e} dJ/ds={ds:.4e}")
 
-    roofline, roofline_hbm = rooflines(prof, n, precond)
+    n_active = active_faces(cell)
+    roofline, roofline_hbm = rooflines(prof, n, precond, n_active)
+    # every HBM kind of the timed region, for the record
+    roofline_all = {}
+    for k, v in prof.items():
+        if v[1] > 0 and (k in BYTES_PER_UNIT or k in FACE_BYTES):
+            r1, _ = rooflines({k: v}, n, precond, n_active)
+            roofline_all[k] = {q: r1[q] for q in ("achieved", "frac", "avg_us", "launches",
+                                                   "bytes_per_launch")}
     log("kernel time in the timed region (ms, launches): " +
         ", ".join(f"{k}={v[0]:.1f}/{v[1]}" for k, v in prof.items() if v[1]))
 
@@ -995,6 +1027,8 @@ def main():
                    "pressure_history": not args.no_pressure_history},
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
+        "roofline_all_hbm": roofline_all,
+        "active_faces": n_active,
         "peak_mem_bytes": peak_mem,
         "workspace_bytes": ws_bytes,
         "grad_fd": grad_fd,
