@@ -4,11 +4,19 @@
 // factor sigma = 0.25, in lexicographic cell order (x fastest), as in the
 // fluid-simulation text the paper defers to for its solver details
 // (Section 3.2.2).  The factor and both triangular solves have a dependency
-// along i+j+k: every cell needs its three lower (or upper) neighbours.  The
-// GPU processes one hyperplane i+j+k = s per launch; all cells of a plane
-// are independent.  That reproduces the sequential order exactly, so the
-// iterates match a sequential implementation up to rounding, at the cost of
-// 3n-2 dependent launches per sweep (latency-bound, not bandwidth-bound).
+// along i+j+k: every cell needs its three lower (or upper) neighbours.
+//
+// The factor (once per mask) processes one cell hyperplane i+j+k = s per
+// launch.  The two triangular solves of every application go by 8^3 tiles:
+// tiles on one tile hyperplane I+J+K = S are independent (their cells'
+// neighbours across tile faces lie in tiles of S-1, or S+1 going back), so
+// one launch per tile hyperplane, 3(n/8)-2 per sweep instead of 3n-2.  A
+// tile is one wave: lane (i', j') owns a column and takes cell k' at level
+// i'+j'+k'; the three neighbours a cell needs were produced at the level
+// before by lanes (i'-1, j'), (i', j'-1) and itself, so a level is two
+// cross-lane shuffles (16^3 tiles of four waves, with a barrier per level,
+// measured slower).  The order of the operations per cell is the
+// sequential one, so the result matches a sequential sweep up to rounding.
 #include "common.h"
 #include "ctx.h"
 
@@ -112,6 +120,127 @@ __global__ void k_mic0_bwd_plane(int n, int s, int k_lo, int k_count,
   z[c] = (q[c] + p * acc) * p;
 }
 
+constexpr int MT = 8;  // tile edge of the triangular solves: one wave per tile
+
+// Forward substitution on tile (I, J, S - I - J): q_c = (r_c + sum over the
+// lower liquid neighbours m of precon_m q_m) precon_c, zero off liquid.
+// Block = one wave, lane (i', j') = (lane % 8, lane / 8); grid (tiles_x,
+// tiles_y), the blocks off the hyperplane return at once.  Each lane's column inputs (r, precon, and what the neighbours
+// across the tile's x- and y-faces contribute) sit in LDS, one 16-byte word
+// per cell, so that a level reads its cell with one LDS load; the x- and
+// y-neighbours inside the tile come from the lanes beside it by shuffles.
+__global__ void __launch_bounds__(64)
+    k_mic0_fwd_tile(int n, int S, const uint8_t* __restrict__ cdiag,
+                    const float* __restrict__ precon, const float* __restrict__ r,
+                    float* __restrict__ q, const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  __shared__ float4 in_l[MT][64];
+  __shared__ float out_l[MT][64];
+  const int tn = (n + MT - 1) / MT;
+  const int I = blockIdx.x, J = blockIdx.y, K = S - I - J;
+  if (K < 0 || K >= tn) return;
+  const int lane = threadIdx.x, li = lane % MT, lj = lane / MT;
+  const int x = I * MT + li, y = J * MT + lj, z0 = K * MT;
+  const bool col_ok = x < n && y < n;
+  const int64_t sy = n, sz = (int64_t)n * n;
+  // precon_m q_m of the neighbours across the tile's faces (zero outside
+  // the box and off liquid, where precon and q are zero)
+#pragma unroll
+  for (int k = 0; k < MT; ++k) {
+    const int zz = z0 + k;
+    const bool ok = col_ok && zz < n;
+    const int64_t c = x + sy * y + sz * zz;
+    float4 v;
+    v.x = ok && cdiag[c] ? r[c] : 0.f;
+    v.y = ok ? precon[c] : 0.f;
+    v.z = ok && li == 0 && x > 0 ? precon[c - 1] * q[c - 1] : 0.f;
+    v.w = ok && lj == 0 && y > 0 ? precon[c - sy] * q[c - sy] : 0.f;
+    in_l[k][lane] = v;
+  }
+  const float wz = col_ok && z0 > 0 ? precon[x + sy * y + sz * (z0 - 1)] * q[x + sy * y + sz * (z0 - 1)] : 0.f;
+  wave_sync();
+  float w_last = 0.f;  // precon q of this lane's previous cell
+#pragma unroll
+  for (int L = 0; L < 3 * MT - 2; ++L) {
+    const float from_x = __shfl(w_last, (lane + 63) & 63);  // lane (i' - 1, j')
+    const float from_y = __shfl(w_last, (lane + 56) & 63);  // lane (i', j' - 1)
+    const int k = L - li - lj;
+    if (k >= 0 && k < MT) {
+      const float4 v = in_l[k][lane];
+      float t = v.x;
+      t += li > 0 ? from_x : v.z;
+      t += lj > 0 ? from_y : v.w;
+      t += k > 0 ? w_last : wz;
+      const float qc = t * v.y;
+      out_l[k][lane] = qc;
+      w_last = v.y * qc;
+    }
+  }
+  wave_sync();
+  if (col_ok) {
+#pragma unroll
+    for (int k = 0; k < MT; ++k)
+      if (z0 + k < n) q[x + sy * y + sz * (z0 + k)] = out_l[k][lane];
+  }
+}
+
+// Back substitution on tile (I, J, S - I - J): z_c = (q_c + precon_c sum over
+// the upper liquid neighbours m of z_m) precon_c, zero off liquid; the levels
+// in reverse, the neighbours from lanes (i' + 1, j'), (i', j' + 1).
+__global__ void __launch_bounds__(64)
+    k_mic0_bwd_tile(int n, int S, const uint8_t* __restrict__ cdiag,
+                    const float* __restrict__ precon, const float* __restrict__ q,
+                    float* __restrict__ zout, const int* __restrict__ flags) {
+  if (flags && flags[F_DONE]) return;
+  __shared__ float4 in_l[MT][64];
+  __shared__ float out_l[MT][64];
+  const int tn = (n + MT - 1) / MT;
+  const int I = blockIdx.x, J = blockIdx.y, K = S - I - J;
+  if (K < 0 || K >= tn) return;
+  const int lane = threadIdx.x, li = lane % MT, lj = lane / MT;
+  const int x = I * MT + li, y = J * MT + lj, z0 = K * MT;
+  const bool col_ok = x < n && y < n;
+  const int64_t sy = n, sz = (int64_t)n * n;
+#pragma unroll
+  for (int k = 0; k < MT; ++k) {
+    const int zz = z0 + k;
+    const bool ok = col_ok && zz < n;
+    const int64_t c = x + sy * y + sz * zz;
+    float4 v;
+    v.x = ok ? q[c] : 0.f;
+    v.y = ok ? precon[c] : 0.f;
+    v.z = ok && li == MT - 1 && x + 1 < n ? zout[c + 1] : 0.f;
+    v.w = ok && lj == MT - 1 && y + 1 < n ? zout[c + sy] : 0.f;
+    in_l[k][lane] = v;
+  }
+  const int ztop = z0 + MT;
+  const float uz = col_ok && ztop < n ? zout[x + sy * y + sz * ztop] : 0.f;
+  wave_sync();
+  float z_last = 0.f;  // z of this lane's previous (upper) cell
+#pragma unroll
+  for (int L = 3 * MT - 3; L >= 0; --L) {
+    const float from_x = __shfl(z_last, (lane + 1) & 63);  // lane (i' + 1, j')
+    const float from_y = __shfl(z_last, (lane + 8) & 63);  // lane (i', j' + 1)
+    const int k = L - li - lj;
+    if (k >= 0 && k < MT) {
+      const float4 v = in_l[k][lane];
+      float acc = 0.f;
+      acc += li < MT - 1 ? from_x : v.z;
+      acc += lj < MT - 1 ? from_y : v.w;
+      acc += k < MT - 1 ? z_last : uz;
+      const float zc = (v.x + v.y * acc) * v.y;
+      out_l[k][lane] = zc;
+      z_last = zc;
+    }
+  }
+  wave_sync();
+  if (col_ok) {
+#pragma unroll
+    for (int k = 0; k < MT; ++k)
+      if (z0 + k < n) zout[x + sy * y + sz * (z0 + k)] = out_l[k][lane];
+  }
+}
+
 void launch_mic0_setup(sim_ctx* c) {
   const int n = c->n;
   for (int s = 0; s <= 3 * (n - 1); ++s) {
@@ -124,19 +253,14 @@ void launch_mic0_setup(sim_ctx* c) {
 
 void launch_mic0_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
   const int n = c->n;
+  const int tn = (n + MT - 1) / MT;
   prof_mark(c, SIM_KERN_MIC0, true);
-  for (int s = 0; s <= 3 * (n - 1); ++s) {
-    PlaneRange pr = plane_range(n, s);
-    int threads = n * pr.k_count;
-    hipLaunchKernelGGL(k_mic0_fwd_plane, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       c->stream, n, s, pr.k_lo, pr.k_count, c->cdiag, c->precon, r, c->mq, flags);
-  }
-  for (int s = 3 * (n - 1); s >= 0; --s) {
-    PlaneRange pr = plane_range(n, s);
-    int threads = n * pr.k_count;
-    hipLaunchKernelGGL(k_mic0_bwd_plane, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       c->stream, n, s, pr.k_lo, pr.k_count, c->cdiag, c->precon, c->mq, z, flags);
-  }
+  for (int S = 0; S <= 3 * (tn - 1); ++S)
+    hipLaunchKernelGGL(k_mic0_fwd_tile, dim3(tn, tn), dim3(64), 0, c->stream, n, S, c->cdiag,
+                       c->precon, r, c->mq, flags);
+  for (int S = 3 * (tn - 1); S >= 0; --S)
+    hipLaunchKernelGGL(k_mic0_bwd_tile, dim3(tn, tn), dim3(64), 0, c->stream, n, S, c->cdiag,
+                       c->precon, c->mq, z, flags);
   prof_mark(c, SIM_KERN_MIC0, false);
 }
 
