@@ -77,49 +77,6 @@ __global__ void k_mic0_setup_plane(int n, int s, int k_lo, int k_count,
   precon[c] = (float)(1.0 / sqrt(e));
 }
 
-// q_c = (r_c + sum over lower liquid neighbours m of precon_m q_m) precon_c
-__global__ void k_mic0_fwd_plane(int n, int s, int k_lo, int k_count,
-                                 const uint8_t* __restrict__ cdiag,
-                                 const float* __restrict__ precon, const float* __restrict__ r,
-                                 float* __restrict__ q, const int* __restrict__ flags) {
-  if (flags && flags[F_DONE]) return;
-  int i, j, k;
-  if (!plane_cell(n, s, k_lo, k_count, i, j, k)) return;
-  const int64_t c = i + (int64_t)n * (j + (int64_t)n * k);
-  if (!cdiag[c]) {
-    q[c] = 0.f;
-    return;
-  }
-  float t = r[c];
-  const int64_t sy = n, sz = (int64_t)n * n;
-  if (i > 0 && cdiag[c - 1]) t += precon[c - 1] * q[c - 1];
-  if (j > 0 && cdiag[c - sy]) t += precon[c - sy] * q[c - sy];
-  if (k > 0 && cdiag[c - sz]) t += precon[c - sz] * q[c - sz];
-  q[c] = t * precon[c];
-}
-
-// z_c = (q_c + precon_c * sum over upper liquid neighbours m of z_m) precon_c
-__global__ void k_mic0_bwd_plane(int n, int s, int k_lo, int k_count,
-                                 const uint8_t* __restrict__ cdiag,
-                                 const float* __restrict__ precon, const float* __restrict__ q,
-                                 float* __restrict__ z, const int* __restrict__ flags) {
-  if (flags && flags[F_DONE]) return;
-  int i, j, k;
-  if (!plane_cell(n, s, k_lo, k_count, i, j, k)) return;
-  const int64_t c = i + (int64_t)n * (j + (int64_t)n * k);
-  if (!cdiag[c]) {
-    z[c] = 0.f;
-    return;
-  }
-  const int64_t sy = n, sz = (int64_t)n * n;
-  float acc = 0.f;
-  if (i < n - 1 && cdiag[c + 1]) acc += z[c + 1];
-  if (j < n - 1 && cdiag[c + sy]) acc += z[c + sy];
-  if (k < n - 1 && cdiag[c + sz]) acc += z[c + sz];
-  const float p = precon[c];
-  z[c] = (q[c] + p * acc) * p;
-}
-
 constexpr int MT = 8;  // tile edge of the triangular solves: one wave per tile
 
 // Forward substitution on tile (I, J, S - I - J): q_c = (r_c + sum over the
