@@ -160,6 +160,13 @@ def parse():
                    help="only measure adjoint vs central FD (exact and upwind convection "
                         "gradients) for these comma-separated rollout lengths and exit")
     p.add_argument("--cpu-n", type=int, default=128)
+    p.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "OUT", "TITLE", "COMMAND"),
+                   help="write a kernel-trace summary for profiles/ and exit (no GPU)")
+    p.add_argument("--summarize-traffic", nargs=5,
+                   metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "PRECOND"),
+                   help="write the per-kind traffic summaries for profiles/ and exit (no GPU)")
+    p.add_argument("--commands", nargs="*", default=[],
+                   help="the commands that produced the counter files (for --summarize-traffic)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
                         "byte counters) and exit")
@@ -662,6 +669,191 @@ def _rel(a, b):
     return abs(a - b) / abs(b) if b != 0 else float("inf")
 
 
+# ------------------------------------------------------------------ profiles
+# Summaries of rocprofv3 output for profiles/: the per-kind kernel patterns,
+# and the sources each kind's counters depend on (a summary whose sources
+# changed is no longer read).
+
+TRAFFIC_KINDS = {
+    # kind: (precond the run used, kernel name patterns, sources)
+    "pcg_dir_spmv": {"jacobi": ["k_dir_spmv_zm<0, false>"], "learned": ["k_dir_spmv_zm<1, true>"]},
+    "pcg_update": {"jacobi": ["k_update4<4, true, false>", "k_update4<4, false, false>"],
+                   "learned": ["k_update4<4, true, true>", "k_update4<4, false, true>"]},
+    "pcg_check": {"jacobi": ["k_check_zm<0>"], "learned": ["k_check_zm<1>"]},
+    "dcg_dir_spmv": {"learned": ["k_dcg_dir_spmv_zm"]},
+    "dcg_update": {"learned": ["k_dcg_update"]},
+    "net": {"learned": ["k_conv_in", "k_conv_zm", "k_upconv", "k_conv_out", "k_conv<",
+                        "k_convILi", "k_dot_cells"]},
+    "percnn": {"jacobi": ["k_percnn_layer("]},
+    "percnn_adj": {"jacobi": ["k_percnn_layer_adj"]},
+    "upwind": {"jacobi": ["k_convection_grad_upwind"]},
+}
+TRAFFIC_SOURCES = {
+    "pcg_dir_spmv": ["k_pcg.hip", "common.h"], "pcg_update": ["k_pcg.hip", "common.h"],
+    "pcg_check": ["k_pcg.hip", "common.h"], "dcg_dir_spmv": ["k_pcg.hip", "common.h"],
+    "dcg_update": ["k_pcg.hip", "common.h"],
+    "net": ["k_conv_zm.hip", "k_conv_in.hip", "k_conv_out.hip", "k_upconv.hip", "k_unet.hip",
+            "net.cpp", "common.h"],
+    "percnn": ["k_percnn.hip"], "percnn_adj": ["k_percnn.hip"], "upwind": ["upwind.hip"],
+}
+
+
+def _rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _demangle(name):
+    """A readable kernel name: strip argument lists of plain names."""
+    return name.split("(")[0] if "(" in name else name
+
+
+def _matches(name, pats):
+    return any(p in name for p in pats)
+
+
+def summarize_trace(trace_csv, out, title, command, net_launch_ratio=None):
+    """Markdown summary of a rocprofv3 --kernel-trace run (per-dispatch CSV):
+    per kernel the calls, total, and the average over the dispatches that did
+    work (longer than 5% of the kernel's longest; dispatches of a solve that
+    had already converged return at once), and the network's time per working
+    application (the sum of its kernels' working averages)."""
+    import collections
+    rows = _rows(trace_csv)
+    dur = collections.defaultdict(list)
+    for r in rows:
+        dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    total_all = sum(sum(v) for v in dur.values())
+    table = []
+    for k, v in dur.items():
+        mx = max(v)
+        work = [d for d in v if d >= 0.05 * mx]
+        table.append((sum(v), k, len(v), len(work), sum(work) / len(work), min(v), mx))
+    table.sort(reverse=True)
+    net_pats = TRAFFIC_KINDS["net"]["learned"]
+    net_us = sum(t[4] for t in table if _matches(t[1], net_pats))
+    lines = [f"# Kernel trace: {title}", "",
+             "Command (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first, "
+             "R = repository path):", "", "```", command, "```", "",
+             "Per kernel: calls, total time, and the average over the dispatches that did work "
+             "(longer than 5% of the kernel's longest: the CG kernels and the network return at "
+             "once when the solve has already converged).", "",
+             "| kernel | calls | working | total ms | avg us (working) | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for tot, k, calls, nw, avg, mn, mx in table[:40]:
+        lines.append(f"| `{_demangle(k)}` | {calls} | {nw} | {tot / 1e3:.1f} | {avg:.2f} | "
+                     f"{mn:.2f} | {mx:.2f} | {100 * tot / total_all:.2f} |")
+    lines += ["", f"The network's kernels per working application add up to **{net_us:.1f} us** "
+              "(one dispatch of each per application)."]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {out}; network {net_us:.1f} us per application")
+
+
+def _counter_by_dispatch(path, counter):
+    out = {}
+    for r in _rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        d = r["Dispatch_Id"]
+        out.setdefault(d, [r["Kernel_Name"], 0.0])
+        out[d][1] += float(r["Counter_Value"])
+    return out
+
+
+def _copy_factor(path, counter, mib):
+    vals = [v for _, v in _counter_by_dispatch(path, counter).values()]
+    big = sorted(vals)[-20:]
+    avg = sum(big) / len(big)
+    return mib * 1024.0 / avg, avg
+
+
+def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, precond, n, commands,
+                      out_dir, copy_mib=1024):
+    """Per-kind HBM traffic summaries from FETCH_SIZE and WRITE_SIZE passes
+    (KiB per dispatch), scaled by their reading for a plain copy of copy_mib
+    MiB, averaged over the working dispatches (above 5% of the kernel's
+    largest reading), with the SHA-256 of the sources the kind depends on."""
+    import hashlib
+    ff, fa = _copy_factor(copy_fetch_csv, "FETCH_SIZE", copy_mib)
+    wf, wa = _copy_factor(copy_write_csv, "WRITE_SIZE", copy_mib)
+    fetch = _counter_by_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _counter_by_dispatch(write_csv, "WRITE_SIZE")
+    C, F3 = n ** 3, 3 * (n + 1) * n * n
+    written = []
+    for kind, per in TRAFFIC_KINDS.items():
+        pats = per.get(precond)
+        if not pats:
+            continue
+
+        def per_kernel(table):
+            acc = {}
+            for name, v in table.values():
+                if _matches(name, pats):
+                    acc.setdefault(name, []).append(v)
+            res = {}
+            for name, vs in acc.items():
+                mx = max(vs)
+                w = [x for x in vs if x >= 0.05 * mx]
+                res[name] = (len(w), sum(w) / len(w))
+            return res
+        kf, kw = per_kernel(fetch), per_kernel(write)
+        if not kf:
+            continue
+        rows, tot_f, tot_w = [], 0.0, 0.0
+        for name in sorted(kf):
+            nf, af = kf[name]
+            nw, aw = kw.get(name, (0, 0.0))
+            share = 1.0
+            if kind == "pcg_update":  # one dispatch in four updates the FP64 iterate
+                share = 0.25 if "true" in name.split(",")[1] else 0.75
+            tot_f += share * af * 1024 * ff
+            tot_w += share * aw * 1024 * wf
+            rows.append(f"| `{_demangle(name)}` | {nf} | {af:.0f} | {aw:.0f} | "
+                        f"{(af * ff + aw * wf) * 1024 / 1e6:.1f} MB |")
+        if kind == "net":
+            alg = None
+        elif kind in BYTES_PER_UNIT:
+            per_unit = BYTES_PER_UNIT[kind]
+            if kind == "pcg_dir_spmv" and precond == "learned":
+                per_unit = 21.0
+            alg = per_unit * C
+        elif kind in FACE_BYTES:
+            alg = None  # depends on the mask's active faces: stated in the text below
+        else:
+            alg = {"percnn": PERCNN_BYTES["percnn"] * C, "percnn_adj": PERCNN_BYTES["percnn_adj"] * C,
+                   "upwind": UPWIND_BYTES * F3}.get(kind)
+        srcs = {f"paper_2503_00868_amd/csrc/{f}": hashlib.sha256(
+            open(os.path.join(ROOT, "paper_2503_00868_amd", "csrc", f), "rb").read()).hexdigest()
+            for f in TRAFFIC_SOURCES[kind]}
+        total = tot_f + tot_w
+        lines = [f"# HBM traffic: `{kind}` at {n}^3 ({precond} run)", "",
+                 "Commands (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first, "
+                 "R = repository path), one pass per counter:", "", "```"] + commands + [
+                 "```", "",
+                 f"Scale factors from a plain copy of {copy_mib} MiB (`bench.py --copy-probe "
+                 f"{copy_mib}`, 20 copies): FETCH_SIZE reads {fa:.0f} KiB per copy (x {ff:.3f}), "
+                 f"WRITE_SIZE {wa:.0f} KiB (x {wf:.3f}).  Averages are over the dispatches that did "
+                 "work (above 5% of the kernel's largest reading).", "",
+                 "| kernel | working dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |",
+                 "|---|---:|---:|---:|---:|"] + rows + [
+                 "", f"Per launch of the `{kind}` kind: **{total / 1e6:.1f} MB** "
+                 f"(reads {tot_f / 1e6:.1f} MB, writes {tot_w / 1e6:.1f} MB)"
+                 + (f" against {alg / 1e6:.1f} MB algorithmic ({total / alg:.2f}x)." if alg else "."),
+                 "", "bench-traffic: " + json.dumps({"kind": kind, "precond": precond, "n": n,
+                                                     "bytes_per_launch": int(total),
+                                                     "read_bytes": int(tot_f),
+                                                     "write_bytes": int(tot_w),
+                                                     "sources": srcs})]
+        path = os.path.join(out_dir, f"{kind}_{precond}_{n}_traffic.md")
+        with open(path, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        written.append(path)
+        print(f"wrote {path}: {total / 1e6:.1f} MB per launch")
+    return written
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -670,6 +862,13 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        fc, wc, cf, cw, pc = args.summarize_traffic
+        summarize_traffic(fc, wc, cf, cw, pc, args.n, args.commands, os.path.join(ROOT, "profiles"))
         return
     import numpy as np
     import torch
