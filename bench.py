@@ -160,6 +160,14 @@ def parse():
                    help="only measure adjoint vs central FD (exact and upwind convection "
                         "gradients) for these comma-separated rollout lengths and exit")
     p.add_argument("--cpu-n", type=int, default=128)
+    p.add_argument("--workload", default="rollout",
+                   choices=["rollout", "forward128", "grad128", "learned128"],
+                   help="rollout: the benchmark (default).  The others measure the smaller "
+                        "workloads the method is also checked on and print their own JSON line: "
+                        "forward128 = 16-step MIC(0)-PCG forward rollout at 128^3; grad128 = "
+                        "32-step differentiable rollout at 128^3 (checkpoint every 8), adjoint "
+                        "gradient against central FD; learned128 = learned preconditioner "
+                        "against MIC(0)-PCG at 128^3 (held-out masks)")
     p.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "OUT", "TITLE", "COMMAND"),
                    help="write a kernel-trace summary for profiles/ and exit (no GPU)")
     p.add_argument("--summarize-traffic", nargs=5,
@@ -854,6 +862,163 @@ def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, prec
     return written
 
 
+def workload_128(args, dev, weights):
+    """The smaller workloads at 128^3 (one JSON line each; not the benchmark).
+
+    forward128: 16 steps of the forward step with MIC(0)-PCG to 1e-6 on the
+    seed's mask and velocity, nu drawn log-uniformly from [1e-4, 1e-1] for the
+    seed (implicit viscosity when nu dt / h^2 > 1/12), timed after a warmup,
+    with every HBM kind's roofline from the timing hooks and the FP64 oracle's
+    forward step on the same state timed on the host.
+    grad128: a 32-step differentiable rollout (checkpoint every 8, MSE against
+    a target from (nu*, s*)), the adjoint's dJ/dtheta_nu and dJ/dtheta_s (exact
+    and upwind convection gradients) against central FD with h = 1e-3 in
+    theta = log(param), solves to 1e-7.
+    learned128: one cold projection per held-out mask (seeds 900..903, state
+    after one step) with the learned preconditioner and with MIC(0)-PCG, and
+    the 16-step rollout of forward128 with each: iterations and wall time."""
+    import numpy as np
+    import torch
+
+    from paper_2503_00868_amd import inputs
+    from paper_2503_00868_amd.fluidsim import Sim
+
+    n, dt, g = 128, 1.0 / 120, (0.0, -9.8, 0.0)
+    seed = args.seed
+    cell, ug = inputs.gen_case(n, seed)
+    nu = inputs.gen_nu(seed)
+    lam = nu * dt * n * n
+    out = {"workload": args.workload, "n": n, "seed": seed, "nu": nu,
+           "viscosity": "explicit" if lam <= 1.0 / 12 else "implicit",
+           "liquid_fraction": round(inputs.liquid_fraction(cell), 4), "dtype": "f32 (FP64 iterate, dots and residual)",
+           "data": "synthetic (seeded slab + ellipsoids mask, curl-of-potential velocity)"}
+
+    def rollout_time(pc, steps, on_cell=cell, on_ug=ug, profile=False):
+        s = Sim(on_cell, precond=pc, tol=1e-6, diff_tol=1e-6, max_iter=20000,
+                check_every=4 if pc != "jacobi" else 16, warm_start=True, device=dev)
+        if pc == "learned":
+            s.net_set_weights(weights)
+        s.set_params(nu=nu, dt=dt, s=1.0, gravity=g)
+        ugen = s.to_faces(on_ug)
+        u = s.faces()
+        s.init_state(ugen, u)
+        s.step(u, 2)
+        s.init_state(ugen, u)
+        torch.cuda.synchronize()
+        if profile:
+            s.profile_enable(True)
+        t0 = time.perf_counter()
+        st = s.step(u, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = s.profile_read() if profile else None
+        s.close()
+        return el, st, prof
+
+    if args.workload == "forward128":
+        el, st, prof = rollout_time("mic0", 16, profile=True)
+        out["precond"] = "mic0"
+        out["steps"] = 16
+        out["ms"] = round(el * 1e3, 1)
+        out["value"] = n ** 3 * 16 / el
+        out["unit"] = "cell-steps/s"
+        out["pressure_iters_mean"] = float(np.mean([q["iters"] for q in st]))
+        n_active = active_faces(cell)
+        out["rooflines"] = {}
+        for k, v in prof.items():
+            if v[1] > 0 and (k in BYTES_PER_UNIT or k in FACE_BYTES):
+                r1, _ = rooflines({k: v}, n, "mic0", n_active)
+                out["rooflines"][k] = {q: r1[q] for q in ("achieved", "frac", "avg_us", "launches",
+                                                         "bytes_per_launch")}
+        out["kernel_ms"] = {k: round(v[0], 2) for k, v in prof.items() if v[1]}
+        log(f"forward128: {el * 1e3:.1f} ms for 16 steps, {out['value']:.3e} cell-steps/s, "
+            f"{out['pressure_iters_mean']:.1f} MIC(0) iterations per projection")
+        if not args.no_cpu_baseline:
+            from oracle import fluid as orc
+            u0 = orc.mask_faces(cell, ug)
+            orc.lib()
+            t0 = time.perf_counter()
+            _, info = orc.step(cell, u0, nu, dt, tol=1e-6, diff_tol=1e-6)
+            t_f = time.perf_counter() - t0
+            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+            out["cpu_baseline"] = {"value": n ** 3 / t_f, "unit": "cell-steps/s", "cores": threads,
+                                   "kind": "oracle", "cpu_model": cpu_model(),
+                                   "sample": f"one forward step of the FP64 oracle at {n}^3 from the "
+                                             f"same state ({t_f:.1f} s; plain CG to 1e-6, "
+                                             f"{info.proj_iters} iterations)"}
+            log(f"oracle forward step: {t_f:.1f} s")
+    elif args.workload == "grad128":
+        T, K = 32, 8
+        nu_t, s_t = inputs.gen_nu(100), inputs.gen_scale(100)
+        nu_e, s_e = inputs.gen_nu(101), inputs.gen_scale(101)
+        tsim = Sim(cell, precond="jacobi", tol=1e-7, diff_tol=1e-7, max_iter=20000,
+                   check_every=16, warm_start=True, device=dev)
+        ugen = tsim.to_faces(ug)
+        tsim.set_params(nu=nu_t, dt=dt, s=s_t, gravity=g)
+        target = tsim.faces()
+        tsim.init_state(ugen, target)
+        tsim.step(target, T)
+        torch.cuda.synchronize()
+        tsim.close()
+        out.update({"rollout": T, "checkpoint_every": K, "nu_eval": nu_e, "s_eval": s_e,
+                    "target": {"nu": nu_t, "s": s_t}, "tol": 1e-7, "fd_h": 1e-3, "precond": "mic0"})
+        for conv in ("exact", "upwind"):
+            gs = Sim(cell, precond="mic0", tol=1e-7, diff_tol=1e-7, max_iter=20000, check_every=4,
+                     checkpoint_every=K, max_steps=T, warm_start=True, store_pressures=False,
+                     convection_grad=conv, device=dev)
+            t0 = time.perf_counter()
+            out[conv] = adjoint_gradient(gs, ugen, target, nu_e, s_e, dt, g, T)
+            torch.cuda.synchronize()
+            out[conv]["ms_forward_backward"] = round((time.perf_counter() - t0) * 1e3, 1)
+            if conv == "exact":
+                out["fd"] = fd_gradient(gs, ugen, target, nu_e, s_e, dt, g, T)
+            gs.close()
+        for conv in ("exact", "upwind"):
+            for key in ("dtheta_nu", "dtheta_s"):
+                out[conv]["rel_err_" + key] = _rel(out[conv][key], out["fd"][key])
+        log(f"grad128: FD {out['fd']}; exact {out['exact']['dtheta_nu']:.5e} "
+            f"{out['exact']['dtheta_s']:.5e}; upwind {out['upwind']['dtheta_nu']:.5e} "
+            f"{out['upwind']['dtheta_s']:.5e}")
+    else:
+        if weights is None:
+            raise SystemExit("learned128 needs the trained weights")
+        proj = []
+        for hs in range(900, 904):
+            hcell, hug = inputs.gen_case(n, hs)
+            row = {"seed": hs}
+            for pc in ("learned", "mic0"):
+                s = Sim(hcell, precond=pc, tol=1e-6, max_iter=20000, check_every=4, device=dev)
+                if pc == "learned":
+                    s.net_set_weights(weights)
+                s.set_params(nu=nu, dt=dt, s=1.0, gravity=g)
+                ugen = s.to_faces(hug)
+                u = s.faces()
+                s.init_state(ugen, u)
+                s.step(u, 1)
+                s.project(u)  # warm the code path; the timed solve starts cold below
+                s.init_state(ugen, u)
+                s.step(u, 1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, _ = s.project(u)
+                torch.cuda.synchronize()
+                row[pc] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iters": st["iters"],
+                           "rel_residual": st["rel_residual"]}
+                s.close()
+            log(f"learned128 seed {hs}: learned {row['learned']}, mic0 {row['mic0']}")
+            proj.append(row)
+        out["projections"] = proj
+        out["rollout16"] = {}
+        for pc in ("learned", "mic0"):
+            el, st, _ = rollout_time(pc, 16)
+            out["rollout16"][pc] = {"ms": round(el * 1e3, 1),
+                                    "pressure_iters_mean": float(np.mean([q["iters"] for q in st]))}
+            log(f"learned128 rollout with {pc}: {el * 1e3:.1f} ms")
+        out["rollout16"]["learned_over_mic0"] = (out["rollout16"]["mic0"]["ms"] /
+                                                 out["rollout16"]["learned"]["ms"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -894,6 +1059,9 @@ def main():
             raise SystemExit(f"no trained weights at {args.weights}")
         else:
             precond = "jacobi"
+    if args.workload != "rollout":
+        workload_128(args, dev, weights)
+        return
     log(f"n={n} rollout={T} checkpoint={K} precond={precond}")
 
     cell, ug = inputs.gen_case(n, args.seed)
