@@ -170,8 +170,7 @@ def parse():
                         "against MIC(0)-PCG at 128^3 (held-out masks)")
     p.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "OUT", "TITLE", "COMMAND"),
                    help="write a kernel-trace summary for profiles/ and exit (no GPU)")
-    p.add_argument("--summarize-traffic", nargs=5,
-                   metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "PRECOND"),
+    p.add_argument("--summarize-traffic", nargs=3, metavar=("RUN_CSV", "COPY_CSV", "PRECOND"),
                    help="write the per-kind traffic summaries for profiles/ and exit (no GPU)")
     p.add_argument("--commands", nargs="*", default=[],
                    help="the commands that produced the counter files (for --summarize-traffic)")
@@ -183,7 +182,7 @@ def parse():
 
 def copy_probe(mib):
     """Twenty device-to-device copies of `mib` MiB with torch's copy kernel:
-    the reference for scaling FETCH_SIZE / WRITE_SIZE counter readings."""
+    the check of the HBM byte counters' readings."""
     import torch
     a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -542,7 +541,8 @@ def loss_bench(cell, ugen, nu, s, dt, g, dev, reps=10):
     return {"J": J, "us_per_call": round(us, 2),
             "roofline": {"bound": "hbm", "kernel": "k_loss_cells + k_loss_fold + k_loss_face_grad",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": load_traffic("loss", n, "jacobi"),
                          "avg_us": round(us, 2), "bytes_per_call": LOSS_BYTES * cells}}
 
 
@@ -554,7 +554,7 @@ def screen_bytes_per_iter(f):
     return 33.0 + 1.0 + 56.0 * f
 
 
-def screen_bench(dev, H=1080, W=1920, seed=7, reps=3):
+def screen_bench(dev, H=1080, W=1920, seed=7, reps=3, traffic_n=256):
     """The paper's screen-space constrained projection on a 1080 x 1920 frame
     of the seeded generator, to a 1e-9 relative residual: ms per call,
     iterations, and the HBM rate of its CG iterations."""
@@ -585,7 +585,8 @@ def screen_bench(dev, H=1080, W=1920, seed=7, reps=3):
             "ms_per_call": round(t, 3),
             "roofline": {"bound": "hbm", "kernel": "k_s2_dir_spmv + k_s2_update (+ 2 finalize)",
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": load_traffic("screen", traffic_n, "jacobi"),
                          "avg_us_per_iter": round(per_iter_s * 1e6, 2),
                          "bytes_per_iter": screen_bytes_per_iter(f) * H * W}}
 
@@ -635,17 +636,19 @@ def apic_bench(cell, dev, per_cell=8, reps=5):
     g2p_bytes = 72.0 * P + 12.0 * F
     sim.close()
 
-    def rl(name, byts, us):
+    def rl(name, kind, byts, us):
         ach = byts / (us * 1e-6) / 1e9
         return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(kind, n, "jacobi") if per_cell == 8 else None,
                 "avg_us": round(us, 2), "bytes_per_call": byts}
     return {"particles": P, "per_liquid_cell": per_cell, "p2g_us": round(p2g_us, 1),
             "g2p_us": round(g2p_us, 1),
             "p2g_particles_per_s": P / (p2g_us * 1e-6),
             "g2p_particles_per_s": P / (g2p_us * 1e-6),
-            "roofline_p2g": rl("k_apic_zero + k_apic_p2g + k_apic_normalize", p2g_bytes, p2g_us),
-            "roofline_g2p": rl("k_apic_g2p", g2p_bytes, g2p_us)}
+            "roofline_p2g": rl("k_apic_zero + k_apic_p2g + k_apic_normalize", "apic_p2g", p2g_bytes,
+                               p2g_us),
+            "roofline_g2p": rl("k_apic_g2p", "apic_g2p", g2p_bytes, g2p_us)}
 
 
 def fd_gradient(sim, ugen, target, nu, s, dt, g, T, h=1e-3):
@@ -695,15 +698,31 @@ TRAFFIC_KINDS = {
     "percnn": {"jacobi": ["k_percnn_layer("]},
     "percnn_adj": {"jacobi": ["k_percnn_layer_adj"]},
     "upwind": {"jacobi": ["k_convection_grad_upwind"]},
+    "advect": {"learned": ["k_advect("]},
+    "advect_adjoint": {"learned": ["k_advect_adjoint"]},
+    "constrained": {"jacobi": ["k_cp_lambda", "k_pressure_update"]},
+    "loss": {"jacobi": ["k_loss_cells", "k_loss_fold", "k_loss_face_grad"]},
+    "screen": {"jacobi": ["k_s2_dir_spmv", "k_s2_update"]},
+    "apic_p2g": {"jacobi": ["k_apic_zero", "k_apic_p2g", "k_apic_normalize"]},
+    "apic_g2p": {"jacobi": ["k_apic_g2p"]},
 }
 TRAFFIC_SOURCES = {
     "pcg_dir_spmv": ["k_pcg.hip", "common.h"], "pcg_update": ["k_pcg.hip", "common.h"],
     "pcg_check": ["k_pcg.hip", "common.h"], "dcg_dir_spmv": ["k_pcg.hip", "common.h"],
     "dcg_update": ["k_pcg.hip", "common.h"],
     "net": ["k_conv_zm.hip", "k_conv_in.hip", "k_conv_out.hip", "k_upconv.hip", "k_unet.hip",
-            "net.cpp", "common.h"],
+            "net.cpp", "common.h", "block_or.h"],
     "percnn": ["k_percnn.hip"], "percnn_adj": ["k_percnn.hip"], "upwind": ["upwind.hip"],
+    "advect": ["k_step.hip", "common.h"], "advect_adjoint": ["k_step.hip", "common.h"],
+    "constrained": ["constrained.hip", "common.h"], "loss": ["loss.hip", "common.h"],
+    "screen": ["screen2d.hip", "common.h"], "apic_p2g": ["apic.hip"], "apic_g2p": ["apic.hip"],
 }
+# Counter passes the summaries read: the L2's read and write requests to the
+# memory side in 32-byte units (a 64-byte request counts 2, a 128-byte read 4),
+# so bytes = 32 x count with no assumption about request sizes; both fit one
+# pass (two TCC counters).
+DRAM_READ = "TCC_EA0_RDREQ_DRAM_32B_sum"
+DRAM_WRITE = "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"
 
 
 def _rows(path):
@@ -713,7 +732,9 @@ def _rows(path):
 
 
 def _demangle(name):
-    """A readable kernel name: strip argument lists of plain names."""
+    """A readable kernel name: strip argument lists of plain names (keeping
+    the names of kernels in anonymous namespaces)."""
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0] if "(" in name else name
 
 
@@ -770,25 +791,22 @@ def _counter_by_dispatch(path, counter):
     return out
 
 
-def _copy_factor(path, counter, mib):
-    vals = [v for _, v in _counter_by_dispatch(path, counter).values()]
-    big = sorted(vals)[-20:]
-    avg = sum(big) / len(big)
-    return mib * 1024.0 / avg, avg
-
-
-def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, precond, n, commands,
-                      out_dir, copy_mib=1024):
-    """Per-kind HBM traffic summaries from FETCH_SIZE and WRITE_SIZE passes
-    (KiB per dispatch), scaled by their reading for a plain copy of copy_mib
-    MiB, averaged over the working dispatches (above 5% of the kernel's
-    largest reading), with the SHA-256 of the sources the kind depends on."""
+def summarize_traffic(run_csv, copy_csv, precond, n, commands, out_dir, copy_mib=1024, seed=4):
+    """Per-kind HBM traffic summaries from one counter pass over a bench run
+    (DRAM_READ and DRAM_WRITE per dispatch, 32-byte units), averaged over the
+    working dispatches (above 5% of the kernel's largest reading), with the
+    same counters' reading for plain copies of copy_mib MiB as the check of
+    the byte count, and the SHA-256 of the sources each kind depends on."""
     import hashlib
-    ff, fa = _copy_factor(copy_fetch_csv, "FETCH_SIZE", copy_mib)
-    wf, wa = _copy_factor(copy_write_csv, "WRITE_SIZE", copy_mib)
-    fetch = _counter_by_dispatch(fetch_csv, "FETCH_SIZE")
-    write = _counter_by_dispatch(write_csv, "WRITE_SIZE")
+    rd = _counter_by_dispatch(run_csv, DRAM_READ)
+    wr = _counter_by_dispatch(run_csv, DRAM_WRITE)
+    crd = sorted(v for _, v in _counter_by_dispatch(copy_csv, DRAM_READ).values())[-20:]
+    cwr = sorted(v for _, v in _counter_by_dispatch(copy_csv, DRAM_WRITE).values())[-20:]
+    copy_bytes = copy_mib * (1 << 20)
+    copy_r = 32.0 * sum(crd) / len(crd) / copy_bytes
+    copy_w = 32.0 * sum(cwr) / len(cwr) / copy_bytes
     C, F3 = n ** 3, 3 * (n + 1) * n * n
+    n_active = None
     written = []
     for kind, per in TRAFFIC_KINDS.items():
         pats = per.get(precond)
@@ -799,66 +817,76 @@ def summarize_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, prec
             acc = {}
             for name, v in table.values():
                 if _matches(name, pats):
-                    acc.setdefault(name, []).append(v)
+                    acc.setdefault(name, []).append(32.0 * v)
             res = {}
             for name, vs in acc.items():
                 mx = max(vs)
                 w = [x for x in vs if x >= 0.05 * mx]
                 res[name] = (len(w), sum(w) / len(w))
             return res
-        kf, kw = per_kernel(fetch), per_kernel(write)
-        if not kf:
+        kr, kw = per_kernel(rd), per_kernel(wr)
+        if not kr:
             continue
-        rows, tot_f, tot_w = [], 0.0, 0.0
-        for name in sorted(kf):
-            nf, af = kf[name]
+        rows, tot_r, tot_w = [], 0.0, 0.0
+        for name in sorted(kr):
+            nr, ar = kr[name]
             nw, aw = kw.get(name, (0, 0.0))
             share = 1.0
             if kind == "pcg_update":  # one dispatch in four updates the FP64 iterate
                 share = 0.25 if "true" in name.split(",")[1] else 0.75
-            tot_f += share * af * 1024 * ff
-            tot_w += share * aw * 1024 * wf
-            rows.append(f"| `{_demangle(name)}` | {nf} | {af:.0f} | {aw:.0f} | "
-                        f"{(af * ff + aw * wf) * 1024 / 1e6:.1f} MB |")
-        if kind == "net":
-            alg = None
-        elif kind in BYTES_PER_UNIT:
+            tot_r += share * ar
+            tot_w += share * aw
+            rows.append(f"| `{_demangle(name)}` | {nr} | {ar / 1e6:.1f} | {aw / 1e6:.1f} | "
+                        f"{(ar + aw) / 1e6:.1f} |")
+        alg = None
+        if kind in BYTES_PER_UNIT:
             per_unit = BYTES_PER_UNIT[kind]
             if kind == "pcg_dir_spmv" and precond == "learned":
                 per_unit = 21.0
             alg = per_unit * C
         elif kind in FACE_BYTES:
-            alg = None  # depends on the mask's active faces: stated in the text below
+            if n_active is None:
+                from paper_2503_00868_amd import inputs
+                n_active = active_faces(inputs.gen_mask(n, seed))
+            every, active = FACE_BYTES[kind]
+            alg = every * F3 + active * n_active
         else:
             alg = {"percnn": PERCNN_BYTES["percnn"] * C, "percnn_adj": PERCNN_BYTES["percnn_adj"] * C,
-                   "upwind": UPWIND_BYTES * F3}.get(kind)
+                   "upwind": UPWIND_BYTES * F3, "loss": LOSS_BYTES * C}.get(kind)
         srcs = {f"paper_2503_00868_amd/csrc/{f}": hashlib.sha256(
             open(os.path.join(ROOT, "paper_2503_00868_amd", "csrc", f), "rb").read()).hexdigest()
             for f in TRAFFIC_SOURCES[kind]}
-        total = tot_f + tot_w
+        total = tot_r + tot_w
+        unit = {"screen": "iteration (direction + stencil, update)", "apic_p2g": "call",
+                "apic_g2p": "call", "loss": "call", "constrained": "iteration (multipliers, pressure update)"
+                }.get(kind, "launch")
         lines = [f"# HBM traffic: `{kind}` at {n}^3 ({precond} run)", "",
                  "Commands (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first, "
-                 "R = repository path), one pass per counter:", "", "```"] + commands + [
+                 "R = repository path):", "", "```"] + commands + [
                  "```", "",
-                 f"Scale factors from a plain copy of {copy_mib} MiB (`bench.py --copy-probe "
-                 f"{copy_mib}`, 20 copies): FETCH_SIZE reads {fa:.0f} KiB per copy (x {ff:.3f}), "
-                 f"WRITE_SIZE {wa:.0f} KiB (x {wf:.3f}).  Averages are over the dispatches that did "
-                 "work (above 5% of the kernel's largest reading).", "",
-                 "| kernel | working dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |",
+                 f"Counters: `{DRAM_READ}` and `{DRAM_WRITE}`, the L2's read and write requests "
+                 "to the memory side in 32-byte units (a 64-byte request counts 2, a 128-byte "
+                 "read 4); bytes = 32 x count.  The same pass over 20 plain copies of "
+                 f"{copy_mib} MiB reads {copy_r:.3f} x the bytes copied and writes {copy_w:.3f} x "
+                 "(the check of the count).  Averages are over the dispatches that did work "
+                 "(above 5% of the kernel's largest reading).", "",
+                 "| kernel | working dispatches | read MB | written MB | MB |",
                  "|---|---:|---:|---:|---:|"] + rows + [
-                 "", f"Per launch of the `{kind}` kind: **{total / 1e6:.1f} MB** "
-                 f"(reads {tot_f / 1e6:.1f} MB, writes {tot_w / 1e6:.1f} MB)"
+                 "", f"Per {unit} of the `{kind}` kind: **{total / 1e6:.1f} MB** "
+                 f"(reads {tot_r / 1e6:.1f} MB, writes {tot_w / 1e6:.1f} MB)"
                  + (f" against {alg / 1e6:.1f} MB algorithmic ({total / alg:.2f}x)." if alg else "."),
                  "", "bench-traffic: " + json.dumps({"kind": kind, "precond": precond, "n": n,
                                                      "bytes_per_launch": int(total),
-                                                     "read_bytes": int(tot_f),
+                                                     "read_bytes": int(tot_r),
                                                      "write_bytes": int(tot_w),
+                                                     "algorithmic_bytes": int(alg) if alg else None,
+                                                     "copy_check": [round(copy_r, 4), round(copy_w, 4)],
                                                      "sources": srcs})]
         path = os.path.join(out_dir, f"{kind}_{precond}_{n}_traffic.md")
         with open(path, "w") as f:
             f.write("\n".join(lines) + "\n")
         written.append(path)
-        print(f"wrote {path}: {total / 1e6:.1f} MB per launch")
+        print(f"wrote {path}: {total / 1e6:.1f} MB per {unit}")
     return written
 
 
@@ -1032,8 +1060,8 @@ def main():
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:
-        fc, wc, cf, cw, pc = args.summarize_traffic
-        summarize_traffic(fc, wc, cf, cw, pc, args.n, args.commands, os.path.join(ROOT, "profiles"))
+        rc, cc, pc = args.summarize_traffic
+        summarize_traffic(rc, cc, pc, args.n, args.commands, os.path.join(ROOT, "profiles"))
         return
     import numpy as np
     import torch
@@ -1361,7 +1389,7 @@ def main():
 
     screen_out = None
     if not args.no_screen:
-        screen_out = screen_bench(dev)
+        screen_out = screen_bench(dev, traffic_n=n)
         log(f"screen-space projection 1080x1920: {screen_out['ms_per_call']:.2f} ms, "
             f"{screen_out['iters']} iterations")
 

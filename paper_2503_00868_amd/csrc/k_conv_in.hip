@@ -11,6 +11,7 @@
 // [voxel] and each lane stores 4 channels of one voxel straight from its
 // registers.  r and the mask are read directly from the solver's arrays, so
 // the 2-channel input tensor is never stored.
+#include "block_or.h"
 #include "common.h"
 #include "ctx.h"
 #include "net.h"
@@ -50,6 +51,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   if (flags && flags[F_DONE]) return;
   count_work(work);
   __shared__ uint32_t ring[4][IRV];  // (r / rms, mask) as two bf16; four slots as in k_conv_zm
+  __shared__ __attribute__((aligned(16))) int votes[4][4];  // per ring slot
   const double rms = n_liquid > 0.0 ? sqrt(*sumsq / n_liquid) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
   const float inv = rms > 0.0 ? (float)(1.0 / rms) : 0.f;
@@ -134,9 +136,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   // all-zero neighbourhoods (air far from liquid) skip the MFMAs, as in
   // k_conv_zm
   load_plane(z0 - 1, ra);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1, ra));
+  int nz_m = barrier_or(store_plane(z0 - 1, ra), votes[(z0 + 3) & 3]);
   load_plane(z0, ra);
-  int nz_0 = __syncthreads_or(store_plane(z0, ra));
+  int nz_0 = barrier_or(store_plane(z0, ra), votes[z0 & 3]);
   load_plane(z0 + 1, ra);
   if (z0 + 2 <= z1) load_plane(z0 + 2, rb);
 
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   // (the per-plane work of this layer is too small to hide one load
   // latency)
   auto plane_step = [&](int z, Raw& cur) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1, cur));
+    const int nz_p = barrier_or(store_plane(z + 1, cur), votes[(z + 1) & 3]);
     if (z + 3 <= z1) load_plane(z + 3, cur);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;

@@ -12,6 +12,7 @@
 // After plane p, output plane p - 1 is complete and is stored.  Every input
 // voxel is read from memory once per block (plus the xy halo), the output is
 // written once.
+#include "block_or.h"
 #include "common.h"
 #include "ctx.h"
 #include "net.h"
@@ -55,6 +56,7 @@ __global__ void __launch_bounds__(kBlock)
   // two staged planes, each as two 8-channel halves [half][voxel] (16 B per
   // voxel and half: the 16 lanes of a row read consecutive words)
   __shared__ uint4 ring[2][2][ORV];
+  __shared__ __attribute__((aligned(16))) int votes[2][4];  // per ring slot
   __shared__ uint8_t live_s[OMAXC + 3], live_in_s[OMAXC + 3];
 
   const int tpr = (n + OT - 1) / OT;
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(kBlock)
   for (int p = z0 - 1; p <= z1; ++p) {
     const int slot = p & 1;
     // the slot was last read for plane p - 2, before the previous barrier
-    const int nz = __syncthreads_or(store_plane(slot));
+    const int nz = barrier_or(store_plane(slot), votes[slot]);
     // the output plane p - 1 is complete after this plane; its mask byte is
     // loaded (from a clamped address) ahead of the next plane's loads, so
     // that waiting for it does not wait for them

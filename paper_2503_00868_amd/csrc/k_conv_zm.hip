@@ -25,6 +25,7 @@
 // Within a step group the A fragment depends only on halo row a + dy, so a
 // wave (4 output rows) loads 6 fragments and issues 12 MFMAs per group.
 // Weight fragments stay in registers for the whole block.
+#include "block_or.h"
 #include "common.h"
 #include "ctx.h"
 #include "net.h"
@@ -50,6 +51,28 @@ __device__ inline int zm_tap1(int s) {
   if (s < 9) return (s % 3) + 3 * (s / 3) + 9;          // dz 1
   if (s < 12) return 1 + 3 * (s - 9) + 18;              // (1, dy, 2)
   return 27;                                            // zero tap
+}
+
+// The 15 steps of a chunk in 5 groups whose A fragments share one halo
+// column: groups k = 0-2 are dx = k with taps dz 0 | dz 1 (planes z-1 | z),
+// group 3 is dz 2 with (dx 0 | dx 1), group 4 dz 2 with (dx 2 | zero).  Step
+// of group k at row offset dy:
+__device__ inline int zm_group_step(int k, int dy) {
+  return k < 3 ? k + 3 * dy : 9 + 3 * (k - 3) + dy;
+}
+
+// The 6 halo rows (4 output rows + 2) of group gi = 5 q + k for this lane:
+// 8 channels (half g & 1 of chunk q) at column col + the group's x offset,
+// from the ring slots of planes z-1 (sm), z (s0) and z+1 (sp).
+__device__ inline void zm_load_group(int gi, const __bf16* sm, const __bf16* s0, const __bf16* sp,
+                                     int wv, int g, int col, bf16x8z (&f)[6]) {
+  const int q = gi / 5, k = gi % 5;
+  const __bf16* base = k < 3 ? (g < 2 ? sm : s0) : sp;
+  const int xo = k < 3 ? k : (k == 3 ? (g < 2 ? 0 : 1) : 2);
+  base += (int64_t)(2 * q + (g & 1)) * ZRV * 8;
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+    f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
 }
 
 struct ZmGrid {
@@ -93,6 +116,7 @@ __global__ void __launch_bounds__(kBlock)
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
+  __shared__ __attribute__((aligned(16))) int votes[4][4];  // per ring slot
   // Epilogue: layers with 32 or more channels on either side take the
   // weights as the MFMA's A operand (D = [output channel][voxel]) and store
   // straight from registers; 16 -> 16 layers take the input as A (D =
@@ -252,15 +276,15 @@ __global__ void __launch_bounds__(kBlock)
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
   load_plane(z0 - 1);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1));
+  int nz_m = barrier_or(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
   load_plane(z0);
-  int nz_0 = __syncthreads_or(store_plane(z0));
+  int nz_0 = barrier_or(store_plane(z0), votes[z0 & 3]);
   load_plane(z0 + 1);
 
   // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
   // is loaded while the MFMAs of plane z run
   auto plane_step = [&](int z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1));
+    const int nz_p = barrier_or(store_plane(z + 1), votes[(z + 1) & 3]);
     if (z + 2 <= z1) load_plane(z + 2);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
@@ -298,47 +322,33 @@ __global__ void __launch_bounds__(kBlock)
     const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
     const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
     const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
-    const int sub = g & 1;  // 8-channel half of the chunk
+    if (work) {
+      // the 5 step groups of each chunk in turn, the fragments of group gi + 1
+      // read from LDS before the MFMAs of group gi are issued
+      bf16x8z fa[6], fb[6];
+      zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+      __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
-    for (int q = 0; q < (work ? NCH : 0); ++q) {
-      // groups 0-2: dx = 0..2, taps dz 0 | dz 1
+      for (int gi = 0; gi < 5 * NCH; ++gi) {
+        bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
+        if (gi + 1 < 5 * NCH) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+        const int q = gi / 5, k = gi % 5;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)(2 * q + sub) * ZRV * 8;
-        bf16x8z f[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 8);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int dy = 0; dy < 3; ++dy) {
+          const int st = zm_group_step(k, dy);
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-              acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[q][dx + 3 * dy][t],
-                                                                           f[a + dy], acc[a][t], 0, 0, 0)
-                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][dx + 3 * dy][t],
+              acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[q][st][t], f[a + dy],
+                                                                           acc[a][t], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][st][t],
                                                                            acc[a][t], 0, 0, 0);
-      }
-      // groups 3-4: dz 2 with (dx 0 | dx 1) and (dx 2 | zero)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int xo = h == 0 ? (g < 2 ? 0 : 1) : 2;
-        const __bf16* base = sp + (int64_t)(2 * q + sub) * ZRV * 8;
-        bf16x8z f[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                       bw[q][9 + 3 * h + dy][t], f[a + dy], acc[a][t], 0, 0, 0)
-                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                       f[a + dy], bw[q][9 + 3 * h + dy][t], acc[a][t], 0, 0, 0);
+        }
+        // keep that order in the schedule: the next group's 6 LDS reads, then
+        // this group's MFMAs
+        if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
       }
     }
 
@@ -474,6 +484,7 @@ __global__ void __launch_bounds__(kBlock)
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
+  __shared__ __attribute__((aligned(16))) int votes[4][4];  // per ring slot
   constexpr int STAGE_BYTES = 4 * 4 * ZT * COUT * (EPI == NET_EPI_RELU_ADD ? 4 : 2);
   __shared__ __attribute__((aligned(16))) char stage_raw[STAGE_BYTES];
   __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
@@ -605,9 +616,9 @@ __global__ void __launch_bounds__(kBlock)
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
   load_plane(z0 - 1);
-  int nz_m = __syncthreads_or(store_plane(z0 - 1));
+  int nz_m = barrier_or(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
   load_plane(z0);
-  int nz_0 = __syncthreads_or(store_plane(z0));
+  int nz_0 = barrier_or(store_plane(z0), votes[z0 & 3]);
   load_plane(z0 + 1);
   float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
 #pragma unroll
@@ -616,7 +627,7 @@ __global__ void __launch_bounds__(kBlock)
   // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
   // is loaded while the MFMAs of plane z run
   auto plane_step = [&](int z) {
-    const int nz_p = __syncthreads_or(store_plane(z + 1));
+    const int nz_p = barrier_or(store_plane(z + 1), votes[(z + 1) & 3]);
     if (z + 2 <= z1) load_plane(z + 2);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
@@ -660,43 +671,28 @@ __global__ void __launch_bounds__(kBlock)
     const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
     const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
     const __bf16* sp = ring + ((z + 1) & 3) * SLOT;  // plane z+1 (dz = 2)
-    const int sub = g & 1;  // 8-channel half of the chunk
+    if (work) {
+      // as in k_conv_zm: group gi + 1's fragments are read before group gi's MFMAs
+      bf16x8z fa[6], fb[6];
+      zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+      __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
-    for (int q = 0; q < (work ? NCH : 0); ++q) {
-      // groups 0-2: dx = 0..2, taps dz 0 | dz 1
+      for (int gi = 0; gi < 5 * NCH; ++gi) {
+        bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
+        if (gi + 1 < 5 * NCH) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+        const int q = gi / 5, k = gi % 5;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const __bf16* base = (g < 2 ? sm : s0) + (int64_t)(2 * q + sub) * ZRV * 8;
-        bf16x8z f[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + dx) * 8);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][dx + 3 * dy][t],
-                                                                  acc[a][t], 0, 0, 0);
-      }
-      // groups 3-4: dz 2 with (dx 0 | dx 1) and (dx 2 | zero)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int xo = h == 0 ? (g < 2 ? 0 : 1) : 2;
-        const __bf16* base = sp + (int64_t)(2 * q + sub) * ZRV * 8;
-        bf16x8z f[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int dy = 0; dy < 3; ++dy) {
+          const int st = zm_group_step(k, dy);
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  f[a + dy], bw[q][9 + 3 * h + dy][t], acc[a][t], 0, 0, 0);
+              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][st][t], acc[a][t],
+                                                                  0, 0, 0);
+        }
+        if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
       }
     }
 

@@ -53,3 +53,52 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def _counter_csv(path, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_summary_counts_32_byte_units(tmp_path):
+    """32 x the request counts, averaged over working dispatches only (the
+    ones that return at once on the done flag are left out), the four-step
+    update weighted 1:3, and the copy's reading reported as the check."""
+    import json
+
+    import bench
+    R, W = bench.DRAM_READ, bench.DRAM_WRITE
+    mib = 1
+    copy_units = mib * (1 << 20) // 32
+    _counter_csv(tmp_path / "copy.csv", [(i, "copy", c, copy_units) for i in range(20)
+                                         for c in (R, W)])
+    rows = []
+    did = 0
+    for reads, writes in [(1000, 500), (1200, 700), (3, 1)]:  # the last one returned at once
+        rows += [(did, "void fs::k_dir_spmv_zm<0, false>(int, int)", R, reads),
+                 (did, "void fs::k_dir_spmv_zm<0, false>(int, int)", W, writes)]
+        did += 1
+    for name, reads in [("void fs::k_update4<4, true, false>(int)", 4000),
+                        ("void fs::k_update4<4, false, false>(int)", 2000)]:
+        rows += [(did, name, R, reads), (did, name, W, 0)]
+        did += 1
+    _counter_csv(tmp_path / "run.csv", rows)
+    out = tmp_path / "profiles"
+    out.mkdir()
+    written = bench.summarize_traffic(str(tmp_path / "run.csv"), str(tmp_path / "copy.csv"),
+                                      "jacobi", 16, ["cmd"], str(out), copy_mib=mib)
+    recs = {}
+    for p in written:
+        line = [l for l in open(p).read().splitlines() if l.startswith("bench-traffic:")][0]
+        rec = json.loads(line.split(":", 1)[1])
+        recs[rec["kind"]] = rec
+    spmv = recs["pcg_dir_spmv"]
+    assert spmv["read_bytes"] == 32 * 1100 and spmv["write_bytes"] == 32 * 600
+    assert spmv["copy_check"] == [1.0, 1.0]
+    assert spmv["algorithmic_bytes"] == 17 * 16 ** 3
+    upd = recs["pcg_update"]
+    assert upd["read_bytes"] == int(32 * (0.25 * 4000 + 0.75 * 2000))
