@@ -675,7 +675,9 @@ __global__ void __launch_bounds__(kBlock)
       // as in k_conv_zm: group gi + 1's fragments are read before group gi's MFMAs
       bf16x8z fa[6], fb[6];
       zm_load_group(0, sm, s0, sp, wv, g, col, fa);
-      __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+      // (not for the 16-channel pool layer: at its three waves per SIMD the
+      // deeper pipeline spills, and the compiler's own order measured faster)
+      if (!(NCH == 1 && EPI == NET_EPI_RELU_POOL)) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
       for (int gi = 0; gi < 5 * NCH; ++gi) {
         bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
@@ -691,8 +693,10 @@ __global__ void __launch_bounds__(kBlock)
               acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][st][t], acc[a][t],
                                                                   0, 0, 0);
         }
-        if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
+        if (!(NCH == 1 && EPI == NET_EPI_RELU_POOL)) {
+          if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
+        }
       }
     }
 
