@@ -825,6 +825,329 @@ __global__ void __launch_bounds__(kBlock)
   for (int z = z0; z < z1; ++z) plane_step(z);
 }
 
+// Decoder layer c9 in one pass: ReLU(conv3(cat(up(D2), E1))) at the fine
+// level, with the upsampled half evaluated on the coarse grid as in k_upconv
+// (per parity class a 2x2x2 convolution of the 32-channel coarse tensor with
+// summed weights) and the skip half as in k_conv_zm_pa, inside one z-march:
+// the two halves meet in LDS instead of through an FP16 partial-sum tensor
+// written and read back (two passes over 32 B per fine voxel).
+//
+// A block has 8 waves: waves 0-3 compute the skip half of rows 4 j .. 4 j + 3
+// (j = wave % 4) as k_conv_zm_pa does, waves 4-7 the coarse half of the same
+// rows, each into its own FP32 stage; after a second barrier every thread
+// adds the two stages for 8 channels of one voxel and stores.  (With one
+// wave per row group doing both halves, the 64 KB of staged weights left
+// room for one block per CU and one wave per SIMD: slower than the two
+// kernels it replaced.)
+//
+// Coarse half, per fine plane z (parity pz, coarse plane Z = z / 2): rows
+// 4 j + P and 4 j + P + 2 (P = 0, 1) share the y parity py = P, and with one
+// x parity px their 16 voxels (8 per row) form one M block whose coarse
+// voxels are (X0 + m % 8, Y0 + 2 j + m / 8).  For a coarse offset (ox, oy,
+// oz) the A fragment is the same for both x parities, so each (ty, tz) loads
+// 3 A fragments (ox = -1, 0, 1) for the 4 MFMAs of (px, tx).  B fragments
+// (the summed weights of all 8 classes, 64 KB) are read from LDS, staged once
+// per block.  The coarse planes Z-1 .. Z+1 (10 x 10 voxels with the halo, 32
+// channels) sit in a three-slot ring; coarse plane K is stored at fine step
+// 2K - 1 and last read at 2K + 2.
+constexpr int CAT_BLOCK = 512;
+constexpr int CAT_KT = ZT / 2 + 2;          // coarse ring plane edge with halo
+constexpr int CAT_KRV = CAT_KT * CAT_KT;    // 100 coarse voxels per ring plane
+constexpr int CAT_KSLOT = CAT_KRV * 32;     // bf16 per coarse ring slot
+constexpr int CAT_KITEMS = CAT_KRV * 4;     // uint4 items per coarse plane
+constexpr int CAT_KPF = (CAT_KITEMS + CAT_BLOCK - 1) / CAT_BLOCK;
+constexpr int CAT_WL = 8 * 8 * 16 * 32;     // bf16 of the summed weights
+
+__global__ void __launch_bounds__(CAT_BLOCK)
+    k_conv_cat(int n, int zc, const __bf16* __restrict__ coarse, const __bf16* __restrict__ skip,
+               const __bf16* __restrict__ weff, const __bf16* __restrict__ wskip,
+               __bf16* __restrict__ out, const int* __restrict__ flags,
+               const uint8_t* __restrict__ act) {
+  if (flags && flags[F_DONE]) return;
+  constexpr int P8 = 2;                  // 8-channel parts per skip voxel
+  constexpr int ITEMS = ZRV * P8;
+  constexpr int PF = (ITEMS + CAT_BLOCK - 1) / CAT_BLOCK;
+  constexpr int SLOT = ZRV * 16;
+  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
+  __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
+  __shared__ __attribute__((aligned(16))) __bf16 wl[CAT_WL];
+  __shared__ __attribute__((aligned(16))) float stage[2][4][4 * ZT * 16];
+  __shared__ __attribute__((aligned(16))) int votes[4][8];
+  __shared__ uint8_t live_s[ZMAXC + 3];
+
+  const int tiles = ((n + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
+  const int tpr = (n + ZT - 1) / ZT;
+  int tile, chunk;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, chunk);
+  const int x0 = (tile % tpr) * ZT, y0 = (tile / tpr) * ZT;
+  const int z0 = chunk * zc;
+  const int z1 = min(z0 + zc, n);
+  if (z0 >= n) return;
+  const int nc = n >> 1, X0 = x0 >> 1, Y0 = y0 >> 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int wv = wave & 3;             // row group of this wave
+  const bool coarse_role = wave >= 4;  // block-uniform per wave
+
+  // output tile-plane activity (as in k_conv_zm: planes marked 0 are neither
+  // computed nor stored, input planes marked 0 read as zero)
+  if (act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += CAT_BLOCK) {
+      const int zi = z0 - 1 + t;
+      live_s[t] = (unsigned)zi < (unsigned)n ? act[(int64_t)zi * tiles + tile] : 0;
+      any |= t >= 1 && t <= z1 - z0 && live_s[t];
+    }
+    if (!__syncthreads_or(any)) return;
+  }
+  auto live = [&](int zi) -> bool { return !act || live_s[zi - z0 + 1] != 0; };
+  // block-wide OR with one barrier (as barrier_or, for 8 waves)
+  auto vote = [&](int v, int* slot) -> int {
+    const bool any = __ballot(v != 0) != 0ull;
+    if (lane == 0) slot[wave] = any;
+    __syncthreads();
+    const int4 a = *reinterpret_cast<const int4*>(slot);
+    const int4 b = *reinterpret_cast<const int4*>(slot + 4);
+    return a.x | a.y | a.z | a.w | b.x | b.y | b.z | b.w;
+  };
+
+  // the summed coarse weights, [p * 8 + tap][c / 8][co][8] (conflict-free
+  // fragment reads, as in k_upconv)
+  for (int q = threadIdx.x; q < CAT_WL / 8; q += CAT_BLOCK) {
+    const int cl = q % 16, kc = (q / 16) % 4, pt = q / 64;
+    *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) =
+        *reinterpret_cast<const uint4*>(weff + ((int64_t)pt * 16 + cl) * 32 + kc * 8);
+  }
+
+  // skip-half weight fragments (B operand), as in k_conv_zm_pa
+  bf16x8z bw[ZSTEPS];
+#pragma unroll
+  for (int st = 0; st < ZSTEPS; ++st) {
+    const int tap = g < 2 ? zm_tap0(st) : zm_tap1(st);
+    bw[st] = *reinterpret_cast<const bf16x8z*>(wskip + ((int64_t)col * ZTAPS + tap) * 16 + (g & 1) * 8);
+  }
+
+  // skip plane loads: per-item offsets fixed for the block
+  uint32_t ioff[PF];
+  bool iok[PF];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int it = threadIdx.x + k * CAT_BLOCK;
+    const int hv = it / P8, p = it - hv * P8;
+    const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
+    iok[k] = it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+    ioff[k] = iok[k] ? (uint32_t)((((int64_t)gx + (int64_t)n * gy) * 16 + p * 8) * 2) : 0u;
+  }
+  const int64_t splane = (int64_t)n * n * 16 * 2;
+  uint4 pf[PF];
+  auto load_plane = [&](int zi) {
+    if (!live(zi) || (unsigned)zi >= (unsigned)n) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k) pf[k] = make_uint4(0u, 0u, 0u, 0u);
+      return;
+    }
+    const char* pa = reinterpret_cast<const char*>(skip) + (int64_t)zi * splane;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) pf[k] = *reinterpret_cast<const uint4*>(pa + ioff[k]);
+  };
+  auto store_plane = [&](int zi) -> int {
+    __bf16* slot = ring + ((zi + 4) & 3) * SLOT;
+    uint32_t any = 0u;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int it = threadIdx.x + k * CAT_BLOCK;
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
+        // component selects (a select of whole vectors went through scratch)
+        uint4 v = pf[k];
+        v.x = iok[k] ? v.x : 0u;
+        v.y = iok[k] ? v.y : 0u;
+        v.z = iok[k] ? v.z : 0u;
+        v.w = iok[k] ? v.w : 0u;
+        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        any |= v.x | v.y | v.z | v.w;
+      }
+    }
+    return any != 0u;
+  };
+
+  // coarse plane loads: item it = 4 v + part (v a halo voxel of the 10 x 10
+  // coarse plane, part 8 of its 32 channels)
+  uint32_t koff[CAT_KPF];
+  bool kok[CAT_KPF];
+#pragma unroll
+  for (int k = 0; k < CAT_KPF; ++k) {
+    const int it = threadIdx.x + k * CAT_BLOCK;
+    const int cv = it >> 2, part = it & 3;
+    const int cx = X0 - 1 + cv % CAT_KT, cy = Y0 - 1 + cv / CAT_KT;
+    kok[k] = it < CAT_KITEMS && (unsigned)cx < (unsigned)nc && (unsigned)cy < (unsigned)nc;
+    koff[k] = kok[k] ? (uint32_t)((((int64_t)cx + (int64_t)nc * cy) * 32 + part * 8) * 2) : 0u;
+  }
+  const int64_t cplane = (int64_t)nc * nc * 32 * 2;
+  uint4 kpf[CAT_KPF];
+  bool kpf_on = false;
+  auto load_coarse = [&](int K) {
+    kpf_on = (unsigned)K < (unsigned)nc;
+    const char* pc = reinterpret_cast<const char*>(coarse) + (int64_t)(kpf_on ? K : 0) * cplane;
+#pragma unroll
+    for (int k = 0; k < CAT_KPF; ++k) kpf[k] = *reinterpret_cast<const uint4*>(pc + koff[k]);
+  };
+  auto kslot = [](int K) -> int { return ((K % 3) + 3) % 3; };
+  auto store_coarse = [&](int K) {
+    __bf16* slot = kring + kslot(K) * CAT_KSLOT;
+#pragma unroll
+    for (int k = 0; k < CAT_KPF; ++k) {
+      const int it = threadIdx.x + k * CAT_BLOCK;
+      if (it < CAT_KITEMS) {
+        const int cv = it >> 2, part = it & 3;
+        const bool on = kpf_on && kok[k];
+        uint4 v = kpf[k];
+        v.x = on ? v.x : 0u;
+        v.y = on ? v.y : 0u;
+        v.z = on ? v.z : 0u;
+        v.w = on ? v.w : 0u;
+        *reinterpret_cast<uint4*>(slot + (part * CAT_KRV + cv) * 8) = v;
+      }
+    }
+  };
+
+  // prologue: skip planes z0-1, z0 and coarse planes Z0-1, Z0 to LDS, skip
+  // plane z0+1 and coarse plane Z0+1 in flight
+  const int Z0 = z0 >> 1;
+  load_coarse(Z0 - 1);
+  store_coarse(Z0 - 1);
+  load_coarse(Z0);
+  store_coarse(Z0);
+  load_plane(z0 - 1);
+  int nz_m = vote(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
+  load_plane(z0);
+  int nz_0 = vote(store_plane(z0), votes[z0 & 3]);
+  load_plane(z0 + 1);
+  load_coarse(Z0 + 1);
+
+  float* sf = stage[coarse_role ? 1 : 0][wv];
+  auto plane_step = [&](int z) {
+    // coarse plane (z + 1) / 2 is first read at odd z
+    if (z & 1) store_coarse((z + 1) >> 1);
+    const int nz_p = vote(store_plane(z + 1), votes[(z + 1) & 3]);
+    if (z + 2 <= z1) load_plane(z + 2);
+    if ((z & 1) && z + 2 < z1) load_coarse((z + 3) >> 1);
+    const bool work = (nz_m | nz_0 | nz_p) != 0;
+    nz_m = nz_0;
+    nz_0 = nz_p;
+    if (!live(z)) return;
+
+    if (!coarse_role) {
+      // skip half (as k_conv_zm_pa), into stage 0 [row a][x][channel]
+      f32x4z acc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      const __bf16* sm = ring + ((z + 3) & 3) * SLOT;
+      const __bf16* s0 = ring + (z & 3) * SLOT;
+      const __bf16* sp = ring + ((z + 1) & 3) * SLOT;
+      if (work) {
+        bf16x8z fa[6], fb[6];
+        zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+#pragma unroll
+        for (int gi = 0; gi < 5; ++gi) {
+          bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
+          if (gi + 1 < 5) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const int st = zm_group_step(gi, dy);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+              acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[st], acc[a], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * 16 + col] = acc[a][i];
+    } else {
+      // coarse half: kacc[P][px], M block of rows 4 wv + P (+ 2), x parity px
+      f32x4z kacc[2][2];
+#pragma unroll
+      for (int P = 0; P < 2; ++P)
+#pragma unroll
+        for (int px = 0; px < 2; ++px) kacc[P][px] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      const int pz = z & 1, Zc = z >> 1;
+#pragma unroll
+      for (int tz = 0; tz < 2; ++tz) {
+        const int oz = tz - (pz ? 0 : 1);
+        const __bf16* ks = kring + kslot(Zc + oz) * CAT_KSLOT + g * CAT_KRV * 8;
+#pragma unroll
+        for (int ty = 0; ty < 2; ++ty) {
+          bf16x8z A[2][3];
+#pragma unroll
+          for (int P = 0; P < 2; ++P) {
+            const int cy = 2 * wv + (col >> 3) + ty - (P ? 0 : 1) + 1;
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox)
+              A[P][ox] = *reinterpret_cast<const bf16x8z*>(ks + (cy * CAT_KT + (col & 7) + ox) * 8);
+          }
+#pragma unroll
+          for (int P = 0; P < 2; ++P)
+#pragma unroll
+            for (int px = 0; px < 2; ++px)
+#pragma unroll
+              for (int tx = 0; tx < 2; ++tx) {
+                const int p = px + 2 * P + 4 * pz, tap = tx + 2 * ty + 4 * tz;
+                const bf16x8z B = *reinterpret_cast<const bf16x8z*>(wl + (((p * 8 + tap) * 4 + g) * 16 + col) * 8);
+                // coarse x offset tx - (px ? 0 : 1), as an index into A (0..2)
+                kacc[P][px] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[P][tx + px], B, kacc[P][px], 0, 0, 0);
+              }
+        }
+      }
+      // into stage 1, same layout: M row m = 4 g + i is the voxel of row
+      // P + 2 (m / 8), x 2 (m % 8) + px
+#pragma unroll
+      for (int P = 0; P < 2; ++P)
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = 4 * g + i;
+            const int a = P + 2 * (m >> 3), x = 2 * (m & 7) + px;
+            sf[((a * ZT) + x) * 16 + col] = kacc[P][px][i];
+          }
+    }
+    __syncthreads();
+    // both halves, ReLU, bf16: thread t takes 8 channels of one voxel
+    {
+      const int it = threadIdx.x;
+      const int lv = it >> 1, part = it & 1;  // lv: voxel of the tile plane
+      const int r = lv / ZT, xl = lv % ZT;    // tile row, x
+      const int x = x0 + xl, y = y0 + r;
+      if (x < n && y < n) {
+        const float* s8a = stage[0][r >> 2] + ((r & 3) * ZT + xl) * 16 + part * 8;
+        const float* s8b = stage[1][r >> 2] + ((r & 3) * ZT + xl) * 16 + part * 8;
+        __bf16 o8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float v = s8a[e] + s8b[e];
+          o8[e] = (__bf16)(v > 0.f ? v : 0.f);
+        }
+        *reinterpret_cast<uint4*>(out + ((int64_t)x + (int64_t)n * (y + (int64_t)n * z)) * 16 + part * 8) =
+            *reinterpret_cast<const uint4*>(o8);
+      }
+    }
+    // the stages are written again only after the next plane's barrier
+  };
+  for (int z = z0; z < z1; ++z) plane_step(z);
+}
+
+bool net_conv_cat(sim_ctx* c, int n, const __bf16* coarse, const __bf16* skip, const __bf16* weff,
+                  const __bf16* wskip, __bf16* out, const int* flags, const uint8_t* act) {
+  if (n % ZT != 0) return false;
+  // (longer z-runs, to stage the weights less often, measured slower: the
+  // busy tiles then load the CUs unevenly)
+  const ZmGrid g = zm_grid(n);
+  hipLaunchKernelGGL(k_conv_cat, dim3(g.blocks), dim3(CAT_BLOCK), 0, c->stream, n, g.zc, coarse, skip,
+                     weff, wskip, out, flags, act);
+  return true;
+}
+
 template <int CIN, int WS, int COUT, int EPI>
 static void zm_launch(sim_ctx* c, int n, NetSrc src, const __bf16* w, NetOut out,
                       const int* flags) {

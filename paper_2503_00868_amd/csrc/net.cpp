@@ -186,6 +186,10 @@ int dgrad(sim_ctx* c, int n, int l, int epi, const __bf16* G, NetOut out) {
 int split_conv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
                _Float16* T, NetSrc skip, const __bf16* wskip, __bf16* out, const int* flags,
                const uint8_t* act_c, const uint8_t* act_f) {
+  // the fine layer (32 coarse + 16 skip channels) in one pass
+  if (cc == 32 && cout == 16 && skip.ca == 16 && !skip.b &&
+      net_conv_cat(c, n, coarse, skip.a, weff, wskip, out, flags, act_f))
+    return SIM_OK;
   if (!net_upconv(c, n, cc, cout, coarse, weff, T, flags, act_c) ||
       !net_conv(c, n, skip.ca, cout, NET_EPI_RELU_ADD, skip, wskip,
                 NetOut{out, nullptr, nullptr, nullptr, nullptr, T, nullptr, act_f}, flags)) {

@@ -74,6 +74,13 @@ void net_pool(sim_ctx* c, int n, int C, const __bf16* in, __bf16* out, const int
 // coarse tile-plane marked 0 are not computed (they stay zero).
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
                 _Float16* out, const int* flags, const uint8_t* act);
+// The fine decoder layer with 32 coarse and 16 skip channels and 16 outputs
+// in one pass: out = ReLU(conv(cat(up(coarse), skip))) (bf16), the upsampled
+// half through weff as net_upconv, the skip half through wskip ([16][28][16]).
+// act (nullable): activity map of the fine output (also read for the skip
+// input).  False when n is not a multiple of the 16-voxel tile.
+bool net_conv_cat(sim_ctx* c, int n, const __bf16* coarse, const __bf16* skip, const __bf16* weff,
+                  const __bf16* wskip, __bf16* out, const int* flags, const uint8_t* act);
 // Packs weff from the fp32 master weights W [cout][cin][27] of a layer whose
 // first cc input channels are the upsampled ones; and the skip channels
 // [cc, cin) into the forward layout [cout_p][28][cin - cc].
