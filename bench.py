@@ -694,7 +694,7 @@ TRAFFIC_KINDS = {
     "dcg_dir_spmv": {"learned": ["k_dcg_dir_spmv_zm"]},
     "dcg_update": {"learned": ["k_dcg_update"]},
     "net": {"learned": ["k_conv_in", "k_conv_zm", "k_upconv", "k_conv_out", "k_conv<",
-                        "k_convILi", "k_dot_cells"]},
+                        "k_convILi", "k_conv_cat", "k_dot_cells"]},
     "percnn": {"jacobi": ["k_percnn_layer("]},
     "percnn_adj": {"jacobi": ["k_percnn_layer_adj"]},
     "upwind": {"jacobi": ["k_convection_grad_upwind"]},
