@@ -172,6 +172,8 @@ def parse():
                    help="write a kernel-trace summary for profiles/ and exit (no GPU)")
     p.add_argument("--summarize-traffic", nargs=3, metavar=("RUN_CSV", "COPY_CSV", "PRECOND"),
                    help="write the per-kind traffic summaries for profiles/ and exit (no GPU)")
+    p.add_argument("--summarize-counters", nargs=3, metavar=("COUNTER_CSV", "OUT", "TITLE"),
+                   help="write a per-kernel MFMA / LDS counter summary for profiles/ and exit")
     p.add_argument("--commands", nargs="*", default=[],
                    help="the commands that produced the counter files (for --summarize-traffic)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -890,6 +892,63 @@ def summarize_traffic(run_csv, copy_csv, precond, n, commands, out_dir, copy_mib
     return written
 
 
+def summarize_counters(csv_path, out, title, commands, cu_num=256, simd_per_cu=4, xcc=8):
+    """Per-kernel MFMA and LDS utilisation from one rocprofv3 --pmc pass with
+    SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE, SQ_LDS_IDX_ACTIVE,
+    SQ_LDS_BANK_CONFLICT, SQ_INSTS_MFMA, SQ_INSTS_LDS, SQ_INSTS_VALU and
+    SQ_WAVE_CYCLES: MFMA busy = MFMA-busy cycles over (GPU-active cycles x
+    SIMDs), LDS active = LDS-busy cycles over (GPU-active cycles x CUs), bank
+    conflicts as a share of the LDS-busy cycles; averages over the working
+    dispatches (GPU-active cycles above 5% of the kernel's longest).
+    GRBM_GUI_ACTIVE comes summed over the xcc XCDs, each of which counts the
+    dispatch's active cycles."""
+    import collections
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for r in _rows(csv_path):
+        d = r["Dispatch_Id"]
+        names[d] = r["Kernel_Name"]
+        per[d][r["Counter_Name"]] += float(r["Counter_Value"])
+    by_kernel = collections.defaultdict(list)
+    for d, cs in per.items():
+        by_kernel[names[d]].append(cs)
+    rows = []
+    for k, lst in by_kernel.items():
+        mx = max(c.get("GRBM_GUI_ACTIVE", 0.0) for c in lst)
+        w = [c for c in lst if c.get("GRBM_GUI_ACTIVE", 0.0) >= 0.05 * mx]
+        if not w or mx <= 0:
+            continue
+        avg = {key: sum(c.get(key, 0.0) for c in w) / len(w) for key in w[0]}
+        gui = avg["GRBM_GUI_ACTIVE"] / xcc
+        mfma = 100.0 * avg.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (gui * cu_num * simd_per_cu)
+        lds = 100.0 * avg.get("SQ_LDS_IDX_ACTIVE", 0.0) / (gui * cu_num)
+        bc = avg.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        conf = 100.0 * bc / avg["SQ_LDS_IDX_ACTIVE"] if avg.get("SQ_LDS_IDX_ACTIVE") else 0.0
+        valu_per_mfma = (avg.get("SQ_INSTS_VALU", 0.0) / avg["SQ_INSTS_MFMA"]
+                         if avg.get("SQ_INSTS_MFMA") else float("nan"))
+        lds_per_mfma = (avg.get("SQ_INSTS_LDS", 0.0) / avg["SQ_INSTS_MFMA"]
+                        if avg.get("SQ_INSTS_MFMA") else float("nan"))
+        rows.append((gui, _demangle(k), len(w), mfma, lds, conf, valu_per_mfma, lds_per_mfma))
+    rows.sort(reverse=True)
+    lines = [f"# Counters: {title}", "",
+             "Commands (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first, "
+             "R = repository path):", "", "```"] + list(commands) + ["```", "",
+             "MFMA busy: `SQ_VALU_MFMA_BUSY_CYCLES` / (active cycles x 1024 SIMDs); LDS active: "
+             "`SQ_LDS_IDX_ACTIVE` / (active cycles x 256 CUs), active cycles = `GRBM_GUI_ACTIVE` "
+             "/ 8 (the counter comes summed over the 8 XCDs); bank conflicts: "
+             "`SQ_LDS_BANK_CONFLICT` / `SQ_LDS_IDX_ACTIVE`; instruction ratios from `SQ_INSTS_*` "
+             "(VALU counts the MFMAs too).  Averages over the working dispatches.", "",
+             "| kernel | dispatches | GPU-active cycles | MFMA busy % | LDS active % | "
+             "bank-conflict % of LDS cycles | VALU / MFMA | LDS / MFMA |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for gui, k, nw, mfma, lds, conf, vpm, lpm in rows:
+        lines.append(f"| `{k}` | {nw} | {gui:.0f} | {mfma:.1f} | {lds:.1f} | {conf:.1f} | "
+                     f"{vpm:.2f} | {lpm:.2f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {out}")
+
+
 def workload_128(args, dev, weights):
     """The smaller workloads at 128^3 (one JSON line each; not the benchmark).
 
@@ -1058,6 +1117,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.commands)
         return
     if args.summarize_traffic:
         rc, cc, pc = args.summarize_traffic

@@ -851,6 +851,12 @@ __global__ void __launch_bounds__(kBlock)
 // channels) sit in a three-slot ring; coarse plane K is stored at fine step
 // 2K - 1 and last read at 2K + 2.
 constexpr int CAT_BLOCK = 512;
+
+// Voxel slot of row a, x in a wave's FP32 stage ([slot][16 channels]): the
+// lowest bit is flipped by bit 2 of x and bit 1 of a, so that both halves'
+// stores (16 lanes per voxel group, four groups per instruction) fall into
+// both halves of the 32 LDS banks: two-way instead of four-way conflicts.
+__device__ inline int cat_slot(int a, int x) { return (a * ZT + x) ^ (((x >> 2) ^ (a >> 1)) & 1); }
 constexpr int CAT_KT = ZT / 2 + 2;          // coarse ring plane edge with halo
 constexpr int CAT_KRV = CAT_KT * CAT_KT;    // 100 coarse voxels per ring plane
 constexpr int CAT_KSLOT = CAT_KRV * 32;     // bf16 per coarse ring slot
@@ -1063,7 +1069,7 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * 16 + col] = acc[a][i];
+        for (int i = 0; i < 4; ++i) sf[cat_slot(a, 4 * g + i) * 16 + col] = acc[a][i];
     } else {
       // coarse half: kacc[P][px], M block of rows 4 wv + P (+ 2), x parity px
       f32x4z kacc[2][2];
@@ -1109,7 +1115,7 @@ __global__ void __launch_bounds__(CAT_BLOCK)
           for (int i = 0; i < 4; ++i) {
             const int m = 4 * g + i;
             const int a = P + 2 * (m >> 3), x = 2 * (m & 7) + px;
-            sf[((a * ZT) + x) * 16 + col] = kacc[P][px][i];
+            sf[cat_slot(a, x) * 16 + col] = kacc[P][px][i];
           }
     }
     __syncthreads();
@@ -1120,8 +1126,8 @@ __global__ void __launch_bounds__(CAT_BLOCK)
       const int r = lv / ZT, xl = lv % ZT;    // tile row, x
       const int x = x0 + xl, y = y0 + r;
       if (x < n && y < n) {
-        const float* s8a = stage[0][r >> 2] + ((r & 3) * ZT + xl) * 16 + part * 8;
-        const float* s8b = stage[1][r >> 2] + ((r & 3) * ZT + xl) * 16 + part * 8;
+        const float* s8a = stage[0][r >> 2] + cat_slot(r & 3, xl) * 16 + part * 8;
+        const float* s8b = stage[1][r >> 2] + cat_slot(r & 3, xl) * 16 + part * 8;
         __bf16 o8[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
