@@ -833,23 +833,21 @@ __global__ void __launch_bounds__(kBlock)
 // written and read back (two passes over 32 B per fine voxel).
 //
 // A block has 8 waves: waves 0-3 compute the skip half of rows 4 j .. 4 j + 3
-// (j = wave % 4) as k_conv_zm_pa does, waves 4-7 the coarse half of the same
-// rows, each into its own FP32 stage; after a second barrier every thread
-// adds the two stages for 8 channels of one voxel and stores.  (With one
-// wave per row group doing both halves, the 64 KB of staged weights left
-// room for one block per CU and one wave per SIMD: slower than the two
-// kernels it replaced.)
+// (j = wave % 4) as k_conv_zm_pa does, waves 4-7 the coarse half of the tile
+// plane, each into an FP32 stage; after a second barrier every thread adds
+// the two stages for 8 channels of one voxel and stores.
 //
-// Coarse half, per fine plane z (parity pz, coarse plane Z = z / 2): rows
-// 4 j + P and 4 j + P + 2 (P = 0, 1) share the y parity py = P, and with one
-// x parity px their 16 voxels (8 per row) form one M block whose coarse
-// voxels are (X0 + m % 8, Y0 + 2 j + m / 8).  For a coarse offset (ox, oy,
-// oz) the A fragment is the same for both x parities, so each (ty, tz) loads
-// 3 A fragments (ox = -1, 0, 1) for the 4 MFMAs of (px, tx).  B fragments
-// (the summed weights of all 8 classes, 64 KB) are read from LDS, staged once
-// per block.  The coarse planes Z-1 .. Z+1 (10 x 10 voxels with the halo, 32
-// channels) sit in a three-slot ring; coarse plane K is stored at fine step
-// 2K - 1 and last read at 2K + 2.
+// Coarse half, per fine plane z (parity pz, coarse plane Z = z / 2): coarse
+// wave w takes one parity class, y parity cP = (w / 2) % 2 and x parity
+// cpx = w % 2, over the whole 16 x 16 tile (8 x 8 voxels); its 16 summed
+// weight fragments (8 taps x 2 z parities, the B operand) stay in registers,
+// in the registers that hold a skip wave's weights.  M block b (0..3) holds
+// coarse rows b and b + 4 of the tile, so for the two y taps the input
+// fragment of (b, ty = 1) is that of (b + 1, ty = 0): per (tz, tx) five A
+// fragments from LDS feed eight MFMAs, and no weight is read from LDS.  The
+// coarse planes Z-1 .. Z+1 (10 x 10 voxels with the halo, 32 channels) sit
+// in a three-slot ring; coarse plane K is stored at fine step 2K - 1 and
+// last read at 2K + 2.
 constexpr int CAT_BLOCK = 512;
 
 // Voxel slot of row a, x in a wave's FP32 stage ([slot][16 channels]): the
@@ -862,7 +860,6 @@ constexpr int CAT_KRV = CAT_KT * CAT_KT;    // 100 coarse voxels per ring plane
 constexpr int CAT_KSLOT = CAT_KRV * 32;     // bf16 per coarse ring slot
 constexpr int CAT_KITEMS = CAT_KRV * 4;     // uint4 items per coarse plane
 constexpr int CAT_KPF = (CAT_KITEMS + CAT_BLOCK - 1) / CAT_BLOCK;
-constexpr int CAT_WL = 8 * 8 * 16 * 32;     // bf16 of the summed weights
 
 __global__ void __launch_bounds__(CAT_BLOCK)
     k_conv_cat(int n, int zc, const __bf16* __restrict__ coarse, const __bf16* __restrict__ skip,
@@ -876,7 +873,6 @@ __global__ void __launch_bounds__(CAT_BLOCK)
   constexpr int SLOT = ZRV * 16;
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
-  __shared__ __attribute__((aligned(16))) __bf16 wl[CAT_WL];
   __shared__ __attribute__((aligned(16))) float stage[2][4][4 * ZT * 16];
   __shared__ __attribute__((aligned(16))) int votes[4][8];
   __shared__ uint8_t live_s[ZMAXC + 3];
@@ -916,20 +912,22 @@ __global__ void __launch_bounds__(CAT_BLOCK)
     return a.x | a.y | a.z | a.w | b.x | b.y | b.z | b.w;
   };
 
-  // the summed coarse weights, [p * 8 + tap][c / 8][co][8] (conflict-free
-  // fragment reads, as in k_upconv)
-  for (int q = threadIdx.x; q < CAT_WL / 8; q += CAT_BLOCK) {
-    const int cl = q % 16, kc = (q / 16) % 4, pt = q / 64;
-    *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) =
-        *reinterpret_cast<const uint4*>(weff + ((int64_t)pt * 16 + cl) * 32 + kc * 8);
-  }
-
-  // skip-half weight fragments (B operand), as in k_conv_zm_pa
-  bf16x8z bw[ZSTEPS];
+  // weight fragments (B operand) in registers, one array for both roles so
+  // that they share registers: a skip wave's ZSTEPS steps (as in
+  // k_conv_zm_pa); a coarse wave's 16 summed fragments (tap, z parity) of its
+  // parity class (y parity cP, x parity cpx)
+  const int cP = (wave >> 1) & 1, cpx = wave & 1;
+  constexpr int NWR = 16;
+  static_assert(ZSTEPS <= NWR, "skip steps");
+  bf16x8z wr[NWR];
 #pragma unroll
-  for (int st = 0; st < ZSTEPS; ++st) {
-    const int tap = g < 2 ? zm_tap0(st) : zm_tap1(st);
-    bw[st] = *reinterpret_cast<const bf16x8z*>(wskip + ((int64_t)col * ZTAPS + tap) * 16 + (g & 1) * 8);
+  for (int j = 0; j < NWR; ++j) {
+    const int st = j < ZSTEPS ? j : 0;
+    const int stap = g < 2 ? zm_tap0(st) : zm_tap1(st);
+    const int p = cpx + 2 * cP + 4 * (j >> 3);
+    const __bf16* src = coarse_role ? weff + (((int64_t)(p * 8 + (j & 7)) * 16 + col) * 32 + 8 * g)
+                                    : wskip + ((int64_t)col * ZTAPS + stap) * 16 + (g & 1) * 8;
+    wr[j] = *reinterpret_cast<const bf16x8z*>(src);
   }
 
   // skip plane loads: per-item offsets fixed for the block
@@ -1062,7 +1060,7 @@ __global__ void __launch_bounds__(CAT_BLOCK)
             const int st = zm_group_step(gi, dy);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
-              acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[st], acc[a], 0, 0, 0);
+              acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], wr[st], acc[a], 0, 0, 0);
           }
         }
       }
@@ -1071,52 +1069,52 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
         for (int i = 0; i < 4; ++i) sf[cat_slot(a, 4 * g + i) * 16 + col] = acc[a][i];
     } else {
-      // coarse half: kacc[P][px], M block of rows 4 wv + P (+ 2), x parity px
-      f32x4z kacc[2][2];
+      // coarse half: the wave's parity class (cP, cpx) over the whole tile
+      // plane; M block b holds coarse rows b and b + 4 of the tile (lane row
+      // m: coarse row b + 4 (m >> 3), coarse x m & 7), so that the input
+      // fragment of (b, ty = 1) is that of (b + 1, ty = 0): five fragments per
+      // (tz, tx) feed eight MFMAs
+      f32x4z kacc[4];
 #pragma unroll
-      for (int P = 0; P < 2; ++P)
+      for (int b = 0; b < 4; ++b) kacc[b] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      const int Zc = z >> 1;
 #pragma unroll
-        for (int px = 0; px < 2; ++px) kacc[P][px] = f32x4z{0.f, 0.f, 0.f, 0.f};
-      const int pz = z & 1, Zc = z >> 1;
+      for (int pz = 0; pz < 2; ++pz) {
+        if (pz != (z & 1)) continue;  // block-uniform; keeps the weight index static
 #pragma unroll
-      for (int tz = 0; tz < 2; ++tz) {
-        const int oz = tz - (pz ? 0 : 1);
-        const __bf16* ks = kring + kslot(Zc + oz) * CAT_KSLOT + g * CAT_KRV * 8;
+        for (int tz = 0; tz < 2; ++tz) {
+          const int oz = tz - (pz ? 0 : 1);
+          const __bf16* ks = kring + kslot(Zc + oz) * CAT_KSLOT + g * CAT_KRV * 8;
 #pragma unroll
-        for (int ty = 0; ty < 2; ++ty) {
-          bf16x8z A[2][3];
+          for (int tx = 0; tx < 2; ++tx) {
+            // ring column of coarse x offset tx - (cpx ? 0 : 1), row of row
+            // offset e - (cP ? 0 : 1) (both with the halo's +1)
+            const int cx = (col & 7) + tx + cpx;
+            bf16x8z A[5];
 #pragma unroll
-          for (int P = 0; P < 2; ++P) {
-            const int cy = 2 * wv + (col >> 3) + ty - (P ? 0 : 1) + 1;
+            for (int e = 0; e < 5; ++e) {
+              const int cy = e + 4 * (col >> 3) + cP;
+              A[e] = *reinterpret_cast<const bf16x8z*>(ks + (cy * CAT_KT + cx) * 8);
+            }
 #pragma unroll
-            for (int ox = 0; ox < 3; ++ox)
-              A[P][ox] = *reinterpret_cast<const bf16x8z*>(ks + (cy * CAT_KT + (col & 7) + ox) * 8);
+            for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+                kacc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b + ty], wr[pz * 8 + tx + 2 * ty + 4 * tz],
+                                                                  kacc[b], 0, 0, 0);
           }
-#pragma unroll
-          for (int P = 0; P < 2; ++P)
-#pragma unroll
-            for (int px = 0; px < 2; ++px)
-#pragma unroll
-              for (int tx = 0; tx < 2; ++tx) {
-                const int p = px + 2 * P + 4 * pz, tap = tx + 2 * ty + 4 * tz;
-                const bf16x8z B = *reinterpret_cast<const bf16x8z*>(wl + (((p * 8 + tap) * 4 + g) * 16 + col) * 8);
-                // coarse x offset tx - (px ? 0 : 1), as an index into A (0..2)
-                kacc[P][px] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[P][tx + px], B, kacc[P][px], 0, 0, 0);
-              }
         }
       }
-      // into stage 1, same layout: M row m = 4 g + i is the voxel of row
-      // P + 2 (m / 8), x 2 (m % 8) + px
+      // into stage 1, same layout as the skip half: lane row m = 4 g + i is
+      // fine row 2 (b + 4 (m / 8)) + cP, fine x 2 (m % 8) + cpx
 #pragma unroll
-      for (int P = 0; P < 2; ++P)
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int px = 0; px < 2; ++px)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int m = 4 * g + i;
-            const int a = P + 2 * (m >> 3), x = 2 * (m & 7) + px;
-            sf[cat_slot(a, x) * 16 + col] = kacc[P][px][i];
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int m = 4 * g + i;
+          const int r = 2 * (b + 4 * (m >> 3)) + cP, x = 2 * (m & 7) + cpx;
+          stage[1][r >> 2][cat_slot(r & 3, x) * 16 + col] = kacc[b][i];
+        }
     }
     __syncthreads();
     // both halves, ReLU, bf16: thread t takes 8 channels of one voxel

@@ -55,44 +55,56 @@ __device__ inline TileXYZ tile_of(int n, int b) {
 
 int conv_tiles(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + TZ - 1) / TZ); }
 
-// Stage channels [c0, c0+CK) of the (possibly concatenated) input over the
-// halo of a tile into LDS as [HV][CK] bf16; zero outside the volume.  All of
-// a thread's loads are issued (from valid clamped addresses) before the
-// first store, so the staging waits for one load latency, not one per item.
+// Channels [c0, c0+CK) of the (possibly concatenated) input over the halo of
+// a tile, as [HV][CK] bf16, zero outside the volume: load() issues all of a
+// thread's loads (from valid clamped addresses), store() writes them to LDS,
+// so the staging waits for one load latency, not one per item.
+template <int CK>
+struct HaloRegs {
+  static constexpr int PV = CK / 8;  // 16-byte vectors per voxel
+  static constexpr int NV = HV * PV;
+  static constexpr int NI = (NV + kBlock - 1) / kBlock;
+  uint4 raw[NI];
+  bool ok[NI];
+
+  __device__ inline void load(const NetSrc& s, int n, TileXYZ t, int c0) {
+    const int nc = n / 2;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int vi = threadIdx.x + k * kBlock;
+      const int hv = vi / PV, part = vi - hv * PV;
+      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+      const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
+      ok[k] = vi < NV && inside(gx, gy, gz, n);
+      const int c = c0 + part * 8;
+      const __bf16* src = s.a;
+      if (ok[k]) {
+        if (c < s.ca) {
+          const int64_t v = s.up ? vox(gx >> 1, gy >> 1, gz >> 1, nc) : vox(gx, gy, gz, n);
+          src = s.a + v * s.ca + c;
+        } else {
+          src = s.b + vox(gx, gy, gz, n) * s.cb + (c - s.ca);
+        }
+      }
+      raw[k] = *reinterpret_cast<const uint4*>(src);
+    }
+  }
+  __device__ inline void store(__bf16* __restrict__ lds) const {
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      const int vi = threadIdx.x + k * kBlock;
+      if (vi < NV)
+        *reinterpret_cast<uint4*>(lds + vi * 8) = ok[k] ? raw[k] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+};
+
 template <int CK>
 __device__ inline void load_halo(__bf16* __restrict__ lds, const NetSrc& s, int n, TileXYZ t,
                                  int c0) {
-  constexpr int PV = CK / 8;  // 16-byte vectors per voxel
-  constexpr int NV = HV * PV;
-  constexpr int NI = (NV + kBlock - 1) / kBlock;
-  const int nc = n / 2;
-  uint4 raw[NI];
-  bool ok[NI];
-#pragma unroll
-  for (int k = 0; k < NI; ++k) {
-    const int vi = threadIdx.x + k * kBlock;
-    const int hv = vi / PV, part = vi - hv * PV;
-    const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-    const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
-    ok[k] = vi < NV && inside(gx, gy, gz, n);
-    const int c = c0 + part * 8;
-    const __bf16* src = s.a;
-    if (ok[k]) {
-      if (c < s.ca) {
-        const int64_t v = s.up ? vox(gx >> 1, gy >> 1, gz >> 1, nc) : vox(gx, gy, gz, n);
-        src = s.a + v * s.ca + c;
-      } else {
-        src = s.b + vox(gx, gy, gz, n) * s.cb + (c - s.ca);
-      }
-    }
-    raw[k] = *reinterpret_cast<const uint4*>(src);
-  }
-#pragma unroll
-  for (int k = 0; k < NI; ++k) {
-    const int vi = threadIdx.x + k * kBlock;
-    if (vi < NV)
-      *reinterpret_cast<uint4*>(lds + vi * 8) = ok[k] ? raw[k] : make_uint4(0u, 0u, 0u, 0u);
-  }
+  HaloRegs<CK> h;
+  h.load(s, n, t, c0);
+  h.store(lds);
 }
 
 // ------------------------------------------------------------ convolution
@@ -107,14 +119,17 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int STEPS = CK == 16 ? 14 : 7;
   constexpr int HALO_E = HV * CK;
   constexpr int OUT_E = TX * TY * TZ * COUT;
-  constexpr int LDS_E = HALO_E > OUT_E ? HALO_E : OUT_E;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[LDS_E];
   // 64-output-channel layers (the coarsest level) stage each chunk's weights
   // in LDS as [tap][half][c_out][8]: the 16 lanes of a fragment read
   // consecutive 16-byte words, and no step waits on an L2 load
   constexpr bool WL = CK == 16 && COUT == 64;
   constexpr int WL_E = WL ? TAPS * 2 * COUT * 8 : 8;
-  __shared__ __attribute__((aligned(16))) __bf16 wl[WL_E];
+  // the epilogue's output tile overlays the halo and the weights, so that
+  // the 64-channel layers (78 KB) fit two blocks per CU
+  constexpr int SM_E = HALO_E + WL_E > OUT_E ? HALO_E + WL_E : OUT_E;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[SM_E];
+  __bf16* const lds = smem;
+  __bf16* const wl = smem + HALO_E;
   const TileXYZ t = tile_of(n, blockIdx.x);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
   f32x4 acc[4][NT];
@@ -123,15 +138,17 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // a chunk's halo and (WL) weight words: all of a thread's loads are issued
+  // before its first store
+  constexpr int NW = TAPS * 2 * COUT;
+  constexpr int NWI = WL ? (NW + kBlock - 1) / kBlock : 1;
 #pragma unroll 1
   for (int c0 = 0; c0 < CIN; c0 += CK) {
     __syncthreads();
-    load_halo<CK>(lds, src, n, t, c0);
+    HaloRegs<CK> hr;
+    uint4 wr[NWI];
+    hr.load(src, n, t, c0);
     if (WL) {
-      // all loads of the thread first, then the stores (as in load_halo)
-      constexpr int NW = TAPS * 2 * COUT;
-      constexpr int NWI = (NW + kBlock - 1) / kBlock;
-      uint4 wr[NWI];
 #pragma unroll
       for (int k = 0; k < NWI; ++k) {
         const int q = threadIdx.x + k * kBlock;
@@ -139,6 +156,9 @@ __global__ void __launch_bounds__(kBlock)
         const int co = qq % COUT, half = (qq / COUT) & 1, tap = qq / (2 * COUT);
         wr[k] = *reinterpret_cast<const uint4*>(w + ((int64_t)co * TAPS + tap) * CIN + c0 + half * 8);
       }
+    }
+    hr.store(lds);
+    if (WL) {
 #pragma unroll
       for (int k = 0; k < NWI; ++k) {
         const int q = threadIdx.x + k * kBlock;

@@ -33,6 +33,7 @@ constexpr int UMAXZ = 128;  // coarse planes per block at most
 // weights per output group, so its blocks take runs of 4 coarse planes.
 constexpr int UP_TARGET32 = 512;  // blocks for the 32-channel layer
 constexpr int UP_TARGET64 = 256;  // blocks for the 64-channel layer
+constexpr int UP_SB = 8;  // 16-byte weight words per thread and staging batch
 
 // Coarse offset of fine tap d (-1, 0, 1) for parity q (0, 1).
 __host__ __device__ constexpr int up_off(int q, int d) { return (q + d + 2) / 2 - 1; }
@@ -102,10 +103,21 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();  // the previous group's weights are no longer read
     // LDS layout [p*8 + tap][c / 8][col][8]: the 16 lanes of one weight
     // fragment read consecutive 16-byte words (no bank conflicts)
-    for (int q = threadIdx.x; q < WL / 8; q += kBlock) {
-      const int cl = q % 16, kc = (q / 16) % (CC / 8), pt = q / (16 * (CC / 8));
-      *reinterpret_cast<uint4*>(wl + (int64_t)q * 8) = *reinterpret_cast<const uint4*>(
-          weff + ((int64_t)pt * COUT + t * 16 + cl) * CC + kc * 8);
+    // (batches of UP_SB words per thread: all loads of a batch are issued
+    // before its first store)
+    static_assert((WL / 8) % (kBlock * UP_SB) == 0, "staging batches");
+#pragma unroll 1
+    for (int q0 = 0; q0 < WL / 8; q0 += kBlock * UP_SB) {
+      uint4 tmp[UP_SB];
+#pragma unroll
+      for (int j = 0; j < UP_SB; ++j) {
+        const int q = q0 + threadIdx.x + j * kBlock;
+        const int cl = q % 16, kc = (q / 16) % (CC / 8), pt = q / (16 * (CC / 8));
+        tmp[j] = *reinterpret_cast<const uint4*>(weff + ((int64_t)pt * COUT + t * 16 + cl) * CC + kc * 8);
+      }
+#pragma unroll
+      for (int j = 0; j < UP_SB; ++j)
+        *reinterpret_cast<uint4*>(wl + (int64_t)(q0 + threadIdx.x + j * kBlock) * 8) = tmp[j];
     }
     __syncthreads();
 
