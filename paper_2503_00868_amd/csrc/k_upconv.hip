@@ -231,6 +231,181 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// ------------------------------------------------- one parity class per wave
+// The same upsampled half as k_upconv, for the fine level n (a multiple of
+// 16) with 64 coarse channels and 32 outputs, organised like the coarse half
+// of k_conv_cat: a block of 8 waves owns a 16 x 16 fine tile (8 x 8 coarse
+// voxels) and a run of coarse planes Z, and computes the fine planes 2Z and
+// 2Z + 1 of each.  Wave w takes parity class (px, py, pz) = bits 0, 1, 2 of
+// w and keeps that class's summed weights (8 taps x 2 K-steps x 2 output
+// groups = 32 fragments) in registers for the whole run.  The coarse planes,
+// 10 x 10 with the halo and 64 channels, pass through a four-slot LDS ring
+// (one barrier per plane: plane Z + 1 is stored while Z - 3 is no longer
+// read).  The weights are the MFMA's A operand and the coarse voxels its B
+// operand, so the result is [output channel][voxel] and each lane stores 4
+// channels of one voxel (8 bytes of fp16) straight from its registers.  M
+// block b (as in k_conv_cat) holds coarse rows b and b + 4 of the tile, so
+// five B fragments per (tz, tx, K-step) feed sixteen MFMAs.
+constexpr int UC_BLOCK = 512;
+constexpr int UC_KT = 10;                  // ring plane edge (8 + halo)
+constexpr int UC_KRV = UC_KT * UC_KT;      // 100 coarse voxels per ring plane
+constexpr int UC_CC = 64, UC_COUT = 32;
+constexpr int UC_SLOT = UC_KRV * UC_CC;    // bf16 per ring slot
+constexpr int UC_ITEMS = UC_KRV * (UC_CC / 8);  // uint4 items per coarse plane
+constexpr int UC_PF = (UC_ITEMS + UC_BLOCK - 1) / UC_BLOCK;
+#ifndef UC_TARGET
+#define UC_TARGET 512
+#endif
+constexpr int UC_MAXZ = 64;                // coarse planes per block at most
+
+__global__ void __launch_bounds__(UC_BLOCK)
+    k_upconv_cls(int n, int zr, const __bf16* __restrict__ coarse, const __bf16* __restrict__ weff,
+                 _Float16* __restrict__ out, const int* __restrict__ flags,
+                 const uint8_t* __restrict__ act) {
+  if (flags && flags[F_DONE]) return;
+  constexpr int KS = UC_CC / 32, NG = UC_COUT / 16;
+  __shared__ __attribute__((aligned(16))) __bf16 ring[4 * UC_SLOT];
+  __shared__ uint8_t live_s[2 * UC_MAXZ];
+  const int nc = n >> 1, tpr = n / 16;
+  int tile, run;
+  net_block_of(blockIdx.x, gridDim.x, tpr, tile, run);
+  const int X0 = (tile % tpr) * 8, Y0 = (tile / tpr) * 8;  // coarse tile origin
+  const int Z0 = run * zr, Z1 = min(Z0 + zr, nc);
+  if (Z0 >= nc) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int px = wave & 1, py = (wave >> 1) & 1, pz = wave >> 2;
+  // fine tile-plane activity of the run's output planes (planes marked 0
+  // are not read by the layer that adds these sums: not computed)
+  if (act) {
+    int any = 0;
+    for (int t = threadIdx.x; t < 2 * (Z1 - Z0); t += UC_BLOCK) {
+      live_s[t] = act[(int64_t)(2 * Z0 + t) * (tpr * tpr) + tile];
+      any |= live_s[t];
+    }
+    if (!__syncthreads_or(any)) return;
+  }
+
+  // the class's weight fragments (A operand): lane (g, col) holds output
+  // channel 16 grp + col, coarse channels 32 ks + 8 g .. + 7 of tap t
+  const int p = px + 2 * py + 4 * pz;
+  bf16x8u wr[NG][KS][8];
+#pragma unroll
+  for (int grp = 0; grp < NG; ++grp)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        wr[grp][ks][t] = *reinterpret_cast<const bf16x8u*>(
+            weff + ((int64_t)(p * 8 + t) * UC_COUT + grp * 16 + col) * UC_CC + ks * 32 + 8 * g);
+
+  // coarse plane loads: item it = 8 v + part (v a ring voxel, part 8 of the
+  // 64 channels); ring layout [part][voxel][8]
+  uint32_t koff[UC_PF];
+  bool kok[UC_PF];
+#pragma unroll
+  for (int k = 0; k < UC_PF; ++k) {
+    const int it = threadIdx.x + k * UC_BLOCK;
+    const int cv = it >> 3, part = it & 7;
+    const int cx = X0 - 1 + cv % UC_KT, cy = Y0 - 1 + cv / UC_KT;
+    kok[k] = it < UC_ITEMS && (unsigned)cx < (unsigned)nc && (unsigned)cy < (unsigned)nc;
+    koff[k] = kok[k] ? (uint32_t)(((int64_t)cx + (int64_t)nc * cy) * UC_CC + part * 8) : 0u;
+  }
+  const int64_t cplane = (int64_t)nc * nc * UC_CC;
+  uint4 kpf[UC_PF];
+  bool kpf_on = false;
+  auto load_coarse = [&](int K) {
+    kpf_on = (unsigned)K < (unsigned)nc;
+    const __bf16* pc = coarse + (int64_t)(kpf_on ? K : 0) * cplane;
+#pragma unroll
+    for (int k = 0; k < UC_PF; ++k) kpf[k] = *reinterpret_cast<const uint4*>(pc + koff[k]);
+  };
+  auto store_coarse = [&](int K) {
+    __bf16* slot = ring + ((K + 4) & 3) * UC_SLOT;
+#pragma unroll
+    for (int k = 0; k < UC_PF; ++k) {
+      const int it = threadIdx.x + k * UC_BLOCK;
+      if (it < UC_ITEMS) {
+        const bool on = kpf_on && kok[k];
+        uint4 v = kpf[k];
+        // component selects (a select of whole vectors went through scratch)
+        v.x = on ? v.x : 0u;
+        v.y = on ? v.y : 0u;
+        v.z = on ? v.z : 0u;
+        v.w = on ? v.w : 0u;
+        *reinterpret_cast<uint4*>(slot + ((it & 7) * UC_KRV + (it >> 3)) * 8) = v;
+      }
+    }
+  };
+
+  // prologue: planes Z0 - 1 and Z0 in the ring, Z0 + 1 in flight
+  load_coarse(Z0 - 1);
+  store_coarse(Z0 - 1);
+  load_coarse(Z0);
+  store_coarse(Z0);
+  load_coarse(Z0 + 1);
+
+#pragma unroll 1
+  for (int Z = Z0; Z < Z1; ++Z) {
+    // slot of Z + 1 last held Z - 3, read before the previous barrier
+    store_coarse(Z + 1);
+    __syncthreads();
+    if (Z + 2 <= Z1) load_coarse(Z + 2);
+    const int fz = 2 * Z + pz;
+    if (act && !live_s[fz - 2 * Z0]) continue;  // wave-uniform
+
+    f32x4u acc[NG][4];
+#pragma unroll
+    for (int grp = 0; grp < NG; ++grp)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[grp][b] = f32x4u{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tz = 0; tz < 2; ++tz) {
+      // coarse plane offset tz - (pz ? 0 : 1)
+      const __bf16* sl = ring + ((Z + tz - 1 + pz + 4) & 3) * UC_SLOT;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const __bf16* sp = sl + (ks * 4 + g) * UC_KRV * 8;
+#pragma unroll
+        for (int tx = 0; tx < 2; ++tx) {
+          // ring column of coarse x offset tx - (px ? 0 : 1), row of row
+          // offset e - (py ? 0 : 1), both with the halo's +1
+          const int cx = (col & 7) + tx + px;
+          bf16x8u B[5];
+#pragma unroll
+          for (int e = 0; e < 5; ++e) {
+            const int cy = e + 4 * (col >> 3) + py;
+            B[e] = *reinterpret_cast<const bf16x8u*>(sp + (cy * UC_KT + cx) * 8);
+          }
+#pragma unroll
+          for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+            for (int grp = 0; grp < NG; ++grp)
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+                acc[grp][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    wr[grp][ks][tx + 2 * ty + 4 * tz], B[b + ty], acc[grp][b], 0, 0, 0);
+        }
+      }
+    }
+    // lane (g, col): channels 16 grp + 4 g .. + 3 of coarse voxel (col % 8,
+    // b + 4 (col / 8)) of the tile, i.e. fine voxel (2 x + px, 2 y + py, fz)
+    const int fx = 2 * (X0 + (col & 7)) + px;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int fy = 2 * (Y0 + b + 4 * (col >> 3)) + py;
+      if (fx >= n || fy >= n) continue;
+      _Float16* o = out + ((int64_t)fx + (int64_t)n * (fy + (int64_t)n * fz)) * UC_COUT + 4 * g;
+#pragma unroll
+      for (int grp = 0; grp < NG; ++grp) {
+        _Float16 h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = (_Float16)acc[grp][b][i];
+        *reinterpret_cast<uint2*>(o + grp * 16) = *reinterpret_cast<const uint2*>(h);
+      }
+    }
+  }
+}
+
 // weff[p][tap][co][c] = sum of W[co][c][fine tap] over the fine taps of
 // parity class p that read coarse offset tap; wskip = the skip channels in
 // the forward layout [cout_p][28][cin - cc] (tap 27 and co >= cout zero).
@@ -268,6 +443,20 @@ __global__ void __launch_bounds__(kBlock)
       wskip[k] = (__bf16)v;
     }
   }
+}
+
+bool net_upconv_cls(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
+                    _Float16* out, const int* flags, const uint8_t* act) {
+  if (cc != UC_CC || cout != UC_COUT || n % 16 != 0) return false;
+  const int nc = n / 2, tiles = (n / 16) * (n / 16);
+  int runs = (UC_TARGET + tiles - 1) / tiles;
+  if (runs > nc) runs = nc;
+  int zr = (nc + runs - 1) / runs;
+  if (zr > UC_MAXZ) zr = UC_MAXZ;
+  const int blocks = tiles * ((nc + zr - 1) / zr);
+  hipLaunchKernelGGL(k_upconv_cls, dim3(blocks), dim3(UC_BLOCK), 0, c->stream, n, zr, coarse, weff,
+                     out, flags, act);
+  return true;
 }
 
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,

@@ -190,7 +190,8 @@ int split_conv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const 
   if (cc == 32 && cout == 16 && skip.ca == 16 && !skip.b &&
       net_conv_cat(c, n, coarse, skip.a, weff, wskip, out, flags, act_f))
     return SIM_OK;
-  if (!net_upconv(c, n, cc, cout, coarse, weff, T, flags, act_c) ||
+  if (!(net_upconv_cls(c, n, cc, cout, coarse, weff, T, flags, act_f) ||
+        net_upconv(c, n, cc, cout, coarse, weff, T, flags, act_c)) ||
       !net_conv(c, n, skip.ca, cout, NET_EPI_RELU_ADD, skip, wskip,
                 NetOut{out, nullptr, nullptr, nullptr, nullptr, T, nullptr, act_f}, flags)) {
     c->err = "no split convolution kernel for this channel configuration";

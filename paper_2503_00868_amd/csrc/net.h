@@ -74,6 +74,13 @@ void net_pool(sim_ctx* c, int n, int C, const __bf16* in, __bf16* out, const int
 // coarse tile-plane marked 0 are not computed (they stay zero).
 bool net_upconv(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
                 _Float16* out, const int* flags, const uint8_t* act);
+// The same for 64 coarse channels and 32 outputs with one parity class per
+// wave (k_upconv_cls).  act (nullable): activity map of the fine output
+// level; the tile-planes marked 0 are not computed (the layer that adds the
+// sums does not read them).  False for another channel configuration or
+// when n is not a multiple of 16.
+bool net_upconv_cls(sim_ctx* c, int n, int cc, int cout, const __bf16* coarse, const __bf16* weff,
+                    _Float16* out, const int* flags, const uint8_t* act);
 // The fine decoder layer with 32 coarse and 16 skip channels and 16 outputs
 // in one pass: out = ReLU(conv(cat(up(coarse), skip))) (bf16), the upsampled
 // half through weff as net_upconv, the skip half through wskip ([16][28][16]).
