@@ -850,11 +850,10 @@ __global__ void __launch_bounds__(kBlock)
 // last read at 2K + 2.
 constexpr int CAT_BLOCK = 512;
 
-// Voxel slot of row a, x in a wave's FP32 stage ([slot][16 channels]): the
-// lowest bit is flipped by bit 2 of x and bit 1 of a, so that both halves'
-// stores (16 lanes per voxel group, four groups per instruction) fall into
-// both halves of the 32 LDS banks: two-way instead of four-way conflicts.
-__device__ inline int cat_slot(int a, int x) { return (a * ZT + x) ^ (((x >> 2) ^ (a >> 1)) & 1); }
+// 16-byte chunk of channels 4 q .. 4 q + 3 of stage voxel x: the coarse
+// waves' stores (voxels two apart in x) would put four lanes on the same
+// banks without the swizzle, two with it
+__device__ inline int cat_chunk(int q, int x) { return q ^ ((x >> 1) & 3); }
 constexpr int CAT_KT = ZT / 2 + 2;          // coarse ring plane edge with halo
 constexpr int CAT_KRV = CAT_KT * CAT_KT;    // 100 coarse voxels per ring plane
 constexpr int CAT_KSLOT = CAT_KRV * 32;     // bf16 per coarse ring slot
@@ -873,7 +872,8 @@ __global__ void __launch_bounds__(CAT_BLOCK)
   constexpr int SLOT = ZRV * 16;
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
-  __shared__ __attribute__((aligned(16))) float stage[2][4][4 * ZT * 16];
+  // the coarse half's partial sums of the last two planes, [voxel y*16+x][16]
+  __shared__ __attribute__((aligned(16))) float stage[2][ZT * ZT * 16];
   __shared__ __attribute__((aligned(16))) int votes[4][8];
   __shared__ uint8_t live_s[ZMAXC + 3];
 
@@ -1028,7 +1028,30 @@ __global__ void __launch_bounds__(CAT_BLOCK)
   load_plane(z0 + 1);
   load_coarse(Z0 + 1);
 
-  float* sf = stage[coarse_role ? 1 : 0][wv];
+  // Skip waves lag one plane: at plane z (after its barrier) they finish
+  // plane z - 1 from their accumulators and the coarse partial sums that the
+  // coarse waves staged during plane z - 1, then compute plane z's skip half;
+  // the stage is double-buffered by plane parity, so one barrier per plane
+  // orders both.  Both halves use the weights as the MFMA's A operand: lane
+  // (g, col) holds output channels 4 g .. 4 g + 3 of voxel col of its M block.
+  f32x4z acc[4];
+  int zprev = -1;  // skip waves: plane whose accumulators are pending
+  auto finish = [&]() {
+    // plane zprev, rows 4 wv + a, x = col: skip + coarse, ReLU, 4 bf16
+    const float* st = stage[zprev & 1];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int y = 4 * wv + a;
+      const float4 c4 = *reinterpret_cast<const float4*>(st + (y * ZT + col) * 16 + 4 * cat_chunk(g, col));
+      const float v[4] = {acc[a][0] + c4.x, acc[a][1] + c4.y, acc[a][2] + c4.z, acc[a][3] + c4.w};
+      __bf16 h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = (__bf16)(v[i] > 0.f ? v[i] : 0.f);
+      *reinterpret_cast<uint2*>(out + ((int64_t)(x0 + col) + (int64_t)n * (y0 + y + (int64_t)n * zprev)) * 16 +
+                                4 * g) = *reinterpret_cast<const uint2*>(h);
+    }
+    zprev = -1;
+  };
   auto plane_step = [&](int z) {
     // coarse plane (z + 1) / 2 is first read at odd z
     if (z & 1) store_coarse((z + 1) >> 1);
@@ -1038,11 +1061,11 @@ __global__ void __launch_bounds__(CAT_BLOCK)
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
     nz_0 = nz_p;
+    if (!coarse_role && zprev >= 0) finish();
     if (!live(z)) return;
 
     if (!coarse_role) {
-      // skip half (as k_conv_zm_pa), into stage 0 [row a][x][channel]
-      f32x4z acc[4];
+      // skip half (as k_conv_zm_pa, operands swapped)
 #pragma unroll
       for (int a = 0; a < 4; ++a) acc[a] = f32x4z{0.f, 0.f, 0.f, 0.f};
       const __bf16* sm = ring + ((z + 3) & 3) * SLOT;
@@ -1060,20 +1083,17 @@ __global__ void __launch_bounds__(CAT_BLOCK)
             const int st = zm_group_step(gi, dy);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
-              acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], wr[st], acc[a], 0, 0, 0);
+              acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[st], f[a + dy], acc[a], 0, 0, 0);
           }
         }
       }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sf[cat_slot(a, 4 * g + i) * 16 + col] = acc[a][i];
+      zprev = z;
     } else {
       // coarse half: the wave's parity class (cP, cpx) over the whole tile
-      // plane; M block b holds coarse rows b and b + 4 of the tile (lane row
-      // m: coarse row b + 4 (m >> 3), coarse x m & 7), so that the input
-      // fragment of (b, ty = 1) is that of (b + 1, ty = 0): five fragments per
-      // (tz, tx) feed eight MFMAs
+      // plane; M block b holds coarse rows b and b + 4 of the tile (voxel
+      // col: coarse row b + 4 (col >> 3), coarse x col & 7), so that the
+      // input fragment of (b, ty = 1) is that of (b + 1, ty = 0): five
+      // fragments per (tz, tx) feed eight MFMAs
       f32x4z kacc[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) kacc[b] = f32x4z{0.f, 0.f, 0.f, 0.f};
@@ -1100,45 +1120,26 @@ __global__ void __launch_bounds__(CAT_BLOCK)
             for (int ty = 0; ty < 2; ++ty)
 #pragma unroll
               for (int b = 0; b < 4; ++b)
-                kacc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b + ty], wr[pz * 8 + tx + 2 * ty + 4 * tz],
+                kacc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[pz * 8 + tx + 2 * ty + 4 * tz], A[b + ty],
                                                                   kacc[b], 0, 0, 0);
           }
         }
       }
-      // into stage 1, same layout as the skip half: lane row m = 4 g + i is
-      // fine row 2 (b + 4 (m / 8)) + cP, fine x 2 (m % 8) + cpx
+      // to the stage of this plane: fine voxel (2 (col % 8) + cpx,
+      // 2 (b + 4 (col / 8)) + cP), channels 4 g .. 4 g + 3
+      float* st = stage[z & 1];
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int m = 4 * g + i;
-          const int r = 2 * (b + 4 * (m >> 3)) + cP, x = 2 * (m & 7) + cpx;
-          stage[1][r >> 2][cat_slot(r & 3, x) * 16 + col] = kacc[b][i];
-        }
-    }
-    __syncthreads();
-    // both halves, ReLU, bf16: thread t takes 8 channels of one voxel
-    {
-      const int it = threadIdx.x;
-      const int lv = it >> 1, part = it & 1;  // lv: voxel of the tile plane
-      const int r = lv / ZT, xl = lv % ZT;    // tile row, x
-      const int x = x0 + xl, y = y0 + r;
-      if (x < n && y < n) {
-        const float* s8a = stage[0][r >> 2] + cat_slot(r & 3, xl) * 16 + part * 8;
-        const float* s8b = stage[1][r >> 2] + cat_slot(r & 3, xl) * 16 + part * 8;
-        __bf16 o8[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float v = s8a[e] + s8b[e];
-          o8[e] = (__bf16)(v > 0.f ? v : 0.f);
-        }
-        *reinterpret_cast<uint4*>(out + ((int64_t)x + (int64_t)n * (y + (int64_t)n * z)) * 16 + part * 8) =
-            *reinterpret_cast<const uint4*>(o8);
+      for (int b = 0; b < 4; ++b) {
+        const int y = 2 * (b + 4 * (col >> 3)) + cP, x = 2 * (col & 7) + cpx;
+        *reinterpret_cast<float4*>(st + (y * ZT + x) * 16 + 4 * cat_chunk(g, x)) =
+            make_float4(kacc[b][0], kacc[b][1], kacc[b][2], kacc[b][3]);
       }
     }
-    // the stages are written again only after the next plane's barrier
   };
   for (int z = z0; z < z1; ++z) plane_step(z);
+  // the last plane's coarse partial sums
+  __syncthreads();
+  if (!coarse_role && zprev >= 0) finish();
 }
 
 bool net_conv_cat(sim_ctx* c, int n, const __bf16* coarse, const __bf16* skip, const __bf16* weff,

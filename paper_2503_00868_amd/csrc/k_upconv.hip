@@ -253,9 +253,8 @@ constexpr int UC_CC = 64, UC_COUT = 32;
 constexpr int UC_SLOT = UC_KRV * UC_CC;    // bf16 per ring slot
 constexpr int UC_ITEMS = UC_KRV * (UC_CC / 8);  // uint4 items per coarse plane
 constexpr int UC_PF = (UC_ITEMS + UC_BLOCK - 1) / UC_BLOCK;
-#ifndef UC_TARGET
-#define UC_TARGET 512
-#endif
+constexpr int UC_TARGET = 256;             // blocks to aim for (one per CU: 128 -> 65 us at
+                                           // 256^3 against 512 blocks, 73 us)
 constexpr int UC_MAXZ = 64;                // coarse planes per block at most
 
 __global__ void __launch_bounds__(UC_BLOCK)
