@@ -82,9 +82,10 @@ constexpr int MT = 8;  // tile edge of the triangular solves: one wave per tile
 // Forward substitution on tile (I, J, S - I - J): q_c = (r_c + sum over the
 // lower liquid neighbours m of precon_m q_m) precon_c, zero off liquid.
 // Block = one wave, lane (i', j') = (lane % 8, lane / 8); grid (tiles_x,
-// tiles_y), the blocks off the hyperplane return at once.  Each lane's column inputs (r, precon, and what the neighbours
-// across the tile's x- and y-faces contribute) sit in LDS, one 16-byte word
-// per cell, so that a level reads its cell with one LDS load; the x- and
+// tiles_y), the blocks off the hyperplane return at once (a grid of just the
+// hyperplane's tiles, found by a loop over rows, measured slower).  Each
+// lane's column inputs (r, precon, and what the neighbours across the tile's
+// x- and y-faces contribute) sit in LDS, one 16-byte word per cell, so that a level reads its cell with one LDS load; the x- and
 // y-neighbours inside the tile come from the lanes beside it by shuffles.
 __global__ void __launch_bounds__(64)
     k_mic0_fwd_tile(int n, int S, const uint8_t* __restrict__ cdiag,
@@ -101,20 +102,39 @@ __global__ void __launch_bounds__(64)
   const bool col_ok = x < n && y < n;
   const int64_t sy = n, sz = (int64_t)n * n;
   // precon_m q_m of the neighbours across the tile's faces (zero outside
-  // the box and off liquid, where precon and q are zero)
+  // the box and off liquid, where precon and q are zero).  Every load is
+  // issued from a valid (clamped) address and masked afterwards, so that the
+  // wave waits for one load latency, not one per conditional load.
+  const bool fx = col_ok && li == 0 && x > 0, fy = col_ok && lj == 0 && y > 0;
+  const bool fz = col_ok && z0 > 0;
+  float rv[MT], pv[MT], pxm[MT], qxm[MT], pym[MT], qym[MT];
+  uint8_t cv[MT];
 #pragma unroll
   for (int k = 0; k < MT; ++k) {
-    const int zz = z0 + k;
-    const bool ok = col_ok && zz < n;
-    const int64_t c = x + sy * y + sz * zz;
+    const bool ok = col_ok && z0 + k < n;
+    const int64_t c = x + sy * y + sz * (z0 + k);
+    const int64_t a = ok ? c : 0, ax = ok && fx ? c - 1 : 0, ay = ok && fy ? c - sy : 0;
+    rv[k] = r[a];
+    pv[k] = precon[a];
+    cv[k] = cdiag[a];
+    pxm[k] = precon[ax];
+    qxm[k] = q[ax];
+    pym[k] = precon[ay];
+    qym[k] = q[ay];
+  }
+  const int64_t az = fz ? x + sy * y + sz * (z0 - 1) : 0;
+  const float pzm = precon[az], qzm = q[az];
+#pragma unroll
+  for (int k = 0; k < MT; ++k) {
+    const bool ok = col_ok && z0 + k < n;
     float4 v;
-    v.x = ok && cdiag[c] ? r[c] : 0.f;
-    v.y = ok ? precon[c] : 0.f;
-    v.z = ok && li == 0 && x > 0 ? precon[c - 1] * q[c - 1] : 0.f;
-    v.w = ok && lj == 0 && y > 0 ? precon[c - sy] * q[c - sy] : 0.f;
+    v.x = ok && cv[k] ? rv[k] : 0.f;
+    v.y = ok ? pv[k] : 0.f;
+    v.z = ok && fx ? pxm[k] * qxm[k] : 0.f;
+    v.w = ok && fy ? pym[k] * qym[k] : 0.f;
     in_l[k][lane] = v;
   }
-  const float wz = col_ok && z0 > 0 ? precon[x + sy * y + sz * (z0 - 1)] * q[x + sy * y + sz * (z0 - 1)] : 0.f;
+  const float wz = fz ? pzm * qzm : 0.f;
   wave_sync();
   float w_last = 0.f;  // precon q of this lane's previous cell
 #pragma unroll
@@ -158,20 +178,34 @@ __global__ void __launch_bounds__(64)
   const int x = I * MT + li, y = J * MT + lj, z0 = K * MT;
   const bool col_ok = x < n && y < n;
   const int64_t sy = n, sz = (int64_t)n * n;
+  // all loads from valid (clamped) addresses first, masked afterwards (as in
+  // the forward sweep)
+  const bool fx = col_ok && li == MT - 1 && x + 1 < n, fy = col_ok && lj == MT - 1 && y + 1 < n;
+  const int ztop = z0 + MT;
+  const bool fz = col_ok && ztop < n;
+  float qv[MT], pv[MT], zxm[MT], zym[MT];
 #pragma unroll
   for (int k = 0; k < MT; ++k) {
-    const int zz = z0 + k;
-    const bool ok = col_ok && zz < n;
-    const int64_t c = x + sy * y + sz * zz;
+    const bool ok = col_ok && z0 + k < n;
+    const int64_t c = x + sy * y + sz * (z0 + k);
+    const int64_t a = ok ? c : 0, ax = ok && fx ? c + 1 : 0, ay = ok && fy ? c + sy : 0;
+    qv[k] = q[a];
+    pv[k] = precon[a];
+    zxm[k] = zout[ax];
+    zym[k] = zout[ay];
+  }
+  const float zzm = zout[fz ? x + sy * y + sz * ztop : 0];
+#pragma unroll
+  for (int k = 0; k < MT; ++k) {
+    const bool ok = col_ok && z0 + k < n;
     float4 v;
-    v.x = ok ? q[c] : 0.f;
-    v.y = ok ? precon[c] : 0.f;
-    v.z = ok && li == MT - 1 && x + 1 < n ? zout[c + 1] : 0.f;
-    v.w = ok && lj == MT - 1 && y + 1 < n ? zout[c + sy] : 0.f;
+    v.x = ok ? qv[k] : 0.f;
+    v.y = ok ? pv[k] : 0.f;
+    v.z = ok && fx ? zxm[k] : 0.f;
+    v.w = ok && fy ? zym[k] : 0.f;
     in_l[k][lane] = v;
   }
-  const int ztop = z0 + MT;
-  const float uz = col_ok && ztop < n ? zout[x + sy * y + sz * ztop] : 0.f;
+  const float uz = fz ? zzm : 0.f;
   wave_sync();
   float z_last = 0.f;  // z of this lane's previous (upper) cell
 #pragma unroll
