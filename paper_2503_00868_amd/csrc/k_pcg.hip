@@ -1187,14 +1187,20 @@ __device__ inline float mrow_diag_inv(uint8_t code, float alpha) {
 template <typename T, typename V>
 __device__ inline T mrow(const V* __restrict__ f, int64_t idx, uint8_t code, int64_t sy, int64_t sz,
                          T alpha) {
-  const T v = (T)f[idx];
+  // all seven loads issued at once (an absent neighbour reads the face
+  // itself), then the same additions in the same order as a branchy form
+  const V f0 = f[idx];
+  const V fm1 = f[code & 1 ? idx - 1 : idx], fp1 = f[code & 2 ? idx + 1 : idx];
+  const V fmy = f[code & 4 ? idx - sy : idx], fpy = f[code & 8 ? idx + sy : idx];
+  const V fmz = f[code & 16 ? idx - sz : idx], fpz = f[code & 32 ? idx + sz : idx];
+  const T v = (T)f0;
   T acc = 0;
-  if (code & 1) acc += (T)f[idx - 1] - v;
-  if (code & 2) acc += (T)f[idx + 1] - v;
-  if (code & 4) acc += (T)f[idx - sy] - v;
-  if (code & 8) acc += (T)f[idx + sy] - v;
-  if (code & 16) acc += (T)f[idx - sz] - v;
-  if (code & 32) acc += (T)f[idx + sz] - v;
+  acc = code & 1 ? acc + ((T)fm1 - v) : acc;
+  acc = code & 2 ? acc + ((T)fp1 - v) : acc;
+  acc = code & 4 ? acc + ((T)fmy - v) : acc;
+  acc = code & 8 ? acc + ((T)fpy - v) : acc;
+  acc = code & 16 ? acc + ((T)fmz - v) : acc;
+  acc = code & 32 ? acc + ((T)fpz - v) : acc;
   return v - alpha * acc;
 }
 
