@@ -97,11 +97,25 @@ static ZmGrid zm_grid(int n) {
   return g;
 }
 
+// Layers with two 16-channel output groups and two input chunks (32 -> 32)
+// split their output groups over two sets of four waves: 512 threads per
+// block, wave w takes rows 4 (w % 4) .. + 3 for output group w / 4 and holds
+// only that group's weight fragments, so that two waves fit per SIMD (both
+// groups in one wave need 60 fragments and leave one wave per SIMD).  (The
+// 16 -> 32 layer, with 30 fragments, measured slower split.)
+template <int CIN, int COUT, int EPI>
+__host__ __device__ constexpr bool zm_split() {
+  return CIN == 32 && COUT == 32 &&
+         (EPI == NET_EPI_RELU || EPI == NET_EPI_RAW || EPI == NET_EPI_MASKGRAD);
+}
+template <int CIN, int COUT, int EPI>
+__host__ __device__ constexpr int zm_block() { return zm_split<CIN, COUT, EPI>() ? 2 * kBlock : kBlock; }
+
 // CIN: channels held per ring voxel (multiple of 16; the source may have
 // fewer, the rest is zero).  WS: channel stride of the packed weights.
 // COUT: output channels (16 or 48).
 template <int CIN, int WS, int COUT, int EPI>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
     k_conv_zm(int n, int zc, NetSrc src, const __bf16* __restrict__ w, NetOut out,
               const int* __restrict__ flags) {
   if (flags && flags[F_DONE]) return;
@@ -111,12 +125,15 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
   constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
-  constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
+  constexpr bool SPLIT = zm_split<CIN, COUT, EPI>();
+  constexpr int BLOCK = zm_block<CIN, COUT, EPI>();
+  constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
+  constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
   constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
-  __shared__ __attribute__((aligned(16))) int votes[4][4];  // per ring slot
+  __shared__ __attribute__((aligned(16))) int votes[4][8];  // per ring slot
   // Epilogue: layers with 32 or more channels on either side take the
   // weights as the MFMA's A operand (D = [output channel][voxel]) and store
   // straight from registers; 16 -> 16 layers take the input as A (D =
@@ -136,7 +153,22 @@ __global__ void __launch_bounds__(kBlock)
   const int z1 = min(z0 + zc, n);
   if (z0 >= n) return;
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wv = wave & 3, g = lane >> 4,
+            col = lane & 15;
+  const int tg = SPLIT ? wave >> 2 : 0;  // this wave's first output group
+  // block-wide OR with one barrier (barrier_or, or its 8-wave form)
+  auto bvote = [&](int v, int* slot) -> int {
+    if constexpr (!SPLIT) {
+      return barrier_or(v, slot);
+    } else {
+      const bool any = __ballot(v != 0) != 0ull;
+      if (lane == 0) slot[wave] = any;
+      __syncthreads();
+      const int4 a = *reinterpret_cast<const int4*>(slot);
+      const int4 b = *reinterpret_cast<const int4*>(slot + 4);
+      return a.x | a.y | a.z | a.w | b.x | b.y | b.z | b.w;
+    }
+  };
   const int nc = n >> 1;
 
   // tile-plane activity (block-uniform): an output plane marked 0 in
@@ -149,7 +181,7 @@ __global__ void __launch_bounds__(kBlock)
   if (out.act) {
     const uint8_t* act_in = src.act ? src.act : out.act;
     int any = 0;
-    for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += BLOCK) {
       const int zi = z0 - 1 + t;
       const bool in = (unsigned)zi < (unsigned)n;
       live_s[t] = in ? out.act[(int64_t)zi * tiles + tile] : 0;
@@ -161,8 +193,8 @@ __global__ void __launch_bounds__(kBlock)
   auto live = [&](int zi) -> bool { return !out.act || live_s[zi - z0 + 1] != 0; };
   auto live_in = [&](int zi) -> bool { return !out.act || live_in_s[zi - z0 + 1] != 0; };
 
-  // weight fragments: bw[q][s][t] for chunk q, step s, output group t
-  bf16x8z bw[NCH][ZSTEPS][NT];
+  // weight fragments: bw[q][s][t] for chunk q, step s, output group tg + t
+  bf16x8z bw[NCH][ZSTEPS][NTW];
 #pragma unroll
   for (int q = 0; q < NCH; ++q)
 #pragma unroll
@@ -170,10 +202,10 @@ __global__ void __launch_bounds__(kBlock)
       const int tap = g < 2 ? zm_tap0(s) : zm_tap1(s);
       const int ci = q * 16 + (g & 1) * 8;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
+      for (int t = 0; t < NTW; ++t) {
         bf16x8z v;
         if (ci < WS) {
-          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)(t * 16 + col) * ZTAPS + tap) * WS + ci);
+          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)((tg + t) * 16 + col) * ZTAPS + tap) * WS + ci);
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
@@ -182,7 +214,7 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
 
-  // Load items of this thread: item it = threadIdx.x + k * kBlock holds 8
+  // Load items of this thread: item it = threadIdx.x + k * BLOCK holds 8
   // channels (part p) of halo voxel hv.  Its byte offset within one plane of
   // its source is fixed for the block; only the (uniform) plane offset moves
   // with z.  src: 0 none (outside the volume or channel padding), 1 a, 2 b.
@@ -190,7 +222,7 @@ __global__ void __launch_bounds__(kBlock)
   uint8_t isrc[PF];
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
-    const int it = threadIdx.x + k * kBlock;
+    const int it = threadIdx.x + k * BLOCK;
     const int hv = it / P8, p = it - hv * P8;
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
@@ -241,7 +273,7 @@ __global__ void __launch_bounds__(kBlock)
     uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-      const int it = threadIdx.x + k * kBlock;
+      const int it = threadIdx.x + k * BLOCK;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
         const uint4 v = isrc[k] ? pf[k] : zero;
@@ -276,15 +308,15 @@ __global__ void __launch_bounds__(kBlock)
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
   load_plane(z0 - 1);
-  int nz_m = barrier_or(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
+  int nz_m = bvote(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
   load_plane(z0);
-  int nz_0 = barrier_or(store_plane(z0), votes[z0 & 3]);
+  int nz_0 = bvote(store_plane(z0), votes[z0 & 3]);
   load_plane(z0 + 1);
 
   // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
   // is loaded while the MFMAs of plane z run
   auto plane_step = [&](int z) {
-    const int nz_p = barrier_or(store_plane(z + 1), votes[(z + 1) & 3]);
+    const int nz_p = bvote(store_plane(z + 1), votes[(z + 1) & 3]);
     if (z + 2 <= z1) load_plane(z + 2);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
@@ -313,11 +345,11 @@ __global__ void __launch_bounds__(kBlock)
     if (EPI == NET_EPI_OUT && !DIRECT && own)
       own_mask = out.mask[(int64_t)ox + (int64_t)n * oy + nn * z];
 
-    f32x4z acc[4][NT];
+    f32x4z acc[4][NTW];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NTW; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
 
     const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
     const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
@@ -339,7 +371,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NTW; ++t)
               acc[a][t] = DIRECT ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[q][st][t], f[a + dy],
                                                                            acc[a][t], 0, 0, 0)
                                  : __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][st][t],
@@ -348,7 +380,7 @@ __global__ void __launch_bounds__(kBlock)
         // keep that order in the schedule: the next group's 6 LDS reads, then
         // this group's MFMAs
         if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 12 * NTW, 0);
       }
     }
 
@@ -367,8 +399,8 @@ __global__ void __launch_bounds__(kBlock)
         const bool ok = row_ok(a);
         const int64_t v = vox(a, z);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int64_t e = v * COUT + t * 16 + 4 * g;  // element of channel 4g
+        for (int t = 0; t < NTW; ++t) {
+          const int64_t e = v * COUT + (tg + t) * 16 + 4 * g;  // element of channel 4g
           float f[4] = {acc[a][t][0], acc[a][t][1], acc[a][t][2], acc[a][t][3]};
           if (EPI == NET_EPI_RELU) {
 #pragma unroll
@@ -463,13 +495,22 @@ __global__ void __launch_bounds__(kBlock)
 // The 16 -> 16 pool layer runs at three waves per SIMD (its LDS allows three
 // blocks per CU; the register limit costs a few spilled values): 296 -> 267 us
 // for c2 at 256^3.  The add layer does not fit that limit.
+// The 32 -> 32 layers with these epilogues split their output groups over
+// two sets of four waves as k_conv_zm does (the two waves of a row group meet
+// at a block barrier before the epilogue reads both halves of the stage).
+template <int CIN, int COUT, int EPI>
+__host__ __device__ constexpr bool zm_pa_split() {
+  return CIN == 32 && COUT == 32 && (EPI == NET_EPI_RELU_POOL || EPI == NET_EPI_RELU_ADD);
+}
+template <int CIN, int COUT, int EPI>
+__host__ __device__ constexpr int zm_pa_block() { return zm_pa_split<CIN, COUT, EPI>() ? 2 * kBlock : kBlock; }
 template <int CIN, int COUT, int EPI>
 constexpr int zm_pa_min_waves() {
-  return CIN == 16 && COUT == 16 && EPI == NET_EPI_RELU_POOL ? 3 : 1;
+  return CIN == 16 && COUT == 16 && EPI == NET_EPI_RELU_POOL ? 3 : (zm_pa_split<CIN, COUT, EPI>() ? 2 : 1);
 }
 
 template <int CIN, int WS, int COUT, int EPI>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
     __attribute__((amdgpu_waves_per_eu(zm_pa_min_waves<CIN, COUT, EPI>())))
     k_conv_zm_pa(int n, int zc, NetSrc src, const __bf16* __restrict__ w, NetOut out,
               const int* __restrict__ flags) {
@@ -479,12 +520,15 @@ __global__ void __launch_bounds__(kBlock)
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
   constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
-  constexpr int PF = (ITEMS + kBlock - 1) / kBlock;
+  constexpr bool SPLIT = zm_pa_split<CIN, COUT, EPI>();
+  constexpr int BLOCK = zm_pa_block<CIN, COUT, EPI>();
+  constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
+  constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
   constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
-  __shared__ __attribute__((aligned(16))) int votes[4][4];  // per ring slot
+  __shared__ __attribute__((aligned(16))) int votes[4][8];  // per ring slot
   constexpr int STAGE_BYTES = 4 * 4 * ZT * COUT * (EPI == NET_EPI_RELU_ADD ? 4 : 2);
   __shared__ __attribute__((aligned(16))) char stage_raw[STAGE_BYTES];
   __bf16* stage = reinterpret_cast<__bf16*>(stage_raw);
@@ -498,7 +542,21 @@ __global__ void __launch_bounds__(kBlock)
   const int z1 = min(z0 + zc, n);
   if (z0 >= n) return;
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wv = wave & 3, g = lane >> 4,
+            col = lane & 15;
+  const int tg = SPLIT ? wave >> 2 : 0;  // this wave's first output group
+  auto bvote = [&](int v, int* slot) -> int {
+    if constexpr (!SPLIT) {
+      return barrier_or(v, slot);
+    } else {
+      const bool any = __ballot(v != 0) != 0ull;
+      if (lane == 0) slot[wave] = any;
+      __syncthreads();
+      const int4 a = *reinterpret_cast<const int4*>(slot);
+      const int4 b = *reinterpret_cast<const int4*>(slot + 4);
+      return a.x | a.y | a.z | a.w | b.x | b.y | b.z | b.w;
+    }
+  };
   const int nc = n >> 1;
 
   // tile-plane activity (block-uniform): an output plane marked 0 in
@@ -511,7 +569,7 @@ __global__ void __launch_bounds__(kBlock)
   if (out.act) {
     const uint8_t* act_in = src.act ? src.act : out.act;
     int any = 0;
-    for (int t = threadIdx.x; t < z1 - z0 + 3; t += kBlock) {
+    for (int t = threadIdx.x; t < z1 - z0 + 3; t += BLOCK) {
       const int zi = z0 - 1 + t;
       const bool in = (unsigned)zi < (unsigned)n;
       live_s[t] = in ? out.act[(int64_t)zi * tiles + tile] : 0;
@@ -524,7 +582,7 @@ __global__ void __launch_bounds__(kBlock)
   auto live_in = [&](int zi) -> bool { return !out.act || live_in_s[zi - z0 + 1] != 0; };
 
   // weight fragments: bw[q][s][t] for chunk q, step s, output group t
-  bf16x8z bw[NCH][ZSTEPS][NT];
+  bf16x8z bw[NCH][ZSTEPS][NTW];
 #pragma unroll
   for (int q = 0; q < NCH; ++q)
 #pragma unroll
@@ -532,10 +590,10 @@ __global__ void __launch_bounds__(kBlock)
       const int tap = g < 2 ? zm_tap0(s) : zm_tap1(s);
       const int ci = q * 16 + (g & 1) * 8;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
+      for (int t = 0; t < NTW; ++t) {
         bf16x8z v;
         if (ci < WS) {
-          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)(t * 16 + col) * ZTAPS + tap) * WS + ci);
+          v = *reinterpret_cast<const bf16x8z*>(w + ((int64_t)((tg + t) * 16 + col) * ZTAPS + tap) * WS + ci);
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
@@ -550,7 +608,7 @@ __global__ void __launch_bounds__(kBlock)
   uint8_t isrc[PF];
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
-    const int it = threadIdx.x + k * kBlock;
+    const int it = threadIdx.x + k * BLOCK;
     const int hv = it / P8, p = it - hv * P8;
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
@@ -595,7 +653,7 @@ __global__ void __launch_bounds__(kBlock)
     uint32_t any = 0u;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-      const int it = threadIdx.x + k * kBlock;
+      const int it = threadIdx.x + k * BLOCK;
       if (it < ITEMS) {
         const int hv = it / P8, p = it - hv * P8;
         const uint4 v = isrc[k] ? pf[k] : zero;
@@ -616,9 +674,9 @@ __global__ void __launch_bounds__(kBlock)
   // MFMAs of a plane are skipped when planes z-1, z, z+1 of the tile (with
   // halo) are all zero; the flags come with the barrier after each store.
   load_plane(z0 - 1);
-  int nz_m = barrier_or(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
+  int nz_m = bvote(store_plane(z0 - 1), votes[(z0 + 3) & 3]);
   load_plane(z0);
-  int nz_0 = barrier_or(store_plane(z0), votes[z0 & 3]);
+  int nz_0 = bvote(store_plane(z0), votes[z0 & 3]);
   load_plane(z0 + 1);
   float pacc[8];  // RELU_POOL: sums of the even plane of a z pair
 #pragma unroll
@@ -627,7 +685,7 @@ __global__ void __launch_bounds__(kBlock)
   // one output plane: the prefetched plane z+1 goes to the ring, plane z+2
   // is loaded while the MFMAs of plane z run
   auto plane_step = [&](int z) {
-    const int nz_p = barrier_or(store_plane(z + 1), votes[(z + 1) & 3]);
+    const int nz_p = bvote(store_plane(z + 1), votes[(z + 1) & 3]);
     if (z + 2 <= z1) load_plane(z + 2);
     const bool work = (nz_m | nz_0 | nz_p) != 0;
     nz_m = nz_0;
@@ -649,11 +707,15 @@ __global__ void __launch_bounds__(kBlock)
     // it % PV8), from a clamped address where the item is outside
     constexpr int PV8 = COUT / 8;
     constexpr int ADD_K = EPI == NET_EPI_RELU_ADD ? (4 * ZT * PV8 + 63) / 64 : 1;
-    uint4 hadd[ADD_K];
+    // items per wave: a split pair shares its row group's items
+    constexpr bool ADD_SPLIT = SPLIT && EPI == NET_EPI_RELU_ADD;
+    constexpr int ADD_KW = ADD_SPLIT ? ADD_K / 2 : ADD_K;
+    static_assert(!ADD_SPLIT || ADD_K % 2 == 0, "split add items");
+    uint4 hadd[ADD_KW];
     if (EPI == NET_EPI_RELU_ADD) {
 #pragma unroll
-      for (int k = 0; k < ADD_K; ++k) {
-        const int it = lane + 64 * k;
+      for (int k = 0; k < ADD_KW; ++k) {
+        const int it = lane + 64 * ((ADD_SPLIT ? tg : 0) * ADD_KW + k);
         const int lv = it / PV8, part = it - lv * PV8;
         const int x = x0 + lv % ZT, y = y0 + 4 * wv + lv / ZT;
         const bool ok = it < 4 * ZT * PV8 && x < n && y < n;
@@ -662,11 +724,11 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
 
-    f32x4z acc[4][NT];
+    f32x4z acc[4][NTW];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NTW; ++t) acc[a][t] = f32x4z{0.f, 0.f, 0.f, 0.f};
 
     const __bf16* sm = ring + ((z + 3) & 3) * SLOT;  // plane z-1 (dz = 0)
     const __bf16* s0 = ring + (z & 3) * SLOT;        // plane z   (dz = 1)
@@ -689,13 +751,13 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NTW; ++t)
               acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[a + dy], bw[q][st][t], acc[a][t],
                                                                   0, 0, 0);
         }
         if (!(NCH == 1 && EPI == NET_EPI_RELU_POOL)) {
           if (gi + 1 < 5 * NCH) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-          __builtin_amdgcn_sched_group_barrier(0x008, 12 * NT, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 12 * NTW, 0);
         }
       }
     }
@@ -724,13 +786,17 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NTW; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sf[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = acc[a][t][i];
-      wave_sync();  // per-wave staging
+          for (int i = 0; i < 4; ++i)
+            sf[((a * ZT) + 4 * g + i) * COUT + (tg + t) * 16 + col] = acc[a][t][i];
+      if constexpr (SPLIT)
+        __syncthreads();  // both output groups of the row group staged
+      else
+        wave_sync();  // per-wave staging
 #pragma unroll
-      for (int k = 0; k < ADD_K; ++k) {
-        const int it = lane + 64 * k;
+      for (int k = 0; k < ADD_KW; ++k) {
+        const int it = lane + 64 * ((ADD_SPLIT ? tg : 0) * ADD_KW + k);
         if (it >= 4 * ZT * PV8) break;
         const int lv = it / PV8, part = it - lv * PV8;
         const int a = lv / ZT, xl = lv % ZT;
@@ -753,20 +819,25 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int t = 0; t < NTW; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float v = acc[a][t][i];
           if (EPI == NET_EPI_RELU || EPI == NET_EPI_RELU_POOL) v = v > 0.f ? v : 0.f;
-          st[((a * ZT) + 4 * g + i) * COUT + t * 16 + col] = (__bf16)v;
+          st[((a * ZT) + 4 * g + i) * COUT + (tg + t) * 16 + col] = (__bf16)v;
         }
-    wave_sync();  // per-wave staging
+    if constexpr (SPLIT)
+      __syncthreads();  // both output groups of the row group staged
+    else
+      wave_sync();  // per-wave staging
     if (EPI == NET_EPI_RELU_POOL) {
       // 2x2 in xy from the staged rows of this plane; the z pair (z even,
       // z + 1) accumulates in pacc, the odd plane stores the average
       constexpr int PP = COUT / 8;
-      if (lane < 2 * 8 * PP) {
-        const int part = lane % PP, cxy = lane / PP, cx = cxy % 8, cy = cxy / 8;
+      // a split pair shares the parts: wave tg takes parts tg * PPW .. + PPW - 1
+      constexpr int PPW = SPLIT ? PP / 2 : PP;
+      if (lane < 2 * 8 * PPW) {
+        const int part = tg * PPW + lane % PPW, cxy = lane / PPW, cx = cxy % 8, cy = cxy / 8;
         float s8[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) s8[e] = 0.f;
@@ -797,9 +868,12 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     constexpr int PV = COUT / 8;
+    constexpr int SK = (4 * ZT * PV + 63) / 64;  // store items per lane of a row group
+    constexpr int SKW = SPLIT ? SK / 2 : SK;     // a split pair shares them
+    static_assert(!SPLIT || SK % 2 == 0, "split store items");
 #pragma unroll
-    for (int k = 0; k < (4 * ZT * PV + 63) / 64; ++k) {
-      const int it = lane + 64 * k;
+    for (int k = 0; k < SKW; ++k) {
+      const int it = lane + 64 * (tg * SKW + k);
       if (it >= 4 * ZT * PV) break;
       const int lv = it / PV, part = it - lv * PV;
       const int a = lv / ZT, xl = lv % ZT;
@@ -1158,11 +1232,11 @@ static void zm_launch(sim_ctx* c, int n, NetSrc src, const __bf16* w, NetOut out
                       const int* flags) {
   const ZmGrid g = zm_grid(n);
   if constexpr (EPI == NET_EPI_RELU_ADD || EPI == NET_EPI_RELU_POOL)
-    hipLaunchKernelGGL((k_conv_zm_pa<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream,
-                       n, g.zc, src, w, out, flags);
+    hipLaunchKernelGGL((k_conv_zm_pa<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(zm_pa_block<CIN, COUT, EPI>()), 0,
+                       c->stream, n, g.zc, src, w, out, flags);
   else
-    hipLaunchKernelGGL((k_conv_zm<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(kBlock), 0, c->stream, n,
-                       g.zc, src, w, out, flags);
+    hipLaunchKernelGGL((k_conv_zm<CIN, WS, COUT, EPI>), dim3(g.blocks), dim3(zm_block<CIN, COUT, EPI>()), 0,
+                       c->stream, n, g.zc, src, w, out, flags);
 }
 
 template <int CIN, int WS, int COUT>
