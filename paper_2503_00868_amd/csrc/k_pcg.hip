@@ -740,11 +740,13 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       rv[e] -= alpha_f * qv[e];
-      if (!FLEX) v[0] += (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+      // Jacobi: r.M^-1 r; flexible CG: |r|^2, the learned preconditioner's
+      // input scale (it would otherwise read r once more for it)
+      v[0] += FLEX ? (double)rv[e] * (double)rv[e] : (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
     }
     stf<V>(r + idx, rv);
   }
-  if (!FLEX) store_partials<1>(v, partials, lb);
+  store_partials<1>(v, partials, lb);
   if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_Q0 + phase] = alpha;
 }
 
@@ -1051,6 +1053,8 @@ void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
     FS_CELL_LAUNCH(k_update4, false, true);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
 #undef ARGS
+  // |r|^2 of the updated residual, for the learned preconditioner's input
+  launch_finalize(c, c->grid_cells, 1, FIN_SLOT, 0.0, 0, S_NET_SUMSQ, 1.0, 0);
 }
 
 void launch_pcg_rz_first(sim_ctx* c, int first) {

@@ -210,12 +210,13 @@ void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, 
 // gradient of c1 reads it) and compute every tile; otherwise c1 reads r and
 // the mask directly, and the tiles the activity maps mark as zero are
 // skipped.
-int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_input) {
+int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_input,
+            bool have_sumsq = false) {
   UNetState* s = c->net;
   const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
   const bool skip = !keep_input && s->skip_tiles;
   auto A = [&](int id) -> const uint8_t* { return skip ? s->act[id] : nullptr; };
-  launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
+  if (!have_sumsq) launch_dot_cells_slot(c, r, r, S_NET_SUMSQ, flags);
   int rc = SIM_OK;
   if (keep_input) {
     net_input(c, r, c->scal + S_NET_SUMSQ, c->scal + S_NET_RMS, s->X0, flags);
@@ -392,9 +393,9 @@ void net_destroy(sim_ctx* c) {
 
 bool net_ready(const sim_ctx* c) { return c->net && c->net->ready; }
 
-int net_apply(sim_ctx* c, const float* r, float* z, const int* flags) {
+int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq) {
   prof_mark(c, SIM_KERN_NET, true);
-  int rc = forward(c, r, z, flags, false);
+  int rc = forward(c, r, z, flags, false, have_sumsq);
   prof_mark(c, SIM_KERN_NET, false);
   return rc;
 }

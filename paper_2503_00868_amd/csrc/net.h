@@ -51,8 +51,10 @@ int net_init(sim_ctx* c, const uint8_t* h_cell);
 void net_destroy(sim_ctx* c);
 bool net_ready(const sim_ctx* c);
 // z = mask * rms(r) * U(r / rms(r), mask); returns at once when flags (nullable)
-// has the done flag raised.
-int net_apply(sim_ctx* c, const float* r, float* z, const int* flags);
+// has the done flag raised.  have_sumsq: the caller has already placed |r|^2
+// in the context's S_NET_SUMSQ slot (the flexible-CG update reduces it), so
+// the pass does not read r once more for it.
+int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq = false);
 
 // kernel launchers
 int conv_tiles(int n);

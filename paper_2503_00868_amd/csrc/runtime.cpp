@@ -470,7 +470,9 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
       const float* dirs[4] = {dbuf[(ph + 2) & 3], dbuf[(ph + 3) & 3], dbuf[ph], dbuf[(ph + 1) & 3]};
       launch_fcg_update4(c, dirs, ph);
       if (t == todo - 1) launch_fcg_check(c, tol);
-      int r2 = net_apply(c, c->r, c->z, c->flags);
+      // the update reduced |r|^2 for the network, unless the check has just
+      // replaced r by the true residual
+      int r2 = net_apply(c, c->r, c->z, c->flags, t != todo - 1);
       if (r2) inner_rc = r2;
       launch_fcg_beta(c);
     }
