@@ -58,7 +58,7 @@ enum FinMode : int {
   FIN_DQ,            // [dq]          -> DQ; iteration counted; breakdown if dq <= 0
   FIN_RZ_UPD,        // [rz]          -> RZ_PREV = RZ, RZ, BETA = rz / RZ_PREV
   FIN_RZ_FIRST,      // [rz]          -> RZ, RZ_PREV, BETA = 0
-  FIN_CHECK,         // [rr, rz]      -> RR; (jacobi) RZ, BETA; done at tol
+  FIN_CHECK,         // [rr, rz]      -> RR; (jacobi) RZ, BETA, else NET_SUMSQ = |r|^2; done at tol
   FIN_FCG_DQDR,      // [dq, dr]      -> DQ, DR; iteration counted; breakdown
   FIN_FCG_BETA,      // [zq]          -> BETA = -zq / DQ
   FIN_DCG_INIT,      // [bb, rz, rr]  -> BB, RZ, RZ_PREV, RR, BETA = 0; done at tol
@@ -176,6 +176,7 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
 // of the current group (only dirs[3] is read before phase 3).
 void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 // the same four-step iterate update for the flexible CG (alpha = d.r / d.q)
+// also reduces |r|^2 into S_NET_SUMSQ (the learned preconditioner's input scale)
 void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);

@@ -147,6 +147,8 @@ __global__ void __launch_bounds__(kBlock)
       if (jacobi) {
         scal[S_RZ] = v[1];
         scal[S_BETA] = scal[S_RZ_PREV] > 0.0 ? v[1] / scal[S_RZ_PREV] : 0.0;
+      } else {
+        scal[S_NET_SUMSQ] = v[1];  // |r|^2 of the replaced residual (the network's input scale)
       }
       if (v[0] <= tol2 * scal[S_BB]) {
         flags[F_DONE] = 1;
@@ -615,7 +617,8 @@ __global__ void __launch_bounds__(kBlock)
         const double rc = dg ? (double)bc[e] - ((double)dg * xc[e] - s) : 0.0;
         rf[e] = (float)rc;
         v[0] += rc * rc;
-        if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg];
+        v[1] += PREC == PK_JACOBI ? (double)rf[e] * (double)rf[e] * c_inv_count[dg]
+                                  : (double)rf[e] * (double)rf[e];
       }
       stf<4>(r + idx, rf);
     }
@@ -867,7 +870,8 @@ __global__ void __launch_bounds__(kBlock)
       const double rc = dg[e] ? (double)bv[e] - ((double)dg[e] * xc[e] - s[e]) : 0.0;
       rf[e] = (float)rc;
       v[0] += rc * rc;
-      if (PREC == PK_JACOBI) v[1] += (double)rf[e] * (double)rf[e] * c_inv_count[dg[e]];
+      v[1] += PREC == PK_JACOBI ? (double)rf[e] * (double)rf[e] * c_inv_count[dg[e]]
+                                : (double)rf[e] * (double)rf[e];
     }
     stf<V>(r + idx, rf);
   }

@@ -469,10 +469,11 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
       launch_fcg_dir_spmv(c, dbuf[ph], dbuf[(ph + 1) & 3]);
       const float* dirs[4] = {dbuf[(ph + 2) & 3], dbuf[(ph + 3) & 3], dbuf[ph], dbuf[(ph + 1) & 3]};
       launch_fcg_update4(c, dirs, ph);
+      // the FP64 check runs at block ends only, where x is up to date
       if (t == todo - 1) launch_fcg_check(c, tol);
-      // the update reduced |r|^2 for the network, unless the check has just
-      // replaced r by the true residual
-      int r2 = net_apply(c, c->r, c->z, c->flags, t != todo - 1);
+      // |r|^2 for the network: reduced by the update, or by the check when it
+      // has just replaced r by the true residual
+      int r2 = net_apply(c, c->r, c->z, c->flags, true);
       if (r2) inner_rc = r2;
       launch_fcg_beta(c);
     }
