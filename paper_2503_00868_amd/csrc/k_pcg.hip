@@ -356,11 +356,19 @@ __global__ void __launch_bounds__(kBlock)
 // registers, the current plane (plus a one-cell halo) goes through LDS for
 // the x and y neighbours.  Halo cells outside the box are written as zero,
 // which is also their contribution (every vector is zero off liquid).
-// Target launch size of the z-marching stencils (a compile-time setting):
+// Target launch sizes of the z-marching stencils (compile-time settings):
 // fewer blocks mean longer z-runs and less halo re-reading, more blocks more
-// latency hiding.
+// latency hiding (measured at 256^3: the Jacobi direction + SpMV and the FP64
+// check are fastest at 1024 blocks, the flexible direction + SpMV, which reads
+// four arrays per plane, at 768, the viscosity stencil at 2048).
 #ifndef FS_ZM_BLOCKS
 #define FS_ZM_BLOCKS 1024
+#endif
+#ifndef FS_ZM_BLOCKS_FLEX
+#define FS_ZM_BLOCKS_FLEX 768
+#endif
+#ifndef FS_DZ_BLOCKS
+#define FS_DZ_BLOCKS 2048
 #endif
 constexpr int ZM_GX = 16;  // 4-cell groups per tile along x (64 cells)
 constexpr int ZM_TY = 16;  // rows per tile (ZM_GX * ZM_TY = kBlock threads)
@@ -391,9 +399,10 @@ __device__ inline ZTile ztile(int n, int zc) {
 }
 
 // Raw inputs of the direction at one 4-cell group (z = r/diag for Jacobi,
-// else the explicit z array).  A group of the tile itself (CENTER) also
-// carries what its stencil row needs after the barrier: the diagonal codes
-// and, for the flexible variant's second dot, r.
+// else the explicit z array).  A group of the tile's own output planes (own)
+// also carries what its stencil row needs after the barrier: the diagonal
+// codes and, for the flexible variant's second dot, r; the planes just below
+// and above a z-run feed only the z neighbours and need the direction alone.
 template <int PREC>
 struct DirRaw {
   float a[4];  // r (Jacobi) or z
@@ -406,12 +415,20 @@ template <int PREC, bool CENTER, bool FLEX>
 __device__ inline void dir_raw_load(const float* __restrict__ r, const float* __restrict__ z,
                                     const uint8_t* __restrict__ cdiag,
                                     const float* __restrict__ d_in, int64_t idx, bool ok,
-                                    DirRaw<PREC>& o) {
+                                    bool own, DirRaw<PREC>& o) {
   if (ok) {
     ldf<4>((PREC == PK_JACOBI ? r : z) + idx, o.a);
     ldf<4>(d_in + idx, o.d);
-    o.g = PREC == PK_JACOBI || CENTER ? *reinterpret_cast<const uint32_t*>(cdiag + idx) : 0u;
-    if (CENTER && FLEX) ldf<4>(r + idx, o.rr);
+    o.g = PREC == PK_JACOBI || (CENTER && own) ? *reinterpret_cast<const uint32_t*>(cdiag + idx)
+                                                : 0u;
+    if (CENTER && FLEX) {
+      if (own) {
+        ldf<4>(r + idx, o.rr);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o.rr[e] = 0.f;
+      }
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) o.a[e] = 0.f, o.d[e] = 0.f, o.rr[e] = 0.f;
@@ -456,16 +473,18 @@ __global__ void __launch_bounds__(kBlock)
   const bool has_hy = (t.ty == 0 || t.ty == ZM_TY - 1) && t.x < n;
   const bool has_hx = t.gx == 0 || t.gx == ZM_GX - 1;
 
+  // planes z0 - 1 .. z1 are read, z0 .. z1 - 1 with their diagonal codes (and r)
   auto load_center = [&](int zz, DirRaw<PREC>& o) {
     dir_raw_load<PREC, true, FLEX>(r, z, cdiag, d_in, gidx(t.x, t.y, zz),
-                                   t.in_xy && zz >= 0 && zz < n, o);
+                                   t.in_xy && zz >= 0 && zz < n && zz <= t.z1,
+                                   zz >= t.z0 && zz < t.z1, o);
   };
   auto load_hy = [&](int zz, DirRaw<PREC>& o) {
     dir_raw_load<PREC, false, false>(r, z, cdiag, d_in, gidx(t.x, hy, zz),
-                                     has_hy && in_box(t.x, hy, zz), o);
+                                     has_hy && zz < t.z1 && in_box(t.x, hy, zz), false, o);
   };
   auto load_hx = [&](int zz, float& a, float& d, uint8_t& g) {
-    if (has_hx && in_box(hx, t.y, zz)) {
+    if (has_hx && zz < t.z1 && in_box(hx, t.y, zz)) {
       const int64_t m = gidx(hx, t.y, zz);
       a = (PREC == PK_JACOBI ? r : z)[m];
       d = d_in[m];
@@ -635,9 +654,9 @@ struct ZmShape {
   int blocks, zc;
 };
 
-static ZmShape zm_shape(int n) {
+static ZmShape zm_shape(int n, int target = FS_ZM_BLOCKS) {
   const int tiles = ((n + 4 * ZM_GX - 1) / (4 * ZM_GX)) * ((n + ZM_TY - 1) / ZM_TY);
-  int chunks = FS_ZM_BLOCKS / tiles;
+  int chunks = target / tiles;
   if (chunks < 1) chunks = 1;
   if (chunks > n / 4) chunks = n / 4 > 0 ? n / 4 : 1;
   int zc = (n + chunks - 1) / chunks;
@@ -979,7 +998,7 @@ void launch_pcg_init(sim_ctx* c, int prec) {
 template <bool FLEX>
 static int dir_spmv_any(sim_ctx* c, int prec, const float* d_in, float* d_out) {
   if (c->n % 4 == 0) {
-    const ZmShape zs = zm_shape(c->n);
+    const ZmShape zs = zm_shape(c->n, FLEX ? FS_ZM_BLOCKS_FLEX : FS_ZM_BLOCKS);
     if (prec == PK_JACOBI)
       hipLaunchKernelGGL((k_dir_spmv_zm<PK_JACOBI, FLEX>), dim3(zs.blocks), dim3(kBlock), 0,
                          c->stream, c->n, zs.zc, c->cdiag, c->r, c->z, d_in, d_out, c->q, c->scal,
@@ -1308,7 +1327,7 @@ __host__ __device__ inline DcgZmShape dcg_zm_shape(int n) {
   DcgZmShape s;
   s.tiles_x = (n + 1 + DZ_TX - 1) / DZ_TX;
   s.tiles = s.tiles_x * ((n + 1 + DZ_TY - 1) / DZ_TY);
-  int chunks = (1024 + s.tiles - 1) / s.tiles;
+  int chunks = (FS_DZ_BLOCKS + s.tiles - 1) / s.tiles;
   if (chunks > n + 1) chunks = n + 1;
   s.zc = (n + 1 + chunks - 1) / chunks;
   s.chunks = (n + 1 + s.zc - 1) / s.zc;
@@ -1353,11 +1372,12 @@ __global__ void __launch_bounds__(kBlock)
       float r[DZ_K], d[DZ_K];
       uint8_t c[DZ_K];
     };
+    // planes z0 - 1 .. z1 (the one above the run feeds only the z neighbours)
     auto load_own = [&](int zz, Raw& o) {
 #pragma unroll
       for (int k = 0; k < DZ_K; ++k) {
         const int y = y0 + tg + 4 * k;
-        if (in_grid(x, y, zz)) {
+        if (zz <= z1 && in_grid(x, y, zz)) {
           const int64_t m = x + sy * y + sz * zz;
           o.r[k] = rc[m];
           o.d[k] = di[m];
@@ -1385,7 +1405,7 @@ __global__ void __launch_bounds__(kBlock)
     float hr = 0.f, hd = 0.f;
     uint8_t hc = 0;
     auto load_halo = [&](int zz) {
-      if (hx != -1 && in_grid(hx, hy, zz)) {
+      if (hx != -1 && zz < z1 && in_grid(hx, hy, zz)) {
         const int64_t m = hx + sy * hy + sz * zz;
         hr = rc[m], hd = di[m], hc = code[m];
       } else {
