@@ -39,7 +39,11 @@ enum ScalarSlot {
   S_LSUM2,
   S_COUNT = 32
 };
-enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_COUNT = 16 };
+// F_DONE: 0 running, 1 converged, 2 breakdown, 3 (flexible CG) the recursive
+// residual met the tolerance inside a block of four iterations: the block's
+// remaining iterations are skipped, its iterate update and FP64 check still
+// run, and the check turns 3 into 1, or into 0 with F_RESTART (beta = 0).
+enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_RESTART, F_COUNT = 16 };
 
 struct F3 {
   float* c[3];
@@ -64,6 +68,7 @@ enum FinMode : int {
   FIN_DCG_INIT,      // [bb, rz, rr]  -> BB, RZ, RZ_PREV, RR, BETA = 0; done at tol
   FIN_SLOT,          // [v]           -> scal[slot] = (acc ? scal[slot] : 0) + scale * v
   FIN_SLOTS4,        // [v0..v3]      -> scal[slot + q] = (acc ? scal[slot + q] : 0) + scale * vq
+  FIN_FCG_RR,        // [rr]          -> NET_SUMSQ; at tol (phase = slot < 3): F_DONE = 3, later alphas 0
 };
 
 }  // namespace fs
@@ -177,7 +182,7 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
 void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 // the same four-step iterate update for the flexible CG (alpha = d.r / d.q)
 // also reduces |r|^2 into S_NET_SUMSQ (the learned preconditioner's input scale)
-void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);

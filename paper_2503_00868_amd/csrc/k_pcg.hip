@@ -105,8 +105,10 @@ __global__ void __launch_bounds__(kBlock)
     k_finalize(const double* __restrict__ partials, int nblocks, int nv, int mode, double* scal,
                int* flags, double tol2, int jacobi, int slot, double scale, int acc) {
   const bool in_loop = mode == FIN_DQ || mode == FIN_RZ_UPD || mode == FIN_RZ_FIRST ||
-                       mode == FIN_CHECK || mode == FIN_FCG_DQDR || mode == FIN_FCG_BETA;
-  if (in_loop && flags[F_DONE]) return;
+                       mode == FIN_CHECK || mode == FIN_FCG_DQDR || mode == FIN_FCG_BETA ||
+                       mode == FIN_FCG_RR;
+  // the check also runs after an early stop (F_DONE = 3), which it decides
+  if (in_loop && flags[F_DONE] && !(mode == FIN_CHECK && flags[F_DONE] == 3)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kBlock)
     for (int q = 0; q < nv; ++q) v[q] += partials[(int64_t)b * nv + q];
@@ -122,6 +124,7 @@ __global__ void __launch_bounds__(kBlock)
       flags[F_DONE] = v[0] == 0.0 ? 1 : 0;
       flags[F_ITERS] = 0;
       flags[F_ITERS_AT_DONE] = 0;
+      flags[F_RESTART] = 0;
       break;
     case FIN_DQ:
       scal[S_DQ] = v[0];
@@ -155,6 +158,12 @@ __global__ void __launch_bounds__(kBlock)
         flags[F_ITERS_AT_DONE] = flags[F_ITERS];
       } else if (!(v[0] == v[0])) {
         flags[F_DONE] = 2;
+      } else if (flags[F_DONE] == 3) {
+        // an early stop the true residual does not confirm: go on from the
+        // updated iterate with a fresh direction (the skipped iterations
+        // left the direction buffers behind)
+        flags[F_DONE] = 0;
+        flags[F_RESTART] = 1;
       }
       break;
     case FIN_FCG_DQDR:
@@ -166,8 +175,19 @@ __global__ void __launch_bounds__(kBlock)
       if (!(v[0] > 0.0) || !(v[1] == v[1])) flags[F_DONE] = 2;
       break;
     case FIN_FCG_BETA:
-      scal[S_BETA] = -v[0] / scal[S_DQ];
+      scal[S_BETA] = flags[F_RESTART] ? 0.0 : -v[0] / scal[S_DQ];
+      flags[F_RESTART] = 0;
       if (!(scal[S_BETA] == scal[S_BETA])) flags[F_DONE] = 2;
+      break;
+    case FIN_FCG_RR:
+      // the recursive |r|^2 after the update of phase `slot` (0..2): at the
+      // tolerance the block's later iterations are skipped and drop out of
+      // the four-step iterate update (their alphas 0)
+      scal[S_NET_SUMSQ] = v[0];
+      if (v[0] <= tol2 * scal[S_BB]) {
+        flags[F_DONE] = 3;
+        for (int q = slot + 1; q < 3; ++q) scal[S_ALPHA_Q0 + q] = 0.0;
+      }
       break;
     case FIN_DCG_INIT:
       scal[S_BB] = v[0];
@@ -442,7 +462,8 @@ __device__ inline void dir_raw_eval(const DirRaw<PREC>& w, float beta, float (&o
   for (int e = 0; e < 4; ++e) {
     const float zv =
         PREC == PK_JACOBI ? w.a[e] * c_inv_count[(w.g >> (8 * e)) & 255u] : w.a[e];
-    o[e] = zv + beta * w.d[e];
+    // beta = 0 (first direction, restart): the previous direction is not read
+    o[e] = beta != 0.f ? zv + beta * w.d[e] : zv;
   }
 }
 
@@ -520,7 +541,8 @@ __global__ void __launch_bounds__(kBlock)
     // halo values of plane zz from the data loaded one iteration ago
     float hyv[4];
     dir_raw_eval<PREC>(h1, beta, hyv);
-    const float hxv = (PREC == PK_JACOBI ? hxa * c_inv_count[hxg] : hxa) + beta * hxd;
+    const float hxz = PREC == PK_JACOBI ? hxa * c_inv_count[hxg] : hxa;
+    const float hxv = beta != 0.f ? hxz + beta * hxd : hxz;
     dir_raw_eval<PREC>(c1, beta, dp);
     // issue the next loads before the barrier
     load_center(zz + 2, c2);
@@ -568,7 +590,7 @@ __global__ void __launch_bounds__(kBlock)
     k_check_zm(int n, int zc, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
                const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
                double* partials, int* __restrict__ work) {
-  if (flags[F_DONE]) return;
+  if (flags[F_DONE] == 1 || flags[F_DONE] == 2) return;  // runs after an early stop (3)
   count_work(work);
   // two plane slots, one barrier per plane (as in k_dir_spmv_zm)
   __shared__ double sx2[2][ZM_TY + 2][ZM_W];
@@ -724,10 +746,15 @@ __global__ void __launch_bounds__(kBlock)
               const float* __restrict__ d2, const float* __restrict__ d3,
               const float* __restrict__ q, double* __restrict__ scal, int phase,
               const int* __restrict__ flags, double* partials, int* __restrict__ work) {
-  if (flags[F_DONE]) return;
+  // after an early stop of the flexible CG (F_DONE = 3) the block's iterate
+  // update still runs, without a step of its own (alpha 0) and with the
+  // skipped iterations' alphas zeroed
+  const int done = flags[F_DONE];
+  const bool early = FLEX && WITH_X && done == 3;
+  if (done && !early) return;
   count_work(work);
   const int64_t G = cells(n) / V;
-  const double alpha = (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
+  const double alpha = early ? 0.0 : (FLEX ? scal[S_DR] : scal[S_RZ]) / scal[S_DQ];
   const float alpha_f = (float)alpha;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const Run run = group_run(G, gridDim.x, lb);
@@ -753,10 +780,12 @@ __global__ void __launch_bounds__(kBlock)
       ldf<V>(d1 + idx, e1);
       ldf<V>(d2 + idx, e2);
       ldf<V>(d3 + idx, e3);
+      // a zero alpha leaves its direction unread (a skipped iteration's
+      // buffer may hold anything)
 #pragma unroll
       for (int e = 0; e < V; ++e)
-        xv[e] += (a0 * (double)e0[e] + a1 * (double)e1[e]) +
-                 (a2 * (double)e2[e] + alpha * (double)e3[e]);
+        xv[e] += ((a0 != 0.0 ? a0 * (double)e0[e] : 0.0) + (a1 != 0.0 ? a1 * (double)e1[e] : 0.0)) +
+                 ((a2 != 0.0 ? a2 * (double)e2[e] : 0.0) + (alpha != 0.0 ? alpha * (double)e3[e] : 0.0));
       std_<V>(x + idx, xv);
     }
 #pragma unroll
@@ -837,7 +866,7 @@ __global__ void __launch_bounds__(kBlock)
     k_check(int n, const uint8_t* __restrict__ cdiag, const float* __restrict__ b,
             const double* __restrict__ x, float* __restrict__ r, const int* __restrict__ flags,
             double* partials, int* __restrict__ work) {
-  if (flags[F_DONE]) return;
+  if (flags[F_DONE] == 1 || flags[F_DONE] == 2) return;  // runs after an early stop (3)
   count_work(work);
   const int64_t G = cells(n) / V;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -1068,7 +1097,7 @@ void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
   launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }
 
-void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol) {
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
   if (phase == 3)
     FS_CELL_LAUNCH(k_update4, true, true);
@@ -1076,8 +1105,13 @@ void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
     FS_CELL_LAUNCH(k_update4, false, true);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
 #undef ARGS
-  // |r|^2 of the updated residual, for the learned preconditioner's input
-  launch_finalize(c, c->grid_cells, 1, FIN_SLOT, 0.0, 0, S_NET_SUMSQ, 1.0, 0);
+  // |r|^2 of the updated residual, for the learned preconditioner's input;
+  // inside a block it also ends the block early once it meets 0.9 tol (the
+  // margin keeps the FP64 check from refusing the stop)
+  if (phase < 3)
+    launch_finalize(c, c->grid_cells, 1, FIN_FCG_RR, tol_sq(0.9 * tol), 0, phase, 0.0, 0);
+  else
+    launch_finalize(c, c->grid_cells, 1, FIN_SLOT, 0.0, 0, S_NET_SUMSQ, 1.0, 0);
 }
 
 void launch_pcg_rz_first(sim_ctx* c, int first) {

@@ -342,3 +342,37 @@ def test_trained_network_gain(torch_gpu, orc, seed):
     assert t_it < iters["mic0"][0]
     u_it, u_fb = iters["untrained"]
     assert u_fb == 1 or u_it >= 2 * t_it
+
+
+def test_fcg_early_stop_inside_a_block(torch_gpu, orc):
+    """The flexible CG runs in blocks of four iterations with the FP64 check
+    at each block's end; when the recursive residual meets the tolerance
+    inside a block, the block's remaining iterations (and their network
+    applications) are skipped, the iterate takes only the steps that ran and
+    the check decides.  Solves then end at iteration counts that are not
+    multiples of four, without the fallback, and the fields still match the
+    oracle's 1e-12 projection."""
+    import os
+    from paper_2503_00868_amd import train
+    from paper_2503_00868_amd.fluidsim import SIM_OK, Sim
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2503_00868_amd", "weights", "unet.safetensors")
+    w = torch_gpu.as_tensor(net_weights.load_weights(path), device="cuda")
+    n = 48
+    counts = []
+    for seed in (902, 903, 904, 905):
+        banner(f"fcg early stop n={n} seed={seed}")
+        cell = inputs.gen_mask(n, seed)
+        sim = Sim(cell, precond="learned", check_every=4, learned_max_iter=200)
+        sim.net_set_weights(w)
+        u = train.pre_projection_field(sim, seed)
+        u_in = to_np(u)
+        st, _ = sim.project(u)
+        counts.append(st["iters"])
+        assert st["status"] == SIM_OK and st["fallback_used"] == 0, st
+        assert st["rel_residual"] <= 1e-6, st
+        ref, _, _, _ = orc.project(cell, tuple(x.astype(np.float64) for x in u_in), 1e-12)
+        l2, mx = rel_err(to_np(u), ref)
+        assert mx < 1e-5, (seed, l2, mx)
+    banner(f"  iterations: {counts}")
+    assert any(k % 4 != 0 for k in counts), counts
