@@ -39,10 +39,11 @@ enum ScalarSlot {
   S_LSUM2,
   S_COUNT = 32
 };
-// F_DONE: 0 running, 1 converged, 2 breakdown, 3 (flexible CG) the recursive
-// residual met the tolerance inside a block of four iterations: the block's
-// remaining iterations are skipped, its iterate update and FP64 check still
-// run, and the check turns 3 into 1, or into 0 with F_RESTART (beta = 0).
+// F_DONE: 0 running, 1 converged, 2 breakdown, 3 (flexible and viscosity CG)
+// the recursive residual met the tolerance inside a block of iterations: the
+// block's remaining iterations are skipped, the flexible CG's iterate update
+// and the FP64 check still run, and the check turns 3 into 1, or into 0 with
+// a restart (beta = 0: F_RESTART for the flexible CG's beta).
 enum FlagSlot { F_DONE = 0, F_ITERS, F_ITERS_AT_DONE, F_BAD, F_RESTART, F_COUNT = 16 };
 
 struct F3 {
@@ -69,6 +70,7 @@ enum FinMode : int {
   FIN_SLOT,          // [v]           -> scal[slot] = (acc ? scal[slot] : 0) + scale * v
   FIN_SLOTS4,        // [v0..v3]      -> scal[slot + q] = (acc ? scal[slot + q] : 0) + scale * vq
   FIN_FCG_RR,        // [rr]          -> NET_SUMSQ; at tol (phase = slot < 3): F_DONE = 3, later alphas 0
+  FIN_DCG_UPD,       // [rz, rr]      -> as FIN_RZ_UPD; F_DONE = 3 when rr meets tol
 };
 
 }  // namespace fs
@@ -204,7 +206,7 @@ void launch_fcg_check(sim_ctx* c, double tol);
 // implicit viscosity CG pieces (face domain, FP64 iterate ctx->fx, rhs ctx->tmp)
 void launch_dcg_init(sim_ctx* c, float alpha);
 void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_out);
-void launch_dcg_update(sim_ctx* c, float alpha, const float* d);
+void launch_dcg_update(sim_ctx* c, float alpha, const float* d, double tol);
 void launch_dcg_check(sim_ctx* c, float alpha, double tol);
 void launch_dcg_finish(sim_ctx* c, F3 out);
 

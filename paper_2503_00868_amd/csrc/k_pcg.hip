@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kBlock)
                int* flags, double tol2, int jacobi, int slot, double scale, int acc) {
   const bool in_loop = mode == FIN_DQ || mode == FIN_RZ_UPD || mode == FIN_RZ_FIRST ||
                        mode == FIN_CHECK || mode == FIN_FCG_DQDR || mode == FIN_FCG_BETA ||
-                       mode == FIN_FCG_RR;
+                       mode == FIN_FCG_RR || mode == FIN_DCG_UPD;
   // the check also runs after an early stop (F_DONE = 3), which it decides
   if (in_loop && flags[F_DONE] && !(mode == FIN_CHECK && flags[F_DONE] == 3)) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -163,7 +163,10 @@ __global__ void __launch_bounds__(kBlock)
         // updated iterate with a fresh direction (the skipped iterations
         // left the direction buffers behind)
         flags[F_DONE] = 0;
-        flags[F_RESTART] = 1;
+        if (jacobi)
+          scal[S_BETA] = 0.0;
+        else
+          flags[F_RESTART] = 1;
       }
       break;
     case FIN_FCG_DQDR:
@@ -179,6 +182,17 @@ __global__ void __launch_bounds__(kBlock)
       flags[F_RESTART] = 0;
       if (!(scal[S_BETA] == scal[S_BETA])) flags[F_DONE] = 2;
       break;
+    case FIN_DCG_UPD: {
+      const double rz_old = scal[S_RZ];
+      scal[S_RZ_PREV] = rz_old;
+      scal[S_RZ] = v[0];
+      scal[S_BETA] = v[0] / rz_old;
+      if (!(v[0] >= 0.0))
+        flags[F_DONE] = 2;
+      else if (v[1] <= tol2 * scal[S_BB])
+        flags[F_DONE] = 3;  // the rest of the block is skipped; the check decides
+      break;
+    }
     case FIN_FCG_RR:
       // the recursive |r|^2 after the update of phase `slot` (0..2): at the
       // tolerance the block's later iterations are skipped and drop out of
@@ -269,7 +283,7 @@ __device__ inline void dir_at(const float* __restrict__ r, const float* __restri
     ldf<V>(z + idx, zv);
   }
 #pragma unroll
-  for (int e = 0; e < V; ++e) o[e] = zv[e] + beta * dv[e];
+  for (int e = 0; e < V; ++e) o[e] = beta != 0.f ? zv[e] + beta * dv[e] : zv[e];
 }
 
 // d' = z + beta d_in ; q = A d' ; partials d'.q (and d'.r for flexible CG).
@@ -1319,7 +1333,11 @@ __global__ void __launch_bounds__(kBlock)
   float* __restrict__ qc = q + comp * F;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const Chunk2 ch = chunk_of(F, gridDim.x, lb);
-  auto dir = [&](int64_t m) -> float { return rc[m] * mrow_diag_inv(code[m], alpha) + beta * di[m]; };
+  // beta = 0 (first direction, restart): the previous direction is not read
+  auto dir = [&](int64_t m) -> float {
+    const float zv = rc[m] * mrow_diag_inv(code[m], alpha);
+    return beta != 0.f ? zv + beta * di[m] : zv;
+  };
   double v[1] = {0.0};
   for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock) {
     const uint8_t cd = code[idx];
@@ -1400,7 +1418,11 @@ __global__ void __launch_bounds__(kBlock)
     auto in_grid = [&](int xx, int yy, int zz) {
       return xx >= 0 && xx < dm3.nx && yy >= 0 && yy < dm3.ny && zz >= 0 && zz < dm3.nz;
     };
-    auto dir_of = [&](float rv, float dv, uint8_t cd) { return rv * mrow_diag_inv(cd, alpha) + beta * dv; };
+    // beta = 0 (first direction, restart): the previous direction is not read
+    auto dir_of = [&](float rv, float dv, uint8_t cd) {
+      const float zv = rv * mrow_diag_inv(cd, alpha);
+      return beta != 0.f ? zv + beta * dv : zv;
+    };
     // raw (r, d, code) of this thread's faces of one plane, and of its halo face
     struct Raw {
       float r[DZ_K], d[DZ_K];
@@ -1527,7 +1549,8 @@ __global__ void __launch_bounds__(kBlock)
   const float* __restrict__ qc = q + comp * F;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const Chunk2 ch = chunk_of(F, gridDim.x, lb);
-  double v[1] = {0.0};
+  // [r.M^-1 r, |r|^2 for the early stop]
+  double v[2] = {0.0, 0.0};
   for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock) {
     const uint8_t cd = code[idx];
     if (!(cd & FC_ACTIVE)) continue;
@@ -1535,15 +1558,16 @@ __global__ void __launch_bounds__(kBlock)
     const float rn = rc[idx] - af * qc[idx];
     rc[idx] = rn;
     v[0] += (double)rn * (double)rn * mrow_diag_inv(cd, alpha);
+    v[1] += (double)rn * (double)rn;
   }
-  store_partials<1>(v, partials, comp * gridDim.x + lb);
+  store_partials<2>(v, partials, comp * gridDim.x + lb);
 }
 
 __global__ void __launch_bounds__(kBlock)
     k_dcg_check(int n, const uint8_t* __restrict__ fcode, float alpha, const float* __restrict__ b,
                 const double* __restrict__ x, float* __restrict__ r, int64_t F,
                 const int* __restrict__ flags, double* partials) {
-  if (flags[F_DONE]) return;
+  if (flags[F_DONE] == 1 || flags[F_DONE] == 2) return;  // runs after an early stop (3)
   const int comp = blockIdx.y;
   const Dims d = face_dims(n, comp);
   const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
@@ -1603,13 +1627,15 @@ void launch_dcg_dir_spmv(sim_ctx* c, float alpha, const float* d_in, float* d_ou
   launch_finalize(c, 3 * c->grid_faces, 1, FIN_DQ, 0.0, 0, 0, 0.0, 0);
 }
 
-void launch_dcg_update(sim_ctx* c, float alpha, const float* d) {
+void launch_dcg_update(sim_ctx* c, float alpha, const float* d, double tol) {
   prof_mark(c, SIM_KERN_DCG_UPDATE, true);
   hipLaunchKernelGGL(k_dcg_update, dim3(c->grid_faces, 3), dim3(kBlock), 0, c->stream, c->fcode,
                      alpha, c->fx, c->fr, d, c->fq, c->F, c->scal, c->flags, c->partials,
                      c->work + SIM_KERN_DCG_UPDATE);
   prof_mark(c, SIM_KERN_DCG_UPDATE, false);
-  launch_finalize(c, 3 * c->grid_faces, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
+  // the iterate is updated every iteration, so the block may end as soon as
+  // the recursive |r|^2 meets 0.9 tol (the FP64 check at its end decides)
+  launch_finalize(c, 3 * c->grid_faces, 2, FIN_DCG_UPD, tol_sq(0.9 * tol), 1, 0, 0.0, 0);
 }
 
 void launch_dcg_check(sim_ctx* c, float alpha, double tol) {

@@ -530,7 +530,7 @@ int diffuse_implicit(sim_ctx* c, F3 out, sim_stats* st) {
   auto block = [&](int todo) {
     for (int t = 0; t < todo; ++t) {
       launch_dcg_dir_spmv(c, alpha, din, dout);
-      launch_dcg_update(c, alpha, dout);
+      launch_dcg_update(c, alpha, dout, tol);  // may end the block early
       if (t == todo - 1) launch_dcg_check(c, alpha, tol);
       std::swap(din, dout);
     }

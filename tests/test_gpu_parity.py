@@ -60,6 +60,29 @@ def test_diffuse_parity(torch_gpu, orc, n, nu, mode):
         assert st["diff_iters"] > 0 and st["diff_rel_residual"] <= 1e-7
 
 
+def test_diffuse_early_stop_inside_a_block(torch_gpu, orc):
+    """The viscosity CG checks its FP64 residual every check_every
+    iterations; when the recursive residual meets the tolerance inside a
+    block, the block's remaining iterations are skipped and the block-end
+    check decides.  Iteration counts then need not be multiples of the check
+    period, and the result still matches the oracle's 1e-12 solve."""
+    counts = []
+    for n, nu, seed in ((24, 2e-2, 3), (24, 6e-2, 4), (28, 1e-1, 5), (20, 3e-1, 6)):
+        banner(f"diffuse early stop n={n} nu={nu}")
+        cell, u = case(n, seed)
+        u = orc.mask_faces(cell, u)
+        sim = _sim(cell, diffusion="implicit", diff_tol=1e-7, check_every=8)
+        sim.set_params(nu=nu, dt=DT)
+        out, st = sim.op_diffuse(sim.to_faces(u))
+        counts.append(st["diff_iters"])
+        ref, _, _ = orc.diffuse(cell, u, nu, DT, "implicit", 1e-12)
+        l2, mx = rel_err(to_np(out), ref)
+        assert mx < 2e-6, (n, nu, l2, mx, st)
+        assert st["diff_rel_residual"] <= 1e-7, st
+    banner(f"  iterations: {counts}")
+    assert any(k % 8 != 0 for k in counts), counts
+
+
 @pytest.mark.parametrize("n", [32, 19])
 def test_divergence_and_poisson_apply_parity(torch_gpu, orc, n):
     banner(f"divergence/poisson n={n}")
