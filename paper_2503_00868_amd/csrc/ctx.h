@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/fluidsim.h"
 
@@ -108,8 +109,12 @@ struct sim_ctx {
   float* precon = nullptr;  // MIC(0) factor
   float* mq = nullptr;      // MIC(0) forward-sweep result
   double* pc_acc = nullptr; // recurrent conv solver: weight-gradient sums (28)
-  double* xw = nullptr;     // warm start: pressure of the previous rollout step
-  double* xwa = nullptr;    // warm start: previous adjoint pressure
+  // warm starts: the last two pressures of the rollout's forward steps (xw
+  // newest, xw2) and how many are known; the previous adjoint pressure
+  double* xw = nullptr;
+  double* xw2 = nullptr;
+  int warm_n = 0;
+  double* xwa = nullptr;
 
   // face-domain buffers, each 3F stacked
   float* tmp = nullptr;  // advection output / diffusion right-hand side
@@ -129,7 +134,9 @@ struct sim_ctx {
 
   // rollout recording
   float* ckpt = nullptr;  // (ckpt_slots) x 3F
-  double* ckpt_x = nullptr;  // warm start: (ckpt_slots) x C pressures at the checkpoints
+  double* ckpt_x = nullptr;   // warm start: (ckpt_slots) x C pressures xw at the checkpoints
+  double* ckpt_x2 = nullptr;  // and xw2
+  std::vector<int> ckpt_warm;  // and warm_n
   double* xhist = nullptr;   // store_pressures: max_steps x C pressures of the recorded steps
   float* vhist = nullptr;    // store_pressures: max_steps x 3F implicit viscosity outputs
   int ckpt_slots = 0;
@@ -192,6 +199,8 @@ void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
 // out = x over the cells; skipped when flags (nullable) has the done flag raised
 void launch_x_to_double(sim_ctx* c, const double* x, double* out, const int* flags = nullptr);
+// o = 2 a - o: the linear extrapolation of the sequence ..., o, a
+void launch_x_extrapolate(sim_ctx* c, const double* a, double* o);
 // out = (float)(xref - x) over the cells (FP64 difference)
 void launch_err_snapshot(sim_ctx* c, const double* xref, float* out);
 

@@ -1012,6 +1012,13 @@ __global__ void __launch_bounds__(kBlock)
     o[idx] = a[idx];
 }
 
+__global__ void __launch_bounds__(kBlock)
+    k_extrapolate_double(int64_t C, const double* __restrict__ a, double* __restrict__ o) {
+  for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
+       idx += (int64_t)gridDim.x * kBlock)
+    o[idx] = 2.0 * a[idx] - o[idx];
+}
+
 // ----------------------------------------------------------- launchers
 
 // Launch kern<4, ...> when rows hold whole 4-cell groups, else kern<1, ...>;
@@ -1187,6 +1194,10 @@ void launch_jacobi_apply(sim_ctx* c, const float* r, float* z) {
 void launch_x_to_double(sim_ctx* c, const double* xin, double* out, const int* flags) {
   hipLaunchKernelGGL(k_copy_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, xin, out,
                      flags);
+}
+
+void launch_x_extrapolate(sim_ctx* c, const double* a, double* o) {
+  hipLaunchKernelGGL(k_extrapolate_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, a, o);
 }
 
 // ---------------------------------------------------------- flexible CG

@@ -118,6 +118,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->mq = mic ? cv.take<float>(C) : nullptr;
   t->rprev = d.precond == SIM_PRECOND_LEARNED ? cv.take<float>(C) : nullptr;
   t->xw = d.warm_start ? cv.take<double>(C) : nullptr;
+  t->xw2 = d.warm_start ? cv.take<double>(C) : nullptr;
   t->xwa = d.warm_start ? cv.take<double>(C) : nullptr;
   t->tmp = cv.take<float>(F3n);
   t->fx = cv.take<double>(F3n);
@@ -138,6 +139,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt_slots = (d.max_steps + d.checkpoint_every - 1) / d.checkpoint_every;
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
     t->ckpt_x = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
+    t->ckpt_x2 = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
     t->xhist = d.store_pressures ? cv.take<double>((size_t)d.max_steps * C) : nullptr;
     t->vhist = d.store_pressures && d.diffusion != SIM_DIFFUSION_EXPLICIT
                    ? cv.take<float>((size_t)d.max_steps * F3n)
@@ -147,6 +149,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt_slots = 0;
     t->ckpt = nullptr;
     t->ckpt_x = nullptr;
+    t->ckpt_x2 = nullptr;
     t->xhist = nullptr;
     t->vhist = nullptr;
     t->seg = nullptr;
@@ -580,6 +583,30 @@ void advect_force(sim_ctx* c, CF3 in, F3 out) {
   launch_advect(c, in, out, dth, force);
 }
 
+// Warm-started projection of a rollout's forward step: the solve starts from
+// the linear extrapolation 2 x1 - x2 of the last two steps' pressures (from
+// x1 while fewer are known; x1 is zero at the rollout's start), and its
+// pressure becomes x1.  The guess is formed in x2's storage, the solve stores
+// into it, and the two pointers swap.  (Measured at 256^3 over the benchmark
+// rollout: 30.8 -> 25.3 flexible-CG iterations per forward solve; weights
+// 0.7 and 1.3 on the difference instead of 1 gave 27.6 and 26.7.  The adjoint
+// solves, whose right-hand sides change less smoothly from step to step, run
+// more iterations from an extrapolated start and keep the previous pressure.)
+int project_warm(sim_ctx* c, F3 u, sim_stats* st) {
+  double*& x1 = c->xw;
+  double*& x2 = c->xw2;
+  int& known = c->warm_n;
+  if (!x1 || !x2) return project_inplace(c, u, st, x1);
+  if (known >= 2)
+    launch_x_extrapolate(c, x1, x2);
+  else
+    launch_x_to_double(c, x1, x2);
+  const int rc = project_inplace(c, u, st, x2);
+  std::swap(x1, x2);
+  if (known < 2) ++known;
+  return rc;
+}
+
 // One step in place: advect (+force) -> viscosity -> projection.
 // rec_step >= 0: a recorded step whose implicit viscosity output is kept in
 // the history (store_pressures).
@@ -590,7 +617,7 @@ int step_once(sim_ctx* c, F3 u, sim_stats* st, int rec_step = -1) {
   if (rec_step >= 0 && c->vhist && !diffusion_explicit(c))
     launch_copy_faces(c, cf3(u.c[0], u.c[1], u.c[2]),
                       stacked(c, c->vhist + (int64_t)rec_step * 3 * c->F));
-  return project_inplace(c, u, st, c->xw);
+  return project_warm(c, u, st);
 }
 
 int combine(int a, int b) {
@@ -636,6 +663,7 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   c->n_active = count_active(c->n, h_cell_type);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   carve(*desc, reinterpret_cast<char*>(d_workspace), c);
+  c->ckpt_warm.assign((size_t)c->ckpt_slots, 0);
   c->grid_cells = grid_for(c->C);
   c->grid_faces = grid_for(c->F);
   auto fail = [&](int code) {
@@ -650,7 +678,7 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   if (hipMemsetAsync(c->scal, 0, kCtrlBytes, c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
   if (hipMemsetAsync(c->work, 0, sizeof(int) * SIM_KERN_COUNT, c->stream) != hipSuccess)
     return fail(SIM_ERR_HIP);
-  for (double* wbuf : {c->xw, c->xwa})
+  for (double* wbuf : {c->xw, c->xw2, c->xwa})
     if (wbuf && hipMemsetAsync(wbuf, 0, sizeof(double) * c->C, c->stream) != hipSuccess)
       return fail(SIM_ERR_HIP);
   launch_setup_tables(c);
@@ -781,6 +809,7 @@ int sim_init_state(sim_ctx* c, const float* gu, const float* gv, const float* gw
   }
   launch_mask_scale(c, cf3(gu, gv, gw), f3(u, v, w), (float)c->params.s);
   if (c->xw) HIPCHK(hipMemsetAsync(c->xw, 0, sizeof(double) * c->C, c->stream));
+  c->warm_n = 0;
   return launch_status(c);
 }
 
@@ -810,7 +839,11 @@ int sim_step(sim_ctx* c, float* u, float* v, float* w, int32_t nsteps, int32_t r
   for (int s = 0; s < nsteps; ++s) {
     if (record && s % K == 0) {
       launch_copy_faces(c, cf3(u, v, w), stacked(c, c->ckpt + (int64_t)(s / K) * F3n));
-      if (c->ckpt_x) launch_x_to_double(c, c->xw, c->ckpt_x + (int64_t)(s / K) * c->C);
+      if (c->ckpt_x) {
+        launch_x_to_double(c, c->xw, c->ckpt_x + (int64_t)(s / K) * c->C);
+        launch_x_to_double(c, c->xw2, c->ckpt_x2 + (int64_t)(s / K) * c->C);
+        c->ckpt_warm[s / K] = c->warm_n;
+      }
     }
     sim_stats st{};
     int rc = step_once(c, U, &st, record ? s : -1);
@@ -909,7 +942,11 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
     float* state0 = c->seg;  // slot q: state of step s0+q; slot K+q: viscosity operand
     launch_copy_faces(c, cstacked(c, c->ckpt + (int64_t)(s0 / K) * F3n), stacked(c, state0));
     // the recompute repeats the forward solves from the same starting iterates
-    if (c->ckpt_x) launch_x_to_double(c, c->ckpt_x + (int64_t)(s0 / K) * c->C, c->xw);
+    if (c->ckpt_x) {
+      launch_x_to_double(c, c->ckpt_x + (int64_t)(s0 / K) * c->C, c->xw);
+      launch_x_to_double(c, c->ckpt_x2 + (int64_t)(s0 / K) * c->C, c->xw2);
+      c->warm_n = c->ckpt_warm[s0 / K];
+    }
     // with the history, the implicit viscosity outputs are the forward's own
     // (copied: no advection, no viscosity solve)
     const bool have_visc = c->vhist && !explicit_d;
@@ -932,7 +969,8 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
         else
           launch_copy_faces(c, cf3(nxt.c[0], nxt.c[1], nxt.c[2]), op);
         // the forward's own pressure (stored) or its warm start
-        const int rc = project_inplace(c, nxt, nullptr, c->xhist ? c->xhist + (int64_t)s * c->C : c->xw);
+        const int rc = c->xhist ? project_inplace(c, nxt, nullptr, c->xhist + (int64_t)s * c->C)
+                                : project_warm(c, nxt, nullptr);
         worst = combine(worst, rc);
         if (rc < 0) return rc;
       } else {
