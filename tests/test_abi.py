@@ -78,14 +78,14 @@ def test_workspace_size_grows_with_recording_and_precond():
     # Jacobi keeps two extra direction buffers, MIC(0) its factor and sweep
     # temporary (the same size); the network adds its activations
     assert rec > base and mic == base and learned > mic
-    # warm start: three FP64 pressures (the forward's last two, for their
-    # extrapolation, and the adjoint's last), plus the forward's two per
+    # warm start: four FP64 pressures (the forward's last three, for their
+    # extrapolation, and the adjoint's last), plus the forward's three per
     # checkpoint (16 / 4 = 4) when recording
     n = 16
     _, warm = _ws_size(_desc(max_steps=0, warm_start=True))
     _, warm_rec = _ws_size(_desc(max_steps=16, warm_start=True))
-    assert warm - base >= 3 * 8 * n ** 3
-    assert warm_rec - rec >= (3 + 2 * 4) * 8 * n ** 3
+    assert warm - base >= 4 * 8 * n ** 3
+    assert warm_rec - rec >= (4 + 3 * 4) * 8 * n ** 3
     n = 16
     assert base > (3 * (n + 1) * n * n) * 4 * 7  # at least the face-domain buffers
 
