@@ -215,6 +215,8 @@ void launch_fcg_update(sim_ctx* c, const float* d);
 void launch_fcg_beta(sim_ctx* c);
 void launch_fcg_beta_first(sim_ctx* c, int first);
 void launch_fcg_check(sim_ctx* c, double tol);
+// beta from z.q block partials that the network's output layer reduced
+void launch_fcg_beta_partials(sim_ctx* c, int nblocks);
 
 // implicit viscosity CG pieces (face domain, FP64 iterate ctx->fx, rhs ctx->tmp)
 void launch_dcg_init(sim_ctx* c, float alpha);

@@ -46,12 +46,15 @@ static OutGrid out_grid(int n) {
 // forward layout [16][28][16] bf16 (only output channel 0 is real), read as
 // bf16 pairs: w2[tap * 8 + j] holds input channels 2j, 2j + 1 of tap
 // dx + 3 dy + 9 dz.  act_in, act (nullable, both or neither): activity maps
-// of D and of z.
+// of D and of z.  qdot (nullable): the block also reduces z . qdot over its
+// voxels into partials[blockIdx.x] (FP64), the flexible CG's z.q for beta,
+// which then needs no pass of its own over z and q.
 __global__ void __launch_bounds__(kBlock)
     k_conv_out(int n, int zc, const __bf16* __restrict__ D, const uint32_t* __restrict__ w2,
                float* __restrict__ z, const uint8_t* __restrict__ mask,
                const double* __restrict__ rms_p, const int* __restrict__ flags,
-               const uint8_t* __restrict__ act_in, const uint8_t* __restrict__ act) {
+               const uint8_t* __restrict__ act_in, const uint8_t* __restrict__ act,
+               const float* __restrict__ qdot, double* __restrict__ partials) {
   if (flags && flags[F_DONE]) return;
   // two staged planes, each as two 8-channel halves [half][voxel] (16 B per
   // voxel and half: the 16 lanes of a row read consecutive words)
@@ -66,7 +69,10 @@ __global__ void __launch_bounds__(kBlock)
   const int x0 = (tile % tpr) * OT, y0 = (tile / tpr) * OT;
   const int z0 = chunk * zc;
   const int z1 = min(z0 + zc, n);
-  if (z0 >= n) return;
+  if (z0 >= n) {
+    if (qdot && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
   const int tx = threadIdx.x & (OT - 1), ty = threadIdx.x / OT;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < n && y < n;
@@ -128,6 +134,7 @@ __global__ void __launch_bounds__(kBlock)
   const float rms = (float)*rms_p;
   // sums of the output planes p - 1, p and p + 1 for the input plane p
   float s_lo = 0.f, s_mid = 0.f, s_hi = 0.f;
+  double zq = 0.0;
   load_plane(z0 - 1);
   for (int p = z0 - 1; p <= z1; ++p) {
     const int slot = p & 1;
@@ -164,18 +171,30 @@ __global__ void __launch_bounds__(kBlock)
       s_mid += c1;
       s_lo += c2;
     }
-    if (out_here) z[(int64_t)x + (int64_t)n * y + nn * o] = want_m && m_raw ? rms * s_lo : 0.f;
+    if (out_here) {
+      const int64_t idx = (int64_t)x + (int64_t)n * y + nn * o;
+      const float zv = want_m && m_raw ? rms * s_lo : 0.f;
+      z[idx] = zv;
+      if (qdot && zv != 0.f) zq += (double)zv * (double)qdot[idx];
+    }
     s_lo = s_mid;
     s_mid = s_hi;
     s_hi = 0.f;
   }
+  if (qdot) {
+    double v[1] = {zq};
+    store_partials<1>(v, partials, blockIdx.x);
+  }
 }
 
+int net_conv_out_blocks(int n) { return out_grid(n).blocks; }
+
 void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z, const double* rms,
-                  const int* flags, const uint8_t* act_in, const uint8_t* act) {
+                  const int* flags, const uint8_t* act_in, const uint8_t* act, const float* qdot) {
   const OutGrid g = out_grid(n);
   hipLaunchKernelGGL(k_conv_out, dim3(g.blocks), dim3(kBlock), 0, c->stream, n, g.zc, D,
-                     reinterpret_cast<const uint32_t*>(w), z, c->cdiag, rms, flags, act_in, act);
+                     reinterpret_cast<const uint32_t*>(w), z, c->cdiag, rms, flags, act_in, act,
+                     qdot, c->partials);
 }
 
 }  // namespace fs

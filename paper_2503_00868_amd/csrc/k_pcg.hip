@@ -1244,6 +1244,10 @@ void launch_fcg_beta_first(sim_ctx* c, int first) {
 
 void launch_fcg_beta(sim_ctx* c) { launch_fcg_beta_first(c, 0); }
 
+void launch_fcg_beta_partials(sim_ctx* c, int nblocks) {
+  launch_finalize(c, nblocks, 1, FIN_FCG_BETA, 0.0, 0, 0, 0.0, 0);
+}
+
 void launch_fcg_check(sim_ctx* c, double tol) { launch_pcg_check(c, PK_ZARRAY, tol); }
 
 // ------------------------------------------------- implicit viscosity CG

@@ -211,7 +211,7 @@ void wgrad(sim_ctx* c, int n, int l, NetSrc src, const __bf16* G, int g_stride, 
 // the mask directly, and the tiles the activity maps mark as zero are
 // skipped.
 int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_input,
-            bool have_sumsq = false) {
+            bool have_sumsq = false, const float* qdot = nullptr) {
   UNetState* s = c->net;
   const int n1 = s->n1, n2 = s->n2, n3 = s->n3;
   const bool skip = !keep_input && s->skip_tiles;
@@ -238,7 +238,7 @@ int forward(sim_ctx* c, const float* r, float* z, const int* flags, bool keep_in
   rc |= split_conv(c, n1, 32, 16, s->D2, s->weff9, s->T1, src1(s->E1, 16, A(M0_2)), s->wskip9, s->B1,
                    flags, A(M1_2), A(M0_2));
   rc |= conv(c, n1, 9, NET_EPI_RELU, src1(s->B1, 16, A(M0_2)), out_bf(s->D1, A(M0_1)), flags);
-  net_conv_out(c, n1, s->D1, s->wf[10], z, c->scal + S_NET_RMS, flags, A(M0_1), A(M0_0));
+  net_conv_out(c, n1, s->D1, s->wf[10], z, c->scal + S_NET_RMS, flags, A(M0_1), A(M0_0), qdot);
   return rc ? SIM_ERR_INVALID_ARG : SIM_OK;
 }
 
@@ -393,9 +393,10 @@ void net_destroy(sim_ctx* c) {
 
 bool net_ready(const sim_ctx* c) { return c->net && c->net->ready; }
 
-int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq) {
+int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq,
+              const float* qdot) {
   prof_mark(c, SIM_KERN_NET, true);
-  int rc = forward(c, r, z, flags, false, have_sumsq);
+  int rc = forward(c, r, z, flags, false, have_sumsq, qdot);
   prof_mark(c, SIM_KERN_NET, false);
   return rc;
 }

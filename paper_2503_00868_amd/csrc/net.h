@@ -53,8 +53,10 @@ bool net_ready(const sim_ctx* c);
 // z = mask * rms(r) * U(r / rms(r), mask); returns at once when flags (nullable)
 // has the done flag raised.  have_sumsq: the caller has already placed |r|^2
 // in the context's S_NET_SUMSQ slot (the flexible-CG update reduces it), so
-// the pass does not read r once more for it.
-int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq = false);
+// the pass does not read r once more for it.  qdot (nullable): the output
+// layer also reduces z . qdot into net_conv_out_blocks(n) block partials.
+int net_apply(sim_ctx* c, const float* r, float* z, const int* flags, bool have_sumsq = false,
+              const float* qdot = nullptr);
 
 // kernel launchers
 int conv_tiles(int n);
@@ -100,8 +102,12 @@ void net_input(sim_ctx* c, const float* r, const double* sumsq, double* rms_out,
 // c11 (16 -> 1) fused with the output map: z = mask * rms * conv(D), on the
 // vector ALU (bf16 dot products); w is the layer's packed forward weights.
 // act_in, act (nullable, both or neither): activity maps of D and of z.
+// qdot (nullable): also reduce z . qdot into net_conv_out_blocks(n) FP64
+// block partials (the context's partials buffer).
 void net_conv_out(sim_ctx* c, int n, const __bf16* D, const __bf16* w, float* z, const double* rms,
-                  const int* flags, const uint8_t* act_in, const uint8_t* act);
+                  const int* flags, const uint8_t* act_in, const uint8_t* act,
+                  const float* qdot = nullptr);
+int net_conv_out_blocks(int n);
 // c1 fused with the input: ReLU(conv(r / rms, mask)) -> out (16 channels),
 // rms written to rms_out; the 2-channel input is never stored.  r is read on
 // liquid cells only.  act (nullable): activity map of the level.  work

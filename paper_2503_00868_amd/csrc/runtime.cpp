@@ -468,6 +468,8 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
   const double tol = c->desc.tol;
   int inner_rc = SIM_OK;
   float* const dbuf[4] = {c->dA, c->dB, c->dC, c->dD};
+  const int zq_blocks = net_conv_out_blocks(c->n);
+  const bool zq_fused = zq_blocks <= kPartialDoubles;
   int it = 0;
   auto block = [&](int todo) {
     for (int t = 0; t < todo; ++t, ++it) {
@@ -479,10 +481,14 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
       launch_fcg_update4(c, dirs, ph, tol);
       if (t == todo - 1) launch_fcg_check(c, tol);
       // |r|^2 for the network: reduced by the update, or by the check when it
-      // has just replaced r by the true residual
-      int r2 = net_apply(c, c->r, c->z, c->flags, true);
+      // has just replaced r by the true residual; z.q for beta: reduced by
+      // the network's output layer (when its block partials fit)
+      int r2 = net_apply(c, c->r, c->z, c->flags, true, zq_fused ? c->q : nullptr);
       if (r2) inner_rc = r2;
-      launch_fcg_beta(c);
+      if (zq_fused)
+        launch_fcg_beta_partials(c, zq_blocks);
+      else
+        launch_fcg_beta(c);
     }
   };
   const int m = (c->desc.check_every + 3) / 4 * 4;
