@@ -41,6 +41,25 @@ constexpr int ZRV = ZR * ZR;        // 324 voxels per ring plane
 constexpr int ZSTEPS = 15;          // K-steps per 16-channel chunk
 constexpr int ZTAPS = 28;           // packed taps per weight row (27 + zero)
 constexpr int ZMAXC = 128;          // planes per block at most
+// bf16 between the 8-channel parts of a ring plane: its 324 voxels (5184 B)
+// padded to 5376 B.  A 16-byte LDS read whose 16-lane groups each read 256
+// contiguous bytes runs without bank conflicts on gfx950 only when the
+// groups' start addresses differ by multiples of 256 B (measured: any other
+// offset costs a two-way conflict), and a fragment read's lane groups
+// differ by the part stride.
+constexpr int ZPS = ZRV * 8 + 96;
+// Ring load item it -> (halo voxel hv, 8-channel part p) of a plane with P8
+// parts: each run of 16 consecutive items (lanes) takes 16 consecutive
+// voxels of one part, so that its 16-byte LDS stores cover 256 contiguous
+// bytes (alternating parts put two 128-byte runs on the same banks).  Items
+// with hv >= ZRV (the padding of the last run) do nothing.
+constexpr int ZRV16 = (ZRV + 15) / 16 * 16;
+template <int P8>
+__device__ inline void zm_item(int it, int& hv, int& p) {
+  const int grp = it >> 4;
+  p = grp % P8;
+  hv = (grp / P8) * 16 + (it & 15);
+}
 
 __device__ inline int zm_tap0(int s) {
   if (s < 9) return (s % 3) + 3 * (s / 3);              // dz 0
@@ -69,7 +88,7 @@ __device__ inline void zm_load_group(int gi, const __bf16* sm, const __bf16* s0,
   const int q = gi / 5, k = gi % 5;
   const __bf16* base = k < 3 ? (g < 2 ? sm : s0) : sp;
   const int xo = k < 3 ? k : (k == 3 ? (g < 2 ? 0 : 1) : 2);
-  base += (int64_t)(2 * q + (g & 1)) * ZRV * 8;
+  base += (int64_t)(2 * q + (g & 1)) * ZPS;
 #pragma unroll
   for (int r = 0; r < 6; ++r)
     f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
@@ -124,12 +143,12 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
   constexpr int NCH = CIN / 16;          // 16-channel chunks
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
-  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
+  constexpr int ITEMS = ZRV16 * P8;        // uint4 items per ring plane
   constexpr bool SPLIT = zm_split<CIN, COUT, EPI>();
   constexpr int BLOCK = zm_block<CIN, COUT, EPI>();
   constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
   constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
-  constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
+  constexpr int SLOT = NCH * 2 * ZPS;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
@@ -215,7 +234,7 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
     }
 
   // Load items of this thread: item it = threadIdx.x + k * BLOCK holds 8
-  // channels (part p) of halo voxel hv.  Its byte offset within one plane of
+  // channels (part p) of halo voxel hv (zm_item).  Its byte offset within one plane of
   // its source is fixed for the block; only the (uniform) plane offset moves
   // with z.  src: 0 none (outside the volume or channel padding), 1 a, 2 b.
   uint32_t ioff[PF];
@@ -223,12 +242,13 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * BLOCK;
-    const int hv = it / P8, p = it - hv * P8;
+    int hv, p;
+    zm_item<P8>(it, hv, p);
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
     ioff[k] = 0u;
     isrc[k] = 0;
-    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+    if (it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
       if (c < src.ca) {
         const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
         ioff[k] = (uint32_t)((v * src.ca + c) * 2);
@@ -274,10 +294,11 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * BLOCK;
-      if (it < ITEMS) {
-        const int hv = it / P8, p = it - hv * P8;
+      int hv, p;
+      zm_item<P8>(it, hv, p);
+      if (it < ITEMS && hv < ZRV) {
         const uint4 v = isrc[k] ? pf[k] : zero;
-        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
@@ -519,12 +540,12 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
   constexpr int NCH = CIN / 16;          // 16-channel chunks
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
-  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
+  constexpr int ITEMS = ZRV16 * P8;        // uint4 items per ring plane
   constexpr bool SPLIT = zm_pa_split<CIN, COUT, EPI>();
   constexpr int BLOCK = zm_pa_block<CIN, COUT, EPI>();
   constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
   constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
-  constexpr int SLOT = NCH * ZRV * 16;   // bf16 per ring slot
+  constexpr int SLOT = NCH * 2 * ZPS;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
@@ -609,12 +630,13 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * BLOCK;
-    const int hv = it / P8, p = it - hv * P8;
+    int hv, p;
+    zm_item<P8>(it, hv, p);
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
     ioff[k] = 0u;
     isrc[k] = 0;
-    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+    if (it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
       if (c < src.ca) {
         const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
         ioff[k] = (uint32_t)((v * src.ca + c) * 2);
@@ -654,10 +676,11 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * BLOCK;
-      if (it < ITEMS) {
-        const int hv = it / P8, p = it - hv * P8;
+      int hv, p;
+      zm_item<P8>(it, hv, p);
+      if (it < ITEMS && hv < ZRV) {
         const uint4 v = isrc[k] ? pf[k] : zero;
-        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
@@ -941,9 +964,9 @@ __global__ void __launch_bounds__(CAT_BLOCK)
                const uint8_t* __restrict__ act) {
   if (flags && flags[F_DONE]) return;
   constexpr int P8 = 2;                  // 8-channel parts per skip voxel
-  constexpr int ITEMS = ZRV * P8;
+  constexpr int ITEMS = ZRV16 * P8;
   constexpr int PF = (ITEMS + CAT_BLOCK - 1) / CAT_BLOCK;
-  constexpr int SLOT = ZRV * 16;
+  constexpr int SLOT = 2 * ZPS;
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
   // the coarse half's partial sums of the last two planes, [voxel y*16+x][16]
@@ -1010,9 +1033,10 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * CAT_BLOCK;
-    const int hv = it / P8, p = it - hv * P8;
+    int hv, p;
+    zm_item<P8>(it, hv, p);
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
-    iok[k] = it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+    iok[k] = it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
     ioff[k] = iok[k] ? (uint32_t)((((int64_t)gx + (int64_t)n * gy) * 16 + p * 8) * 2) : 0u;
   }
   const int64_t splane = (int64_t)n * n * 16 * 2;
@@ -1033,15 +1057,16 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * CAT_BLOCK;
-      if (it < ITEMS) {
-        const int hv = it / P8, p = it - hv * P8;
+      int hv, p;
+      zm_item<P8>(it, hv, p);
+      if (it < ITEMS && hv < ZRV) {
         // component selects (a select of whole vectors went through scratch)
         uint4 v = pf[k];
         v.x = iok[k] ? v.x : 0u;
         v.y = iok[k] ? v.y : 0u;
         v.z = iok[k] ? v.z : 0u;
         v.w = iok[k] ? v.w : 0u;
-        *reinterpret_cast<uint4*>(slot + (p * ZRV + hv) * 8) = v;
+        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
