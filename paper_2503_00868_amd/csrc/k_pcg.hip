@@ -109,9 +109,22 @@ __global__ void __launch_bounds__(kBlock)
                        mode == FIN_FCG_RR || mode == FIN_DCG_UPD;
   // the check also runs after an early stop (F_DONE = 3), which it decides
   if (in_loop && flags[F_DONE] && !(mode == FIN_CHECK && flags[F_DONE] == 3)) return;
+  // four blocks' partials per thread and pass, loaded before they are added
+  // (a dependent load per block made the larger reductions latency-bound)
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += kBlock)
-    for (int q = 0; q < nv; ++q) v[q] += partials[(int64_t)b * nv + q];
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kBlock) {
+    double t[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kBlock;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[u][q] = b < nblocks && q < nv ? partials[(int64_t)b * nv + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] += t[u][q];
+  }
   block_sum<4>(v);
   if (threadIdx.x != 0) return;
   switch (mode) {
