@@ -41,25 +41,20 @@ constexpr int ZRV = ZR * ZR;        // 324 voxels per ring plane
 constexpr int ZSTEPS = 15;          // K-steps per 16-channel chunk
 constexpr int ZTAPS = 28;           // packed taps per weight row (27 + zero)
 constexpr int ZMAXC = 128;          // planes per block at most
-// bf16 between the 8-channel parts of a ring plane: its 324 voxels (5184 B)
-// padded to 5376 B.  A 16-byte LDS read whose 16-lane groups each read 256
-// contiguous bytes runs without bank conflicts on gfx950 only when the
-// groups' start addresses differ by multiples of 256 B (measured: any other
-// offset costs a two-way conflict), and a fragment read's lane groups
-// differ by the part stride.
-constexpr int ZPS = ZRV * 8 + 96;
-// Ring load item it -> (halo voxel hv, 8-channel part p) of a plane with P8
-// parts: each run of 16 consecutive items (lanes) takes 16 consecutive
-// voxels of one part, so that its 16-byte LDS stores cover 256 contiguous
-// bytes (alternating parts put two 128-byte runs on the same banks).  Items
-// with hv >= ZRV (the padding of the last run) do nothing.
-constexpr int ZRV16 = (ZRV + 15) / 16 * 16;
-template <int P8>
-__device__ inline void zm_item(int it, int& hv, int& p) {
-  const int grp = it >> 4;
-  p = grp % P8;
-  hv = (grp / P8) * 16 + (it & 15);
-}
+// bf16 between the 8-channel parts of a ring plane.  A 16-byte LDS read
+// whose 16-lane groups each read 256 contiguous bytes runs without bank
+// conflicts on gfx950 only when the groups' start addresses differ by
+// multiples of 256 B (measured: any other offset costs a two-way conflict),
+// and a fragment read's lane groups differ by the part stride: the plane's
+// 324 voxels (5184 B) padded to 5376 B.  The 16-channel kernels keep the
+// tight stride: the padding's 1.5 KB would cost c10 its third block per CU.
+// (The offsets are written as voxels times 8, the form the tight stride's
+// register allocation was tuned in: c10 stays at 168 VGPRs, three waves per
+// SIMD.)
+constexpr int ZPS_PAD = ZRV * 8 + 96;
+constexpr int ZPS_TIGHT = ZRV * 8;
+template <int NCH>
+constexpr int zm_ps() { return NCH >= 2 ? ZPS_PAD : ZPS_TIGHT; }
 
 __device__ inline int zm_tap0(int s) {
   if (s < 9) return (s % 3) + 3 * (s / 3);              // dz 0
@@ -83,12 +78,13 @@ __device__ inline int zm_group_step(int k, int dy) {
 // The 6 halo rows (4 output rows + 2) of group gi = 5 q + k for this lane:
 // 8 channels (half g & 1 of chunk q) at column col + the group's x offset,
 // from the ring slots of planes z-1 (sm), z (s0) and z+1 (sp).
+template <int PS>
 __device__ inline void zm_load_group(int gi, const __bf16* sm, const __bf16* s0, const __bf16* sp,
                                      int wv, int g, int col, bf16x8z (&f)[6]) {
   const int q = gi / 5, k = gi % 5;
   const __bf16* base = k < 3 ? (g < 2 ? sm : s0) : sp;
   const int xo = k < 3 ? k : (k == 3 ? (g < 2 ? 0 : 1) : 2);
-  base += (int64_t)(2 * q + (g & 1)) * ZPS;
+  base += (int64_t)(2 * q + (g & 1)) * (PS / 8) * 8;
 #pragma unroll
   for (int r = 0; r < 6; ++r)
     f[r] = *reinterpret_cast<const bf16x8z*>(base + ((4 * wv + r) * ZR + col + xo) * 8);
@@ -143,12 +139,13 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
   constexpr int NCH = CIN / 16;          // 16-channel chunks
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
-  constexpr int ITEMS = ZRV16 * P8;        // uint4 items per ring plane
+  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
   constexpr bool SPLIT = zm_split<CIN, COUT, EPI>();
   constexpr int BLOCK = zm_block<CIN, COUT, EPI>();
   constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
   constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
-  constexpr int SLOT = NCH * 2 * ZPS;   // bf16 per ring slot
+  constexpr int PS = zm_ps<NCH>();    // bf16 per 8-channel part
+  constexpr int SLOT = NCH * 2 * PS;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
@@ -234,7 +231,7 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
     }
 
   // Load items of this thread: item it = threadIdx.x + k * BLOCK holds 8
-  // channels (part p) of halo voxel hv (zm_item).  Its byte offset within one plane of
+  // channels (part p) of halo voxel hv.  Its byte offset within one plane of
   // its source is fixed for the block; only the (uniform) plane offset moves
   // with z.  src: 0 none (outside the volume or channel padding), 1 a, 2 b.
   uint32_t ioff[PF];
@@ -242,13 +239,12 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * BLOCK;
-    int hv, p;
-    zm_item<P8>(it, hv, p);
+    const int hv = it / P8, p = it - hv * P8;
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
     ioff[k] = 0u;
     isrc[k] = 0;
-    if (it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
       if (c < src.ca) {
         const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
         ioff[k] = (uint32_t)((v * src.ca + c) * 2);
@@ -294,11 +290,10 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * BLOCK;
-      int hv, p;
-      zm_item<P8>(it, hv, p);
-      if (it < ITEMS && hv < ZRV) {
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
         const uint4 v = isrc[k] ? pf[k] : zero;
-        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
+        *reinterpret_cast<uint4*>(slot + (p * (PS / 8) + hv) * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
@@ -379,12 +374,12 @@ __global__ void __launch_bounds__((zm_block<CIN, COUT, EPI>()))
       // the 5 step groups of each chunk in turn, the fragments of group gi + 1
       // read from LDS before the MFMAs of group gi are issued
       bf16x8z fa[6], fb[6];
-      zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+      zm_load_group<PS>(0, sm, s0, sp, wv, g, col, fa);
       __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
       for (int gi = 0; gi < 5 * NCH; ++gi) {
         bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
-        if (gi + 1 < 5 * NCH) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+        if (gi + 1 < 5 * NCH) zm_load_group<PS>(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
         const int q = gi / 5, k = gi % 5;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
@@ -540,12 +535,13 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
   constexpr int NCH = CIN / 16;          // 16-channel chunks
   constexpr int NT = COUT / 16;          // 16-channel output groups
   constexpr int P8 = CIN / 8;            // 8-channel parts per voxel
-  constexpr int ITEMS = ZRV16 * P8;        // uint4 items per ring plane
+  constexpr int ITEMS = ZRV * P8;        // uint4 items per ring plane
   constexpr bool SPLIT = zm_pa_split<CIN, COUT, EPI>();
   constexpr int BLOCK = zm_pa_block<CIN, COUT, EPI>();
   constexpr int NTW = SPLIT ? 1 : NT;    // output groups per wave
   constexpr int PF = (ITEMS + BLOCK - 1) / BLOCK;
-  constexpr int SLOT = NCH * 2 * ZPS;   // bf16 per ring slot
+  constexpr int PS = zm_ps<NCH>();    // bf16 per 8-channel part
+  constexpr int SLOT = NCH * 2 * PS;   // bf16 per ring slot
   // four slots: the store of plane z+1 (slot (z+1) % 4, last read by the
   // compute of plane z-2) needs no barrier of its own
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
@@ -630,13 +626,12 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * BLOCK;
-    int hv, p;
-    zm_item<P8>(it, hv, p);
+    const int hv = it / P8, p = it - hv * P8;
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
     const int c = p * 8;
     ioff[k] = 0u;
     isrc[k] = 0;
-    if (it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
+    if (it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n) {
       if (c < src.ca) {
         const int64_t v = src.up ? (int64_t)(gx >> 1) + (int64_t)nc * (gy >> 1) : (int64_t)gx + (int64_t)n * gy;
         ioff[k] = (uint32_t)((v * src.ca + c) * 2);
@@ -676,11 +671,10 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * BLOCK;
-      int hv, p;
-      zm_item<P8>(it, hv, p);
-      if (it < ITEMS && hv < ZRV) {
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
         const uint4 v = isrc[k] ? pf[k] : zero;
-        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
+        *reinterpret_cast<uint4*>(slot + (p * (PS / 8) + hv) * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
@@ -759,14 +753,14 @@ __global__ void __launch_bounds__((zm_pa_block<CIN, COUT, EPI>()))
     if (work) {
       // as in k_conv_zm: group gi + 1's fragments are read before group gi's MFMAs
       bf16x8z fa[6], fb[6];
-      zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+      zm_load_group<PS>(0, sm, s0, sp, wv, g, col, fa);
       // (not for the 16-channel pool layer: at its three waves per SIMD the
       // deeper pipeline spills, and the compiler's own order measured faster)
       if (!(NCH == 1 && EPI == NET_EPI_RELU_POOL)) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
       for (int gi = 0; gi < 5 * NCH; ++gi) {
         bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
-        if (gi + 1 < 5 * NCH) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+        if (gi + 1 < 5 * NCH) zm_load_group<PS>(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
         const int q = gi / 5, k = gi % 5;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
@@ -964,9 +958,10 @@ __global__ void __launch_bounds__(CAT_BLOCK)
                const uint8_t* __restrict__ act) {
   if (flags && flags[F_DONE]) return;
   constexpr int P8 = 2;                  // 8-channel parts per skip voxel
-  constexpr int ITEMS = ZRV16 * P8;
+  constexpr int ITEMS = ZRV * P8;
   constexpr int PF = (ITEMS + CAT_BLOCK - 1) / CAT_BLOCK;
-  constexpr int SLOT = 2 * ZPS;
+  constexpr int PS = ZPS_PAD;  // c9 runs one block per CU either way
+  constexpr int SLOT = 2 * PS;
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
   // the coarse half's partial sums of the last two planes, [voxel y*16+x][16]
@@ -1033,10 +1028,9 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     const int it = threadIdx.x + k * CAT_BLOCK;
-    int hv, p;
-    zm_item<P8>(it, hv, p);
+    const int hv = it / P8, p = it - hv * P8;
     const int gx = x0 - 1 + hv % ZR, gy = y0 - 1 + hv / ZR;
-    iok[k] = it < ITEMS && hv < ZRV && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
+    iok[k] = it < ITEMS && (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n;
     ioff[k] = iok[k] ? (uint32_t)((((int64_t)gx + (int64_t)n * gy) * 16 + p * 8) * 2) : 0u;
   }
   const int64_t splane = (int64_t)n * n * 16 * 2;
@@ -1057,16 +1051,15 @@ __global__ void __launch_bounds__(CAT_BLOCK)
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int it = threadIdx.x + k * CAT_BLOCK;
-      int hv, p;
-      zm_item<P8>(it, hv, p);
-      if (it < ITEMS && hv < ZRV) {
+      if (it < ITEMS) {
+        const int hv = it / P8, p = it - hv * P8;
         // component selects (a select of whole vectors went through scratch)
         uint4 v = pf[k];
         v.x = iok[k] ? v.x : 0u;
         v.y = iok[k] ? v.y : 0u;
         v.z = iok[k] ? v.z : 0u;
         v.w = iok[k] ? v.w : 0u;
-        *reinterpret_cast<uint4*>(slot + p * ZPS + hv * 8) = v;
+        *reinterpret_cast<uint4*>(slot + (p * (PS / 8) + hv) * 8) = v;
         any |= v.x | v.y | v.z | v.w;
       }
     }
@@ -1172,11 +1165,11 @@ __global__ void __launch_bounds__(CAT_BLOCK)
       const __bf16* sp = ring + ((z + 1) & 3) * SLOT;
       if (work) {
         bf16x8z fa[6], fb[6];
-        zm_load_group(0, sm, s0, sp, wv, g, col, fa);
+        zm_load_group<PS>(0, sm, s0, sp, wv, g, col, fa);
 #pragma unroll
         for (int gi = 0; gi < 5; ++gi) {
           bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
-          if (gi + 1 < 5) zm_load_group(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+          if (gi + 1 < 5) zm_load_group<PS>(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
 #pragma unroll
           for (int dy = 0; dy < 3; ++dy) {
             const int st = zm_group_step(gi, dy);
