@@ -46,6 +46,8 @@ BYTES_PER_UNIT = {
     # Jacobi PCG and the flexible CG update the FP64 iterate every fourth
     # iteration: three of four iterations move r 4+4, q 4, diag 1 (13 B), the
     # fourth also x 8+8 and four directions 4x4 (45 B); the average is 21 B.
+    # The flexible CG's fourth iteration ends a block, whose FP64 check
+    # recomputes r, so it moves x and the directions alone (32 B): 17.75 B.
     # (MIC(0)-PCG updates x every iteration: 33 B.)
     "pcg_update": 21.0,
     "pcg_check": 17.0,      # x 8, b 4, diag 1 in; r 4 out
@@ -273,6 +275,8 @@ def rooflines(prof, n, precond, n_active):
             per_unit = BYTES_PER_UNIT[kind]
             if kind == "pcg_update" and precond == "mic0":
                 per_unit = 33.0
+            if kind == "pcg_update" and precond == "learned":
+                per_unit = 17.75
             if kind == "pcg_dir_spmv" and precond == "learned":
                 per_unit = 21.0  # z 4 + d 4 + r 4 (the flexible-CG dot) + diag 1 in; d 4 + q 4 out
             per_launch = per_unit * C
@@ -691,7 +695,8 @@ TRAFFIC_KINDS = {
     # kind: (precond the run used, kernel name patterns, sources)
     "pcg_dir_spmv": {"jacobi": ["k_dir_spmv_zm<0, false>"], "learned": ["k_dir_spmv_zm<1, true>"]},
     "pcg_update": {"jacobi": ["k_update4<4, true, false>", "k_update4<4, false, false>"],
-                   "learned": ["k_update4<4, true, true>", "k_update4<4, false, true>"]},
+                   "learned": ["k_update4<4, true, true>", "k_update4<4, true, true, false>",
+                               "k_update4<4, false, true>"]},
     "pcg_check": {"jacobi": ["k_check_zm<0>"], "learned": ["k_check_zm<1>"]},
     "dcg_dir_spmv": {"learned": ["k_dcg_dir_spmv_zm"]},
     "dcg_update": {"learned": ["k_dcg_update"]},
@@ -845,6 +850,8 @@ def summarize_traffic(run_csv, copy_csv, precond, n, commands, out_dir, copy_mib
             per_unit = BYTES_PER_UNIT[kind]
             if kind == "pcg_dir_spmv" and precond == "learned":
                 per_unit = 21.0
+            if kind == "pcg_update" and precond == "learned":
+                per_unit = 17.75
             alg = per_unit * C
         elif kind in FACE_BYTES:
             if n_active is None:

@@ -193,7 +193,9 @@ void launch_pcg_update2(sim_ctx* c, const float* d, const float* d_prev, bool wi
 void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase);
 // the same four-step iterate update for the flexible CG (alpha = d.r / d.q)
 // also reduces |r|^2 into S_NET_SUMSQ (the learned preconditioner's input scale)
-void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol);
+// check_follows: the FP64 check runs next (phase 3 then updates x alone)
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol,
+                        bool check_follows);
 void launch_pcg_rz(sim_ctx* c);  // r.z with z from an explicit preconditioner, and beta
 void launch_pcg_rz_first(sim_ctx* c, int first);
 void launch_pcg_check(sim_ctx* c, int prec, double tol);

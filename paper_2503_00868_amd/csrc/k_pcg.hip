@@ -766,7 +766,9 @@ __global__ void __launch_bounds__(kBlock)
 // x += a0 d0 + a1 d1 + a2 d2 + a3 d3 in FP64 (one read-modify-write of x per
 // four iterations).
 // FLEX: the flexible CG's step alpha = d.r / d.q, and no r.z partials.
-template <int V, bool WITH_X, bool FLEX>
+// KEEP_R false: the iterate update alone (an FP64 check that replaces r by
+// the true residual follows at once), no r update and no reduction.
+template <int V, bool WITH_X, bool FLEX, bool KEEP_R = true>
 __global__ void __launch_bounds__(kBlock)
     k_update4(int n, const uint8_t* __restrict__ cdiag, double* __restrict__ x,
               float* __restrict__ r, const float* __restrict__ d0, const float* __restrict__ d1,
@@ -791,14 +793,17 @@ __global__ void __launch_bounds__(kBlock)
     a1 = scal[S_ALPHA_Q1];
     a2 = scal[S_ALPHA_Q2];
   }
+  static_assert(KEEP_R || WITH_X, "an update without r needs the iterate");
   double v[1] = {0.0};
   for (int64_t g = run.begin + threadIdx.x; g < run.end; g += kBlock) {
     const int64_t idx = g * V;
     float qv[V], rv[V];
     uint8_t dg[V];
-    ldf<V>(q + idx, qv);
-    ldf<V>(r + idx, rv);
-    ldg<V>(cdiag + idx, dg);
+    if (KEEP_R) {
+      ldf<V>(q + idx, qv);
+      ldf<V>(r + idx, rv);
+      ldg<V>(cdiag + idx, dg);
+    }
     if (WITH_X) {
       double xv[V];
       float e0[V], e1[V], e2[V], e3[V];
@@ -815,16 +820,18 @@ __global__ void __launch_bounds__(kBlock)
                  ((a2 != 0.0 ? a2 * (double)e2[e] : 0.0) + (alpha != 0.0 ? alpha * (double)e3[e] : 0.0));
       std_<V>(x + idx, xv);
     }
+    if (KEEP_R) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      rv[e] -= alpha_f * qv[e];
-      // Jacobi: r.M^-1 r; flexible CG: |r|^2, the learned preconditioner's
-      // input scale (it would otherwise read r once more for it)
-      v[0] += FLEX ? (double)rv[e] * (double)rv[e] : (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+      for (int e = 0; e < V; ++e) {
+        rv[e] -= alpha_f * qv[e];
+        // Jacobi: r.M^-1 r; flexible CG: |r|^2, the learned preconditioner's
+        // input scale (it would otherwise read r once more for it)
+        v[0] += FLEX ? (double)rv[e] * (double)rv[e] : (double)rv[e] * (double)rv[e] * c_inv_count[dg[e]];
+      }
+      stf<V>(r + idx, rv);
     }
-    stf<V>(r + idx, rv);
   }
-  store_partials<1>(v, partials, lb);
+  if (KEEP_R) store_partials<1>(v, partials, lb);
   if (!WITH_X && blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA_Q0 + phase] = alpha;
 }
 
@@ -1132,14 +1139,21 @@ void launch_pcg_update4(sim_ctx* c, const float* const dirs[4], int phase) {
   launch_finalize(c, c->grid_cells, 1, FIN_RZ_UPD, 0.0, 1, 0, 0.0, 0);
 }
 
-void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol) {
+void launch_fcg_update4(sim_ctx* c, const float* const dirs[4], int phase, double tol,
+                        bool check_follows) {
   prof_mark(c, SIM_KERN_PCG_UPDATE, true);
-  if (phase == 3)
+  // before the FP64 check (which recomputes r from x and reduces its |r|^2)
+  // only the iterate is updated
+  const bool x_only = phase == 3 && check_follows;
+  if (x_only)
+    FS_CELL_LAUNCH(k_update4, true, true, false);
+  else if (phase == 3)
     FS_CELL_LAUNCH(k_update4, true, true);
   else
     FS_CELL_LAUNCH(k_update4, false, true);
   prof_mark(c, SIM_KERN_PCG_UPDATE, false);
 #undef ARGS
+  if (x_only) return;
   // |r|^2 of the updated residual, for the learned preconditioner's input;
   // inside a block it also ends the block early once it meets the tolerance
   // (the FP64 check at the block's end decides; a stop it refuses restarts

@@ -478,7 +478,7 @@ int fcg_solve(sim_ctx* c, const double* x0, sim_stats* st) {
       const float* dirs[4] = {dbuf[(ph + 2) & 3], dbuf[(ph + 3) & 3], dbuf[ph], dbuf[(ph + 1) & 3]};
       // the update ends the block early when the recursive residual meets the
       // tolerance; the FP64 check runs at block ends only, where x is up to date
-      launch_fcg_update4(c, dirs, ph, tol);
+      launch_fcg_update4(c, dirs, ph, tol, t == todo - 1);
       if (t == todo - 1) launch_fcg_check(c, tol);
       // |r|^2 for the network: reduced by the update, or by the check when it
       // has just replaced r by the true residual; z.q for beta: reduced by
