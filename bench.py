@@ -694,9 +694,9 @@ def _rel(a, b):
 TRAFFIC_KINDS = {
     # kind: (precond the run used, kernel name patterns, sources)
     "pcg_dir_spmv": {"jacobi": ["k_dir_spmv_zm<0, false>"], "learned": ["k_dir_spmv_zm<1, true>"]},
-    "pcg_update": {"jacobi": ["k_update4<4, true, false>", "k_update4<4, false, false>"],
-                   "learned": ["k_update4<4, true, true>", "k_update4<4, true, true, false>",
-                               "k_update4<4, false, true>"]},
+    # (prefixes: the names carry the update's last template argument too)
+    "pcg_update": {"jacobi": ["k_update4<4, true, false", "k_update4<4, false, false"],
+                   "learned": ["k_update4<4, true, true", "k_update4<4, false, true"]},
     "pcg_check": {"jacobi": ["k_check_zm<0>"], "learned": ["k_check_zm<1>"]},
     "dcg_dir_spmv": {"learned": ["k_dcg_dir_spmv_zm"]},
     "dcg_update": {"learned": ["k_dcg_update"]},
