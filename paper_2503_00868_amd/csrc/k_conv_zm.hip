@@ -964,8 +964,10 @@ __global__ void __launch_bounds__(CAT_BLOCK)
   constexpr int SLOT = 2 * PS;
   __shared__ __attribute__((aligned(16))) __bf16 ring[4 * SLOT];
   __shared__ __attribute__((aligned(16))) __bf16 kring[3 * CAT_KSLOT];
-  // the coarse half's partial sums of the last two planes, [voxel y*16+x][16]
+  // the coarse half's partial sums of the last two planes, [voxel y*16+x][16],
+  // and the skip half's last K-step group, which the coarse waves compute
   __shared__ __attribute__((aligned(16))) float stage[2][ZT * ZT * 16];
+  __shared__ __attribute__((aligned(16))) float stage2[2][ZT * ZT * 16];
   __shared__ __attribute__((aligned(16))) int votes[4][8];
   __shared__ uint8_t live_s[ZMAXC + 3];
 
@@ -1020,6 +1022,18 @@ __global__ void __launch_bounds__(CAT_BLOCK)
     const __bf16* src = coarse_role ? weff + (((int64_t)(p * 8 + (j & 7)) * 16 + col) * 32 + 8 * g)
                                     : wskip + ((int64_t)col * ZTAPS + stap) * 16 + (g & 1) * 8;
     wr[j] = *reinterpret_cast<const bf16x8z*>(src);
+  }
+  // the skip half's last group (steps 12-14: dz 2 with dx 2 | the zero tap)
+  // runs on the coarse waves, which have 32 MFMAs per plane against the
+  // skip waves' 60: 48 and 44 after the move
+  constexpr int CAT_SKIP_GROUPS = 4;
+  bf16x8z wg4[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int st = zm_group_step(4, i);
+    const int stap = g < 2 ? zm_tap0(st) : zm_tap1(st);
+    wg4[i] = coarse_role ? *reinterpret_cast<const bf16x8z*>(wskip + ((int64_t)col * ZTAPS + stap) * 16 + (g & 1) * 8)
+                         : wr[0];
   }
 
   // skip plane loads: per-item offsets fixed for the block
@@ -1131,11 +1145,15 @@ __global__ void __launch_bounds__(CAT_BLOCK)
   auto finish = [&]() {
     // plane zprev, rows 4 wv + a, x = col: skip + coarse, ReLU, 4 bf16
     const float* st = stage[zprev & 1];
+    const float* st2 = stage2[zprev & 1];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int y = 4 * wv + a;
-      const float4 c4 = *reinterpret_cast<const float4*>(st + (y * ZT + col) * 16 + 4 * cat_chunk(g, col));
-      const float v[4] = {acc[a][0] + c4.x, acc[a][1] + c4.y, acc[a][2] + c4.z, acc[a][3] + c4.w};
+      const int so = (y * ZT + col) * 16 + 4 * cat_chunk(g, col);
+      const float4 c4 = *reinterpret_cast<const float4*>(st + so);
+      const float4 s4 = *reinterpret_cast<const float4*>(st2 + so);
+      const float v[4] = {acc[a][0] + (c4.x + s4.x), acc[a][1] + (c4.y + s4.y), acc[a][2] + (c4.z + s4.z),
+                          acc[a][3] + (c4.w + s4.w)};
       __bf16 h[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) h[i] = (__bf16)(v[i] > 0.f ? v[i] : 0.f);
@@ -1167,9 +1185,9 @@ __global__ void __launch_bounds__(CAT_BLOCK)
         bf16x8z fa[6], fb[6];
         zm_load_group<PS>(0, sm, s0, sp, wv, g, col, fa);
 #pragma unroll
-        for (int gi = 0; gi < 5; ++gi) {
+        for (int gi = 0; gi < CAT_SKIP_GROUPS; ++gi) {
           bf16x8z(&f)[6] = (gi & 1) ? fb : fa;
-          if (gi + 1 < 5) zm_load_group<PS>(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
+          if (gi + 1 < CAT_SKIP_GROUPS) zm_load_group<PS>(gi + 1, sm, s0, sp, wv, g, col, (gi & 1) ? fa : fb);
 #pragma unroll
           for (int dy = 0; dy < 3; ++dy) {
             const int st = zm_group_step(gi, dy);
@@ -1225,6 +1243,30 @@ __global__ void __launch_bounds__(CAT_BLOCK)
         const int y = 2 * (b + 4 * (col >> 3)) + cP, x = 2 * (col & 7) + cpx;
         *reinterpret_cast<float4*>(st + (y * ZT + x) * 16 + 4 * cat_chunk(g, x)) =
             make_float4(kacc[b][0], kacc[b][1], kacc[b][2], kacc[b][3]);
+      }
+      // the skip half's last group for the rows of skip wave wv (the same
+      // operands and layout as there), to the second stage
+      f32x4z sacc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) sacc[a] = f32x4z{0.f, 0.f, 0.f, 0.f};
+      if (work) {
+        const __bf16* sm = ring + ((z + 3) & 3) * SLOT;
+        const __bf16* s0 = ring + (z & 3) * SLOT;
+        const __bf16* sp = ring + ((z + 1) & 3) * SLOT;
+        bf16x8z f[6];
+        zm_load_group<PS>(4, sm, s0, sp, wv, g, col, f);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            sacc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg4[dy], f[a + dy], sacc[a], 0, 0, 0);
+      }
+      float* st2 = stage2[z & 1];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int y = 4 * wv + a;
+        *reinterpret_cast<float4*>(st2 + (y * ZT + col) * 16 + 4 * cat_chunk(g, col)) =
+            make_float4(sacc[a][0], sacc[a][1], sacc[a][2], sacc[a][3]);
       }
     }
   };
