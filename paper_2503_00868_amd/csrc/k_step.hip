@@ -241,8 +241,13 @@ void launch_diffuse_explicit(sim_ctx* c, CF3 in, F3 out, float alpha) {
 
 // b_c = -h * (net outward flux of liquid cell c); zero off liquid.
 __global__ void __launch_bounds__(kBlock)
-    k_divergence(int n, const uint8_t* __restrict__ cdiag, CF3 in, float* __restrict__ b) {
+    k_divergence(int n, const uint8_t* __restrict__ cdiag, const uint8_t* __restrict__ fcode,
+                 int64_t F, CF3 in, float* __restrict__ b) {
   const int64_t C = cells(n);
+  // non-active faces (solid walls, air-air) count as zero, whatever they hold
+  auto face = [&](int comp, int64_t i) -> float {
+    return (fcode[comp * F + i] & FC_ACTIVE) ? in.c[comp][i] : 0.f;
+  };
   const float h = 1.0f / (float)n;
   const Chunk ch = block_chunk(C, gridDim.x, xcd_logical_block(blockIdx.x, gridDim.x));
   Walker w;
@@ -253,8 +258,8 @@ __global__ void __launch_bounds__(kBlock)
       const int64_t iu = w.i + (int64_t)(n + 1) * (w.j + (int64_t)n * w.k);
       const int64_t iv = w.i + (int64_t)n * (w.j + (int64_t)(n + 1) * w.k);
       const int64_t iw = idx;
-      float flux = (in.c[0][iu + 1] - in.c[0][iu]) + (in.c[1][iv + n] - in.c[1][iv]) +
-                   (in.c[2][iw + (int64_t)n * n] - in.c[2][iw]);
+      float flux = (face(0, iu + 1) - face(0, iu)) + (face(1, iv + n) - face(1, iv)) +
+                   (face(2, iw + (int64_t)n * n) - face(2, iw));
       out = -h * flux;
     }
     b[idx] = out;
@@ -263,7 +268,7 @@ __global__ void __launch_bounds__(kBlock)
 
 void launch_divergence(sim_ctx* c, CF3 in, float* b) {
   hipLaunchKernelGGL(k_divergence, dim3(c->grid_cells), dim3(kBlock), 0, c->stream, c->n, c->cdiag,
-                     in, b);
+                     c->fcode, c->F, in, b);
 }
 
 // -------------------------------------------------- pressure-gradient update

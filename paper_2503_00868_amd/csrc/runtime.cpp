@@ -569,12 +569,12 @@ int diffuse_into(sim_ctx* c, F3 out, sim_stats* st) {
   return diffuse_implicit(c, out, st);
 }
 
-// Pressure projection of (u, v, w) in place; non-active faces are zeroed
-// first (the adjoint state can carry values there).  warm (nullable): the
-// solve starts from it and the new pressure is stored back into it.
+// Pressure projection of (u, v, w) in place; non-active faces (the adjoint
+// state can carry values there) count as zero in the divergence and are
+// zeroed by the pressure update.  warm (nullable): the solve starts from it
+// and the new pressure is stored back into it.
 int project_inplace(sim_ctx* c, F3 u, sim_stats* st, double* warm = nullptr) {
   CF3 cu = cf3(u.c[0], u.c[1], u.c[2]);
-  launch_mask_scale(c, cu, u, 1.0f);
   launch_divergence(c, cu, c->b);
   int rc = poisson_solve(c, warm, st);
   if (rc != SIM_OK && rc != SIM_OK_FALLBACK) return rc;
