@@ -435,25 +435,55 @@ void launch_loss_mse(sim_ctx* c, CF3 u, CF3 t, F3 g, int slot) {
 // departure point through the face velocity, itself a trilinear sample of
 // the three components at the face.  Both parts are scattered with FP32
 // atomics.  The body force is a constant and drops out.
-__device__ inline void scatter3(float* __restrict__ g, Dims d, int i, int j, int k, float rx,
-                                float ry, float rz, float s) {
+//
+// Consecutive lanes hold consecutive faces of a row, and their 2x2x2
+// targets usually sit side by side along x: when the next lane's base node
+// is this lane's base node + 1 in x (same y and z), this lane's +x column of
+// four targets is the next lane's own column, so the next lane adds the four
+// values into its atomics and this lane issues none for that column.  Both
+// lanes test the same shuffled integers, so they agree; a lane with nothing
+// to scatter passes an impossible base (on = false).  Every lane of the wave
+// must call this together.
+__device__ inline void scatter3_merged(float* __restrict__ g, Dims d, int i, int j, int k,
+                                       float rx, float ry, float rz, float s, bool on) {
   int i0, j0, k0;
   float fx, fy, fz;
   lattice_axis(i, rx, d.nx, i0, fx);
   lattice_axis(j, ry, d.ny, j0, fy);
   lattice_axis(k, rz, d.nz, k0, fz);
-  const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
-  float* p = g + i0 + sy * j0 + sz * k0;
+  const int key_i = on ? i0 : -1000;
+  const int key_jk = j0 | (k0 << 16);
   const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+  float v[2][2][2];  // [z][y][x]
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        float wgt = s * wx[a] * wy[b] * wz[c];
-        if (wgt != 0.f) atomicAdd(p + a + sy * b + sz * c, wgt);
-      }
+      for (int a = 0; a < 2; ++a) v[c][b][a] = on ? s * wx[a] * wy[b] * wz[c] : 0.f;
+  const int lane = threadIdx.x & 63;
+  const int prev_i = __shfl_up(key_i, 1);
+  const int prev_jk = __shfl_up(key_jk, 1);
+  const int next_i = __shfl_down(key_i, 1);
+  const int next_jk = __shfl_down(key_jk, 1);
+  float pv[2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) pv[c][b] = __shfl_up(v[c][b][1], 1);
+  const bool take = lane > 0 && on && prev_i + 1 == key_i && prev_jk == key_jk;
+  const bool give = lane < 63 && on && key_i + 1 == next_i && key_jk == next_jk;
+  if (!on) return;
+  const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
+  float* p = g + i0 + sy * j0 + sz * k0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const float w0 = take ? v[c][b][0] + pv[c][b] : v[c][b][0];
+      if (w0 != 0.f) atomicAdd(p + sy * b + sz * c, w0);
+      if (!give && v[c][b][1] != 0.f) atomicAdd(p + 1 + sy * b + sz * c, v[c][b][1]);
+    }
 }
 
 // Gradient of the trilinear sample with respect to the position (lattice
@@ -518,30 +548,46 @@ __global__ void __launch_bounds__(kBlock)
   double acc_dt = 0.0, acc_l = 0.0;
   Walker w;
   w.init(d, ch.begin + threadIdx.x, kBlock);
-  for (int64_t idx = ch.begin + threadIdx.x; idx < ch.end; idx += kBlock, w.next()) {
-    if (!(code[idx] & FC_ACTIVE)) continue;
-    const float l = lam.c[comp][idx];
-    if (l == 0.f) continue;
-    float U[3];
+  // the trip count is the same for the whole wave (lanes past the chunk's
+  // end take part with nothing to scatter), so the merged scatters' shuffles
+  // see every lane
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = ch.begin + threadIdx.x - lane; base < ch.end; base += kBlock, w.next()) {
+    const int64_t idx = base + lane;
+    bool on = idx < ch.end && (code[idx] & FC_ACTIVE);
+    const float l = on ? lam.c[comp][idx] : 0.f;
+    on = on && l != 0.f;
+    float U[3] = {0.f, 0.f, 0.f};
     float off[3][3];
+    float grad[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) off[a][ax] = a == comp ? 0.f : cross_offset(ax, comp, a);
-      U[a] = a == comp ? u.c[comp][idx]
-                       : sample3(u.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2]);
+    if (on) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        U[a] = a == comp ? u.c[comp][idx]
+                         : sample3(u.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2]);
     }
     const float rx = -dth * U[0], ry = -dth * U[1], rz = -dth * U[2];
-    float grad[3];
-    sample3_grad(u.c[comp], d, w.i, w.j, w.k, rx, ry, rz, grad);
-    acc_l += (double)l;
-    acc_dt -= (double)l * (double)(fn * (grad[0] * U[0] + grad[1] * U[1] + grad[2] * U[2]));
+    if (on) {
+      sample3_grad(u.c[comp], d, w.i, w.j, w.k, rx, ry, rz, grad);
+      acc_l += (double)l;
+      acc_dt -= (double)l * (double)(fn * (grad[0] * U[0] + grad[1] * U[1] + grad[2] * U[2]));
+    }
     if (SCATTER) {
-      scatter3(g.c[comp], d, w.i, w.j, w.k, rx, ry, rz, l);
+      scatter3_merged(g.c[comp], d, w.i, w.j, w.k, rx, ry, rz, l, on);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const float s = l * (-dth) * grad[a];
-        if (s != 0.f) scatter3(g.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2], s);
+        if (a == comp) {
+          // zero offset: the face itself
+          if (on && s != 0.f) atomicAdd(g.c[comp] + idx, s);
+        } else {
+          scatter3_merged(g.c[a], dd[a], w.i, w.j, w.k, off[a][0], off[a][1], off[a][2], s,
+                          on && s != 0.f);
+        }
       }
     }
   }
