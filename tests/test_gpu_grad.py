@@ -114,11 +114,15 @@ def test_gradient_fd_sanity_on_gpu(torch_gpu, orc):
     assert abs(fd_s - th_s.grad.item()) <= 2e-2 * abs(fd_s), (fd_s, th_s.grad.item())
 
 
-def test_advect_adjoint_parity(torch_gpu, orc):
-    banner("advect adjoint 20^3")
+# (n, velocity scale): the benchmark's kind of flow on a small grid; a grid
+# whose rows are one wave long (y and z faces), where neighbouring lanes'
+# scatter targets line up and are merged; and departure points many cells
+# away, clamped at the walls, where many lanes share one base node.
+@pytest.mark.parametrize("n,scale", [(20, 4.0), (64, 4.0), (33, 60.0)])
+def test_advect_adjoint_parity(torch_gpu, orc, n, scale):
+    banner(f"advect adjoint {n}^3, velocity x{scale}")
     from paper_2503_00868_amd.fluidsim import Sim
-    n = 20
-    cell, u = case(n, 102, 4.0)
+    cell, u = case(n, 102, scale)
     u = orc.mask_faces(cell, u)
     rng = np.random.default_rng(3)
     lam = orc.mask_faces(cell, tuple(rng.standard_normal(orc.face_shape(n, c)) for c in range(3)))
