@@ -38,6 +38,10 @@ enum ScalarSlot {
   S_LSUM0,       //   sums over steps of the adjoint at the body force, per component
   S_LSUM1,       //   (active faces): dJ/dg_c = dt * S_LSUMc
   S_LSUM2,
+  S_GUESS0,      // scaled warm start: x.b, x.Ax (and two unused)
+  S_GUESS1,
+  S_GUESS2,
+  S_GUESS3,
   S_COUNT = 32
 };
 // F_DONE: 0 running, 1 converged, 2 breakdown, 3 (flexible and viscosity CG)
@@ -207,6 +211,7 @@ void launch_x_to_double(sim_ctx* c, const double* x, double* out, const int* fla
 // ahead, into o: order 2 (linear) o = 2 a - b; order 3 (quadratic)
 // o = 3 a - 3 b + o.
 void launch_x_extrapolate(sim_ctx* c, const double* a, const double* b, double* o, int order);
+void launch_guess_scale(sim_ctx* c, double* x);
 // out = (float)(xref - x) over the cells (FP64 difference)
 void launch_err_snapshot(sim_ctx* c, const double* xref, float* out);
 

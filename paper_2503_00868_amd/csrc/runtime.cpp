@@ -573,9 +573,14 @@ int diffuse_into(sim_ctx* c, F3 out, sim_stats* st) {
 // state can carry values there) count as zero in the divergence and are
 // zeroed by the pressure update.  warm (nullable): the solve starts from it
 // and the new pressure is stored back into it.
-int project_inplace(sim_ctx* c, F3 u, sim_stats* st, double* warm = nullptr) {
+// scale_warm: the start is first rescaled to the multiple of it closest to
+// the new solution in the A-norm (the adjoint solves, whose right-hand sides
+// change in size from step to step).
+int project_inplace(sim_ctx* c, F3 u, sim_stats* st, double* warm = nullptr,
+                    bool scale_warm = false) {
   CF3 cu = cf3(u.c[0], u.c[1], u.c[2]);
   launch_divergence(c, cu, c->b);
+  if (warm && scale_warm) launch_guess_scale(c, warm);
   int rc = poisson_solve(c, warm, st);
   if (rc != SIM_OK && rc != SIM_OK_FALLBACK) return rc;
   if (warm) launch_x_to_double(c, c->x, warm);
@@ -1004,7 +1009,7 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
       const int q = s - s0;
       F3 us = stacked(c, c->seg + (int64_t)q * F3n);
       F3 op = stacked(c, c->seg + (int64_t)(K + q) * F3n);
-      int rc = project_inplace(c, lam, &st, c->xwa);
+      int rc = project_inplace(c, lam, &st, c->xwa, true);
       worst = combine(worst, rc);
       if (rc < 0) return rc;
       if (explicit_d) {
