@@ -93,8 +93,9 @@ typedef struct {
                                   steps' pressures (the linear 2 p[s-1] - p[s-2] at the third
                                   step, p[s-1] at the second, 0 at the first), each adjoint
                                   solve of sim_backward from the previous
-                                  adjoint solve's, scaled by x.b / x.Ax (its multiple
-                                  closest to the new solution in the A-norm); the
+                                  adjoint solve's (with SIM_PRECOND_LEARNED scaled by
+                                  x.b / x.Ax, its multiple closest to the new solution
+                                  in the A-norm); the
                                   stopping test, relative to the
                                   right-hand side, is unchanged; 0: every solve starts at 0 */
     int32_t store_pressures;   /* 1 (needs max_steps > 0): a recorded rollout also keeps each

@@ -1009,7 +1009,9 @@ int sim_backward(sim_ctx* c, const float* gu, const float* gv, const float* gw, 
       const int q = s - s0;
       F3 us = stacked(c, c->seg + (int64_t)q * F3n);
       F3 op = stacked(c, c->seg + (int64_t)(K + q) * F3n);
-      int rc = project_inplace(c, lam, &st, c->xwa, true);
+      // the learned preconditioner's adjoint solves start from the previous
+      // adjoint pressure rescaled; Jacobi-PCG ran more iterations from it
+      int rc = project_inplace(c, lam, &st, c->xwa, c->desc.precond == SIM_PRECOND_LEARNED);
       worst = combine(worst, rc);
       if (rc < 0) return rc;
       if (explicit_d) {
